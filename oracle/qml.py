@@ -1,0 +1,181 @@
+"""Fisher matrix, QML quadratic forms, noise bias and deconvolved spectra.
+
+Oracle code: test infrastructure only (see oracle/__init__.py).
+
+Parameters are (spectrum XY, bin b) pairs, index s * n_b + b with s running over
+the requested spectra in TT, EE, BB, TE, TB, EB order.  The bin derivative is
+P_b = sum_{l in b} dC/dC^XY_l, so W_l enters once (reading of the binning of
+Sect. 2.4; pinned by the binning identity F_binned = P F P^T).
+
+Two routes:
+* ``*_dense``: the definitions in pixel space, Eqs. fisher, P_ell, q_ell,
+  noise_bias (derivative matrices built with the pair route);
+* ``*_harmonic``: Z = Y^T C^-1 Y (Eq. projected_inv, computed directly) with the
+  COO trace of Eq. sparse_trace, w = Y^T C^-1 d (Eq. weighted_data) and
+  Eq. q_harmonic; the noise bias as 1/2 tr[E_b (Z - Z Lambda Z)], which equals
+  Eq. noise_bias because Y^T C^-1 N C^-1 Y = Z - Z Lambda Z when the signal band
+  is the analysis window.
+"""
+import numpy as np
+import scipy.linalg as sla
+
+from . import covariance as cv
+from . import healpix
+
+SPECS = cv.SPECS
+_PAIRS = {"TT": (("T", "T"),), "EE": (("E", "E"),), "BB": (("B", "B"),),
+          "TE": (("T", "E"), ("E", "T")), "TB": (("T", "B"), ("B", "T")),
+          "EB": (("E", "B"), ("B", "E"))}
+
+
+def parameters(spectra, lo, hi):
+    """[(spec, l_lo, l_hi)] in Fisher index order s * n_b + b."""
+    order = [s for s in SPECS if s in spectra]
+    return [(s, int(a), int(b)) for s in order for a, b in zip(lo, hi)]
+
+
+def _directions(problem):
+    return healpix.active_directions(problem.nside, problem.mask, problem.theta, problem.phi)
+
+
+def derivative_dense(problem, spec, l_lo, l_hi):
+    """P_b = sum_{l in [l_lo, l_hi]} dC/dC^spec_l (Eq. P_ell and its spin-2 extension)."""
+    th, ph = _directions(problem)
+    unit = np.zeros((6, problem.lmax + 1))
+    unit[SPECS.index(spec), l_lo:l_hi + 1] = 1.0
+    return cv.signal_pairs(th, ph, problem.fields, unit, problem.bl, problem.pl,
+                           problem.lmin, problem.lmax)
+
+
+def fisher_dense(problem, spectra, lo, hi, C=None):
+    """F_AB = 1/2 tr[C^-1 P_A C^-1 P_B] (Eq. fisher)."""
+    if C is None:
+        C = cv.total_covariance(problem)
+    fac = sla.cho_factor(C, lower=True)
+    pars = parameters(spectra, lo, hi)
+    CiP = [sla.cho_solve(fac, derivative_dense(problem, *p)) for p in pars]
+    k = len(pars)
+    F = np.zeros((k, k))
+    for a in range(k):
+        for b in range(k):
+            F[a, b] = 0.5 * np.sum(CiP[a] * CiP[b].T)     # tr[A B] = sum A * B^T
+    return F
+
+
+def quadratic_dense(problem, spectra, lo, hi, maps, C=None):
+    """y_A = 1/2 d^T C^-1 P_A C^-1 d (the data term of Eq. q_ell) for each map; [nmaps][k]."""
+    if C is None:
+        C = cv.total_covariance(problem)
+    fac = sla.cho_factor(C, lower=True)
+    x = sla.cho_solve(fac, np.atleast_2d(maps).T)          # C^-1 d, [n][nmaps]
+    pars = parameters(spectra, lo, hi)
+    y = np.zeros((x.shape[1], len(pars)))
+    for a, p in enumerate(pars):
+        P = derivative_dense(problem, *p)
+        y[:, a] = 0.5 * np.sum(x * (P @ x), axis=0)
+    return y
+
+
+def bias_dense(problem, spectra, lo, hi, C=None):
+    """b_A = 1/2 tr[C^-1 P_A C^-1 N] (Eq. noise_bias)."""
+    if C is None:
+        C = cv.total_covariance(problem)
+    fac = sla.cho_factor(C, lower=True)
+    CiN = sla.cho_solve(fac, problem.noise_matrix())
+    pars = parameters(spectra, lo, hi)
+    out = np.zeros(len(pars))
+    for a, p in enumerate(pars):
+        CiP = sla.cho_solve(fac, derivative_dense(problem, *p))
+        out[a] = 0.5 * np.sum(CiP * CiN.T)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# harmonic (Z) route
+# ---------------------------------------------------------------------------
+def coo_derivatives(problem, modes, spectra, lo, hi):
+    """E_A as COO triplets (r, c, v): v = W_l at the (field pair, l, m) entries of A."""
+    W = cv.window(problem.bl, problem.pl)
+    col = {key: j for j, key in enumerate(modes)}
+    out = []
+    for spec, a, b in parameters(spectra, lo, hi):
+        r, c, v = [], [], []
+        for l in range(a, b + 1):
+            for fa, fb in _PAIRS[spec]:
+                for m in range(0, l + 1):
+                    for cs in ((0,) if m == 0 else (0, 1)):
+                        r.append(col[(fa, l, m, cs)])
+                        c.append(col[(fb, l, m, cs)])
+                        v.append(W[l])
+        out.append((np.array(r), np.array(c), np.array(v)))
+    return out
+
+
+def projected_inverse(problem, C=None):
+    """Z = Y^T C^-1 Y (Eq. projected_inv) with Y, the mode list, and the Cholesky factor of C."""
+    if C is None:
+        C = cv.total_covariance(problem)
+    th, ph = _directions(problem)
+    Y, modes = cv.harmonic_basis(th, ph, problem.fields, problem.lmin, problem.lmax)
+    fac = sla.cho_factor(C, lower=True)
+    Z = Y.T @ sla.cho_solve(fac, Y)
+    return Z, Y, modes, fac
+
+
+def fisher_from_z(Z, coo):
+    """Eq. sparse_trace: F_AB = 1/2 sum_{a in A, b in B} v_a v_b Z[c_b, r_a] Z[c_a, r_b]."""
+    k = len(coo)
+    F = np.zeros((k, k))
+    for i, (ra, ca, va) in enumerate(coo):
+        for j, (rb, cb, vb) in enumerate(coo):
+            z1 = Z[np.ix_(cb, ra)]             # [beta][alpha]
+            z2 = Z[np.ix_(ca, rb)]             # [alpha][beta]
+            F[i, j] = 0.5 * np.sum(vb[:, None] * va[None, :] * z1 * z2.T)
+    return F
+
+
+def quadratic_from_w(w, coo):
+    """Eq. q_harmonic without the bias: y_A = 1/2 w^T E_A w; w is [nmaps][k]."""
+    w = np.atleast_2d(w)
+    return np.stack([0.5 * np.sum(v[None, :] * w[:, r] * w[:, c], axis=1) for r, c, v in coo], axis=1)
+
+
+def bias_from_z(Z, Lam, coo):
+    """b_A = 1/2 tr[E_A (Z - Z Lambda Z)] = 1/2 sum_a v_a X[c_a, r_a]."""
+    ZL = Z @ Lam
+    out = np.zeros(len(coo))
+    for i, (r, c, v) in enumerate(coo):
+        zlz = np.sum(ZL[c, :] * Z[:, r].T, axis=1)      # (Z Lambda Z)[c_a, r_a]
+        out[i] = 0.5 * np.sum(v * (Z[c, r] - zlz))
+    return out
+
+
+def qml_harmonic(problem, spectra, lo, hi, maps=None, C=None):
+    """Fisher, raw y, bias and C_hat = F^-1 (y - b) (Eq. qml_estimate) through Z."""
+    Z, Y, modes, fac = projected_inverse(problem, C)
+    coo = coo_derivatives(problem, modes, spectra, lo, hi)
+    F = fisher_from_z(Z, coo)
+    Lam = cv.mode_covariance(modes, problem.cl, problem.bl, problem.pl)
+    b = bias_from_z(Z, Lam, coo)
+    out = {"F": F, "bias": b, "Z": Z, "modes": modes}
+    if maps is not None:
+        w = (Y.T @ sla.cho_solve(fac, np.atleast_2d(maps).T)).T
+        y = quadratic_from_w(w, coo)
+        out["y"] = y
+        out["chat"] = deconvolve(F, y - b[None, :])
+    return out
+
+
+def deconvolve(F, q):
+    """C_hat = F^-1 q by a Cholesky solve of F (Eqs. qml_estimate, deconvolved); q is [nmaps][k]."""
+    fac = sla.cho_factor(F, lower=True)
+    return sla.cho_solve(fac, np.atleast_2d(q).T).T
+
+
+def bin_matrix(lmin, lmax, lo, hi):
+    """P_Sigma [n_b][n_l]: 1 where l lies in bin b (binning identity of the validation section)."""
+    nl = lmax - lmin + 1
+    P = np.zeros((len(lo), nl))
+    for b, (a, c) in enumerate(zip(lo, hi)):
+        P[b, a - lmin:c - lmin + 1] = 1.0
+    return P

@@ -1,0 +1,364 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each check is chosen so that a plausible slip in the oracle (a dropped term, a
+wrong sign, a swapped index or a transposed operand) fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+from scipy.special import eval_legendre, lpmv
+from scipy.stats import multivariate_normal
+
+from oracle import covariance as cv
+from oracle import healpix, likelihood, qml
+from oracle.wigner import wigner_d
+from paper_2605_21149_amd import inputs as I
+
+from oracle_cases import gl_problem, random_spectra, tiny_healpix
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+# --------------------------------------------------------------------------- geometry
+def test_healpix_counts_and_nside1_centres():
+    for nside in (1, 2, 4, 8):
+        th, ph = healpix.ring_theta_phi(nside)
+        assert th.size == 12 * nside * nside
+        z = np.round(np.cos(th), 12)
+        assert np.unique(z).size == 4 * nside - 1          # 4 nside - 1 rings
+    th, ph = healpix.ring_theta_phi(1)
+    # Gorski et al. 2005: N_side = 1 has rings at z = 2/3, 0, -2/3 of 4 pixels each;
+    # the polar rings sit at phi = pi/4 + k pi/2, the equator at phi = k pi/2.
+    np.testing.assert_allclose(np.cos(th), [2 / 3] * 4 + [0] * 4 + [-2 / 3] * 4, atol=1e-15)
+    np.testing.assert_allclose(ph[:4], np.pi / 4 + np.arange(4) * np.pi / 2, atol=1e-15)
+    np.testing.assert_allclose(ph[4:8], np.arange(4) * np.pi / 2, atol=1e-15)
+    # equal-area: mean of z over the sphere vanishes, mean of z^2 is 1/3 to O(1/npix)
+    th, _ = healpix.ring_theta_phi(16)
+    assert abs(np.mean(np.cos(th))) < 1e-14
+    assert abs(np.mean(np.cos(th) ** 2) - 1 / 3) < 1e-3
+
+
+def test_mask_sizes_of_the_workloads():
+    th8, _ = healpix.ring_theta_phi(8)
+    th16, _ = healpix.ring_theta_phi(16)
+    keep8 = np.abs(np.cos(th8)) > math.sin(math.radians(15))
+    keep16 = np.abs(np.cos(th16)) > math.sin(math.radians(20))
+    # 7 equatorial rings of 32 pixels removed at N_side 8; 1984 kept at N_side 16
+    assert keep8.sum() == 768 - 7 * 32 == 544
+    assert keep16.sum() == 1984
+    assert np.array_equal(keep8, I.mask_abs_z_above(8, math.sin(math.radians(15))).astype(bool))
+    assert np.array_equal(keep16, I.mask_abs_z_above(16, math.sin(math.radians(20))).astype(bool))
+
+
+# --------------------------------------------------------------------------- Wigner d
+def test_wigner_closed_forms_and_legendre():
+    th = np.linspace(0.05, 3.1, 17)
+    mu = np.cos(th)
+    np.testing.assert_allclose(wigner_d(2, 2, 2, th)[2], ((1 + mu) / 2) ** 2, atol=1e-15)
+    np.testing.assert_allclose(wigner_d(2, 2, -2, th)[2], ((1 - mu) / 2) ** 2, atol=1e-15)
+    np.testing.assert_allclose(wigner_d(2, 2, 0, th)[2], math.sqrt(6) / 4 * (1 - mu * mu), atol=1e-15)
+    np.testing.assert_allclose(wigner_d(1, 1, 0, th)[1], -np.sin(th) / math.sqrt(2), atol=1e-15)
+    for l in range(0, 30):
+        np.testing.assert_allclose(wigner_d(29, 0, 0, th)[l], eval_legendre(l, mu), atol=1e-13)
+    # d^l_{m0} = sqrt((l-m)!/(l+m)!) P_l^m with the Condon-Shortley phase (scipy's lpmv)
+    for m in (1, 2, 5, 11):
+        d = wigner_d(20, m, 0, th)
+        for l in range(m, 21):
+            ref = math.sqrt(math.factorial(l - m) / math.factorial(l + m)) * lpmv(m, l, mu)
+            np.testing.assert_allclose(d[l], ref, atol=1e-13)
+
+
+def test_wigner_unitarity_and_symmetries():
+    th = np.array([0.2, 1.0, 1.9, 2.9])
+    for s in (2, -2, 0):
+        for l in (2, 5, 13, 40):
+            tot = sum(wigner_d(l, mp, s, th)[l] ** 2 for mp in range(-l, l + 1))
+            np.testing.assert_allclose(tot, 1.0, atol=1e-12)
+    # orthogonality of columns s = 2 and s = -2 for l >= 2
+    for l in (3, 9):
+        dot = sum(wigner_d(l, mp, 2, th)[l] * wigner_d(l, mp, -2, th)[l] for mp in range(-l, l + 1))
+        np.testing.assert_allclose(dot, 0.0, atol=1e-12)
+    # d^l_{m,s}(pi - th) = (-1)^(l+m) d^l_{m,-s}(th)
+    for m in (0, 3, 7):
+        a = wigner_d(12, m, 2, np.pi - th)
+        b = wigner_d(12, m, -2, th)
+        for l in range(max(m, 2), 13):
+            np.testing.assert_allclose(a[l], (-1) ** (l + m) * b[l], atol=1e-13)
+
+
+def test_pair_functions_against_general_wigner():
+    beta = np.array([0.0, 0.3, 1.2, 2.0, np.pi])
+    mu = np.cos(beta)
+    P, d22, d2m2, d20 = cv.pair_functions(mu, 2, 30)
+    G22, G2m2, G20 = wigner_d(30, 2, 2, beta), wigner_d(30, 2, -2, beta), wigner_d(30, 2, 0, beta)
+    for l in range(2, 31):
+        np.testing.assert_allclose(P[l], eval_legendre(l, mu), atol=1e-13)
+        np.testing.assert_allclose(d22[l], G22[l], atol=1e-13)
+        np.testing.assert_allclose(d2m2[l], G2m2[l], atol=1e-13)
+        np.testing.assert_allclose(d20[l], G20[l], atol=1e-13)
+    # coincident and antipodal limits used for degenerate pixel pairs
+    np.testing.assert_allclose(d22[2:, 0], 1.0, atol=1e-14)
+    np.testing.assert_allclose(d2m2[2:, 0], 0.0, atol=1e-14)
+    np.testing.assert_allclose(d22[2:, -1], 0.0, atol=1e-14)
+    np.testing.assert_allclose(d2m2[2:, -1], (-1.0) ** np.arange(2, 31), atol=1e-13)
+
+
+# --------------------------------------------------------------------------- covariance
+def test_addition_theorem_spin0():
+    """Eq. addition_theorem: Y Lambda Y^T with scipy's Y_lm equals the Legendre pair sum."""
+    th, ph = healpix.ring_theta_phi(4)
+    lmax = 12
+    cl = random_spectra(lmax, 3)
+    bl = I.gaussian_beam(lmax, 600.0)
+    pl = I.disc_pixel_window(lmax, 4)
+    Sp = cv.signal_pairs(th, ph, "T", cl, bl, pl, 2, lmax)
+    Sh = cv.signal_harmonic(th, ph, "T", cl, bl, pl, 2, lmax)
+    assert np.max(np.abs(Sp - Sh)) < 1e-13 * np.max(np.abs(Sp))
+
+
+@pytest.mark.parametrize("fields", ["QU", "TQU"])
+def test_spin2_pair_route_equals_harmonic_route(fields):
+    """Pairs with rotation angles (App. A.4) == V^T Lambda V from Eqs. spin_y_def, EB_from_spin,
+    including TE, TB, EB and the coincident and antipodal pairs of a full-sky map."""
+    th, ph = healpix.ring_theta_phi(2)
+    lmax = 7
+    cl = random_spectra(lmax, 5)
+    bl, pl = np.ones(lmax + 1), np.ones(lmax + 1)
+    Sp = cv.signal_pairs(th, ph, fields, cl, bl, pl, 2, lmax)
+    Sh = cv.signal_harmonic(th, ph, fields, cl, bl, pl, 2, lmax)
+    assert np.max(np.abs(Sp - Sh)) < 1e-13 * np.max(np.abs(Sp))
+    assert np.max(np.abs(Sp - Sp.T)) < 1e-14 * np.max(np.abs(Sp))
+
+
+def test_spin2_sign_structure():
+    """T-Q correlation of a pure positive TE spectrum at small separation on a meridian is
+    negative (the E sign of Eq. EB_from_spin), and it flips with the sign of C^TE."""
+    th = np.array([1.0, 1.05])
+    ph = np.array([0.3, 0.3])
+    lmax = 20
+    cl = np.zeros((6, lmax + 1))
+    cl[0, 2:] = cl[1, 2:] = 1.0
+    cl[3, 2:] = 0.5
+    one = np.ones(lmax + 1)
+    S = cv.signal_pairs(th, ph, "TQU", cl, one, one, 2, lmax)
+    S2 = cv.signal_harmonic(th, ph, "TQU", cl, one, one, 2, lmax)
+    tq = S[0, 3]               # T at pixel 0, Q at pixel 1
+    assert tq < 0 and abs(tq - S2[0, 3]) < 1e-12
+    cl[3] *= -1
+    assert cv.signal_pairs(th, ph, "TQU", cl, one, one, 2, lmax)[0, 3] == pytest.approx(-tq)
+
+
+# --------------------------------------------------------------------------- likelihood
+def test_likelihood_brute_force_tiny():
+    p = tiny_healpix("TQU", nside=1, lmax=4, cut=-1.0, lowrank=2)
+    C = cv.total_covariance(p)
+    d = np.random.default_rng(3).standard_normal((2, p.n))
+    chi2, logdet = likelihood.chi2_logdet(C, d)
+    sign, ld = np.linalg.slogdet(C)
+    assert sign > 0 and abs(ld - logdet) < 1e-10 * abs(ld)
+    Ci = np.linalg.inv(C)
+    np.testing.assert_allclose(chi2, np.einsum("ij,jk,ik->i", d, Ci, d), rtol=1e-10)
+    for j in range(2):
+        lp = multivariate_normal(np.zeros(p.n), C).logpdf(d[j])
+        assert abs(-2 * lp - (chi2[j] + logdet + p.n * math.log(2 * math.pi))) < 1e-9 * abs(lp)
+
+
+def test_logdet_matrix_determinant_lemma_and_gl_closed_form():
+    """ln|C| = ln|N| + sum_l (2l+1) ln det(I + W_l C_l / nu) on an exact-quadrature grid
+    (Eq. logdet with V N^-1 V^T = I / nu)."""
+    lmax, nu = 6, 0.7
+    for fields in ("T", "TQU"):
+        p = gl_problem(fields, lmax, nu)
+        C = cv.total_covariance(p)
+        _, logdet = likelihood.chi2_logdet(C, np.zeros((1, p.n)))
+        ref = np.sum(np.log(p.noise_diag))
+        W = cv.window(p.bl, p.pl)
+        for l in range(2, lmax + 1):
+            B = _block(p.cl, l, fields) * W[l]
+            ref += (2 * l + 1) * np.linalg.slogdet(np.eye(B.shape[0]) + B / nu)[1]
+        assert abs(logdet - ref) < 1e-11 * abs(ref)
+
+
+def _block(cl, l, fields):
+    full = np.array([[cl[0, l], cl[3, l], cl[4, l]],
+                     [cl[3, l], cl[1, l], cl[5, l]],
+                     [cl[4, l], cl[5, l], cl[2, l]]])
+    sel = {"T": [0], "QU": [1, 2], "TQU": [0, 1, 2]}[fields]
+    return full[np.ix_(sel, sel)]
+
+
+# --------------------------------------------------------------------------- Fisher
+def _gl_fisher_closed_form(p, spectra):
+    """Full-sky Fisher: F = (2l+1)/2 tr[Cb^-1 dCb_A Cb^-1 dCb_B] per l, Cb = W_l C_l + nu I."""
+    fields = p.fields
+    W = cv.window(p.bl, p.pl)
+    nu = p.extra["nu"]
+    names = {"T": ["T"], "QU": ["E", "B"], "TQU": ["T", "E", "B"]}[fields]
+    pos = {f: i for i, f in enumerate(names)}
+    pairs = {"TT": ("T", "T"), "EE": ("E", "E"), "BB": ("B", "B"), "TE": ("T", "E"),
+             "TB": ("T", "B"), "EB": ("E", "B")}
+    specs = [s for s in cv.SPECS if s in spectra]
+    nl = p.lmax - 1
+    F = np.zeros((len(specs) * nl, len(specs) * nl))
+    for l in range(2, p.lmax + 1):
+        Cb = W[l] * _block(p.cl, l, fields) + nu * np.eye(len(names))
+        Ci = np.linalg.inv(Cb)
+        dC = []
+        for s in specs:
+            a, b = pairs[s]
+            D = np.zeros_like(Cb)
+            D[pos[a], pos[b]] = D[pos[b], pos[a]] = W[l]
+            dC.append(D)
+        for i, Di in enumerate(dC):
+            for j, Dj in enumerate(dC):
+                F[i * nl + l - 2, j * nl + l - 2] = 0.5 * (2 * l + 1) * np.trace(Ci @ Di @ Ci @ Dj)
+    return F
+
+
+@pytest.mark.parametrize("fields", ["T", "QU", "TQU"])
+def test_fisher_full_sky_closed_form(fields):
+    """On the exact-quadrature grid, F_ll = (2l+1)/2 W^2/(W C + N)^2 for TT and its 2x2 / 3x3
+    generalisation; off-diagonal l != l' vanish.  Checked for both oracle routes."""
+    lmax, nu = 6, 0.4
+    p = gl_problem(fields, lmax, nu, beam_fwhm=1500.0)
+    p.extra["nu"] = nu
+    spectra = I.spectra_for_fields(fields)
+    lo = np.arange(2, lmax + 1)
+    ref = _gl_fisher_closed_form(p, spectra)
+    if fields == "T":
+        W = cv.window(p.bl, p.pl)[2:]
+        np.testing.assert_allclose(np.diag(ref), (2 * lo + 1) / 2 * W ** 2 / (W * p.cl[0, 2:] + nu) ** 2)
+    H = qml.qml_harmonic(p, spectra, lo, lo)
+    scale = np.sqrt(np.outer(np.diag(ref), np.diag(ref)))
+    assert np.max(np.abs(H["F"] - ref) / scale) < 1e-12
+    if fields != "TQU":
+        D = qml.fisher_dense(p, spectra, lo, lo)
+        assert np.max(np.abs(D - ref) / scale) < 1e-12
+
+
+def test_fisher_dense_equals_harmonic_masked_with_correlated_noise():
+    p = tiny_healpix("TQU", nside=2, lmax=5, cut=0.35, lowrank=3)
+    spectra = I.spectra_for_fields("TQU")
+    lo = np.arange(2, 6)
+    C = cv.total_covariance(p)
+    D = qml.fisher_dense(p, spectra, lo, lo, C)
+    H = qml.qml_harmonic(p, spectra, lo, lo, C=C)
+    scale = np.sqrt(np.outer(np.diag(D), np.diag(D)))
+    assert np.max(np.abs(D - H["F"]) / scale) < 1e-11
+    assert np.max(np.abs(D - D.T) / scale) < 1e-13
+    np.linalg.cholesky(D)                     # positive definite
+    bd = qml.bias_dense(p, spectra, lo, lo, C)
+    assert np.max(np.abs(bd - H["bias"]) / np.sqrt(np.diag(D))) < 1e-11
+
+
+def test_fisher_is_minus_half_hessian_of_logdet():
+    """F_ll' = -1/2 d^2 ln|C| / dC_l dC_l' (central finite differences)."""
+    p = tiny_healpix("T", nside=2, lmax=5, cut=0.2)
+    lo = np.arange(2, 6)
+    F = qml.fisher_dense(p, ("TT",), lo, lo)
+
+    def logdet(cl):
+        q = _copy(p, cl)
+        return likelihood.chi2_logdet(cv.total_covariance(q), np.zeros((1, q.n)))[1]
+
+    h = 1e-3 * p.cl[0, 2:]
+    H = np.zeros((4, 4))
+    for i in range(4):
+        for j in range(4):
+            acc = 0.0
+            for si, sj, sg in ((1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)):
+                cl = p.cl.copy()
+                cl[0, 2 + i] += si * h[i]
+                cl[0, 2 + j] += sj * h[j]
+                acc += sg * logdet(cl)
+            H[i, j] = acc / (4 * h[i] * h[j])
+    np.testing.assert_allclose(F, -0.5 * H, rtol=2e-5, atol=1e-8 * np.max(np.abs(F)))
+
+
+def _copy(p, cl):
+    import copy
+    q = copy.copy(p)
+    q.cl = cl
+    return q
+
+
+def test_quadratic_is_minus_half_chi2_gradient_and_newton_step():
+    """y_l = -1/2 d chi^2/dC_l, and F^-1 d lnL/dC = C_hat - C_fid (the QML estimate is one
+    Newton-Raphson step of the pixel likelihood from the fiducial, Sect. 2.6)."""
+    p = tiny_healpix("QU", nside=2, lmax=5, cut=0.25)
+    spectra = ("EE", "BB", "EB")        # every spectrum that enters S, so the identity is exact
+    lo = np.arange(2, 6)
+    C = cv.total_covariance(p)
+    d = np.random.default_rng(9).standard_normal((1, p.n)) * 2.0
+    H = qml.qml_harmonic(p, spectra, lo, lo, d, C)
+
+    def m2lnl(cl):
+        q = _copy(p, cl)
+        chi2, ld = likelihood.chi2_logdet(cv.total_covariance(q), d)
+        return chi2[0], ld
+
+    grad_chi2, grad_lnl = [], []
+    for s in (1, 2, 5):
+        for l in range(2, 6):
+            h = 1e-4 * p.cl[s, l]
+            cp, cm = p.cl.copy(), p.cl.copy()
+            cp[s, l] += h
+            cm[s, l] -= h
+            (xp, lp), (xm, lm) = m2lnl(cp), m2lnl(cm)
+            grad_chi2.append((xp - xm) / (2 * h))
+            grad_lnl.append(-0.5 * ((xp + lp) - (xm + lm)) / (2 * h))
+    np.testing.assert_allclose(H["y"][0], -0.5 * np.array(grad_chi2), rtol=1e-6)
+    cfid = np.concatenate([p.cl[1, 2:6], p.cl[2, 2:6], p.cl[5, 2:6]])
+    step = np.linalg.solve(H["F"], np.array(grad_lnl))
+    np.testing.assert_allclose(step, H["chat"][0] - cfid, rtol=1e-5, atol=1e-8)
+
+
+def test_unbiasedness_identity_and_binning():
+    """1/2 tr[E_b Z] = b_b + sum_l' F_bl' C_l' (exact), F_binned = P F P^T and y_b = sum y_l."""
+    p = tiny_healpix("TQU", nside=2, lmax=6, cut=0.3, lowrank=2)
+    spectra = I.spectra_for_fields("TQU")
+    lo = np.arange(2, 7)
+    C = cv.total_covariance(p)
+    d = np.random.default_rng(4).standard_normal((2, p.n))
+    H = qml.qml_harmonic(p, spectra, lo, lo, d, C)
+    coo = qml.coo_derivatives(p, H["modes"], spectra, lo, lo)
+    half_trace = np.array([0.5 * np.sum(v * H["Z"][c, r]) for r, c, v in coo])
+    cfid = np.concatenate([p.cl[k, 2:7] for k in range(6)])
+    lhs = H["bias"] + H["F"] @ cfid
+    np.testing.assert_allclose(half_trace, lhs, rtol=1e-11)
+    blo, bhi = np.array([2, 4]), np.array([3, 6])
+    Hb = qml.qml_harmonic(p, spectra, blo, bhi, d, C)
+    Pb = np.kron(np.eye(6), qml.bin_matrix(2, 6, blo, bhi))
+    np.testing.assert_allclose(Hb["F"], Pb @ H["F"] @ Pb.T, rtol=1e-11, atol=1e-14 * np.max(np.abs(H["F"])))
+    np.testing.assert_allclose(Hb["y"], H["y"] @ Pb.T, rtol=1e-11)
+    np.testing.assert_allclose(Hb["bias"], Pb @ H["bias"], rtol=1e-11)
+
+
+@pytest.mark.slow
+def test_monte_carlo_unbiasedness_and_fisher_variance():
+    """Seeded simulations d = L z: mean(C_hat) - C_fid within 4 sqrt((F^-1)_bb / N_sims),
+    and the empirical variance within 5 sqrt(2/N_sims) of (F^-1)_bb (Sects. 4.2)."""
+    p = tiny_healpix("QU", nside=4, lmax=8, cut=0.2, noise=0.05)
+    spectra = ("EE", "BB", "EB")
+    lo = np.arange(2, 9, 2)
+    hi = np.minimum(lo + 1, 8)
+    C = cv.total_covariance(p)
+    nsim = 4000
+    L = np.linalg.cholesky(C)
+    z = np.random.default_rng(900).standard_normal((p.n, nsim))
+    maps = (L @ z).T
+    H = qml.qml_harmonic(p, spectra, lo, hi, maps, C)
+    Finv = np.linalg.inv(H["F"])
+    # the binned estimator targets the Fisher-weighted in-bin average; with the bin derivative
+    # of Sect. 2.4 the expectation is F_b^-1 sum_l F_bl C_l, computed from the unbinned Fisher
+    Hu = qml.qml_harmonic(p, spectra, np.arange(2, 9), np.arange(2, 9), C=C)
+    cl_unb = np.concatenate([p.cl[k, 2:9] for k in (1, 2, 5)])
+    Pb = np.kron(np.eye(3), qml.bin_matrix(2, 8, lo, hi))
+    truth = Finv @ (Pb @ Hu["F"] @ cl_unb)
+    mean = H["chat"].mean(axis=0)
+    sig = np.sqrt(np.diag(Finv))
+    assert np.all(np.abs(mean - truth) < 4 * sig / np.sqrt(nsim))
+    var = H["chat"].var(axis=0)
+    assert np.all(np.abs(var / sig ** 2 - 1) < 5 * np.sqrt(2 / nsim))
