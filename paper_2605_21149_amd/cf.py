@@ -1,0 +1,312 @@
+"""ctypes binding of libcf (include/cf.h): argument marshalling only.
+
+Every function here packs numpy arrays (host memory) or torch CUDA tensors (device memory)
+into the C structs of cf.h and calls the library; all arithmetic of the path runs in the
+library's HIP kernels.  Loading fails loudly when libcf.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcf.so")
+
+CF_OK, CF_EINVAL, CF_ENOTPD, CF_ENOMEM, CF_EDEVICE, CF_ENOCONV = range(6)
+CF_FP64, CF_MIXED_FP32, CF_MIXED_BF16X3 = 0, 1, 2
+FIELDS = {"T": 1, "QU": 2, "TQU": 3}
+SPEC_BITS = {"TT": 1, "EE": 2, "BB": 4, "TE": 8, "TB": 16, "EB": 32}
+CF_NOISE_DIAG, CF_NOISE_DENSE = 0, 1
+CF_MEM_HOST, CF_MEM_DEVICE = 0, 1
+_STATUS = {1: "CF_EINVAL", 2: "CF_ENOTPD", 3: "CF_ENOMEM", 4: "CF_EDEVICE", 5: "CF_ENOCONV"}
+
+_dp = C.POINTER(C.c_double)
+
+
+class cf_problem(C.Structure):
+    _fields_ = [("nside", C.c_int32), ("mask", C.POINTER(C.c_uint8)), ("ndir", C.c_int64),
+                ("theta", _dp), ("phi", _dp), ("fields", C.c_int32), ("lmin", C.c_int32),
+                ("lmax", C.c_int32), ("cl", _dp), ("bl", _dp), ("pl", _dp),
+                ("noise_kind", C.c_int32), ("noise", _dp), ("noise_rank", C.c_int32),
+                ("noise_U", _dp), ("mem", C.c_int32)]
+
+
+class cf_bins(C.Structure):
+    _fields_ = [("nbins", C.c_int32), ("lo", C.POINTER(C.c_int32)), ("hi", C.POINTER(C.c_int32)),
+                ("spectra", C.c_uint32)]
+
+
+class cf_exec(C.Structure):
+    _fields_ = [("stream", C.c_void_p), ("stage_timing", C.c_int32), ("refine_max", C.c_int32),
+                ("allow_fallback", C.c_int32)]
+
+
+class cf_report(C.Structure):
+    _fields_ = [("ms_total", C.c_double), ("ms_stage", C.c_double * 8), ("flops", C.c_double),
+                ("logdet", C.c_double), ("n", C.c_int64), ("nmodes", C.c_int64),
+                ("fail_index", C.c_int32), ("ir_iters", C.c_int32), ("est_err", C.c_double * 4),
+                ("n_fallback", C.c_int64)]
+
+    def as_dict(self):
+        return {"ms_total": self.ms_total, "ms_stage": list(self.ms_stage), "flops": self.flops,
+                "logdet": self.logdet, "n": self.n, "nmodes": self.nmodes,
+                "fail_index": self.fail_index, "ir_iters": self.ir_iters,
+                "est_err": list(self.est_err), "n_fallback": self.n_fallback}
+
+
+STAGES = ("build", "potrf", "ybuild", "trsm", "syrk", "reduce", "qml", "other")
+
+# Every symbol include/cf.h declares.
+EXPORTS = ("cf_problem_dim", "cf_problem_nmodes", "cf_cov_build", "cf_fisher", "cf_qml",
+           "cf_loglike_batch", "cf_last_error", "cf_version")
+
+
+class CFError(RuntimeError):
+    def __init__(self, status, msg, report=None):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.report = report
+
+
+_lib = None
+
+
+def lib():
+    """Load libcf.so (raises when it has not been built: there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2605_21149_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        L.cf_last_error.restype = C.c_char_p
+        L.cf_version.restype = C.c_char_p
+        L.cf_problem_dim.restype = C.c_int64
+        L.cf_problem_dim.argtypes = [C.POINTER(cf_problem)]
+        L.cf_problem_nmodes.restype = C.c_int64
+        L.cf_problem_nmodes.argtypes = [C.POINTER(cf_problem)]
+        L.cf_cov_build.argtypes = [C.POINTER(cf_problem), _dp, C.POINTER(C.c_int64),
+                                   C.POINTER(cf_exec), C.POINTER(cf_report)]
+        L.cf_fisher.argtypes = [C.POINTER(cf_problem), C.POINTER(cf_bins), C.c_int32, _dp,
+                                C.POINTER(cf_exec), C.POINTER(cf_report)]
+        L.cf_qml.argtypes = [C.POINTER(cf_problem), C.POINTER(cf_bins), _dp, C.c_int32, C.c_int32,
+                             _dp, _dp, _dp, _dp, C.POINTER(cf_exec), C.POINTER(cf_report)]
+        L.cf_loglike_batch.argtypes = [C.POINTER(cf_problem), C.c_int32, C.c_int32, _dp, C.c_int32,
+                                       C.POINTER(_dp), C.c_int32, C.c_int32, _dp, _dp, _dp,
+                                       C.POINTER(cf_exec), C.POINTER(cf_report)]
+        for name in ("cf_cov_build", "cf_fisher", "cf_qml", "cf_loglike_batch"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().cf_last_error().decode()
+
+
+# ------------------------------------------------------------------------------ marshalling
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, ctype=C.c_double):
+    if x is None:
+        return None
+    if _is_torch(x):
+        return C.cast(C.c_void_p(x.data_ptr()), C.POINTER(ctype))
+    return x.ctypes.data_as(C.POINTER(ctype))
+
+
+def _host(a, dtype=np.float64):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+@dataclass
+class _Packed:
+    struct: cf_problem
+    keep: list
+
+
+def pack_problem(p, device=False, torch_device="cuda") -> _Packed:
+    """Build a cf_problem from an ``inputs.Problem``.  device=True stages the noise arrays as
+    torch tensors on the GPU (mem = CF_MEM_DEVICE); otherwise they stay numpy host arrays."""
+    keep = []
+    s = cf_problem()
+    s.nside = int(p.nside)
+    if p.nside:
+        if p.mask is not None:
+            m = _host(p.mask, np.uint8)
+            keep.append(m)
+            s.mask = _ptr(m, C.c_uint8)
+    else:
+        th, ph = _host(p.theta), _host(p.phi)
+        keep += [th, ph]
+        s.ndir = th.shape[0]
+        s.theta, s.phi = _ptr(th), _ptr(ph)
+    s.fields = FIELDS[p.fields]
+    s.lmin, s.lmax = int(p.lmin), int(p.lmax)
+    cl, bl, pl = _host(p.cl), _host(p.bl), _host(p.pl)
+    keep += [cl, bl, pl]
+    s.cl, s.bl, s.pl = _ptr(cl), _ptr(bl), _ptr(pl)
+    if p.noise_dense is not None:
+        s.noise_kind = CF_NOISE_DENSE
+        noise = p.noise_dense
+        U = None
+    else:
+        s.noise_kind = CF_NOISE_DIAG
+        noise = p.noise_diag
+        U = p.noise_U
+    noise = _to_mem(noise, device, torch_device)
+    keep.append(noise)
+    s.noise = _ptr(noise)
+    if U is not None:
+        U = _to_mem(U, device, torch_device)
+        keep.append(U)
+        s.noise_rank = U.shape[1]
+        s.noise_U = _ptr(U)
+    s.mem = CF_MEM_DEVICE if device else CF_MEM_HOST
+    return _Packed(s, keep)
+
+
+def _to_mem(a, device, torch_device):
+    if device:
+        import torch
+        if _is_torch(a):
+            return a.to(device=torch_device, dtype=torch.float64).contiguous()
+        return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(torch_device)
+    if _is_torch(a):
+        raise TypeError("host call given a torch tensor")
+    return _host(a)
+
+
+def pack_bins(b):
+    lo, hi = _host(b.lo, np.int32), _host(b.hi, np.int32)
+    s = cf_bins()
+    s.nbins = lo.shape[0]
+    s.lo, s.hi = _ptr(lo, C.c_int32), _ptr(hi, C.c_int32)
+    s.spectra = sum(SPEC_BITS[x] for x in b.spectra)
+    return s, [lo, hi]
+
+
+def _exec(stream=None, stage_timing=False):
+    e = cf_exec()
+    e.stream = stream
+    e.stage_timing = 1 if stage_timing else 0
+    e.refine_max = -1
+    e.allow_fallback = 0
+    return e
+
+
+def _torch_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(st, rep=None):
+    if st != CF_OK:
+        raise CFError(st, last_error(), rep.as_dict() if rep is not None else None)
+
+
+def _alloc(shape, device):
+    if device:
+        import torch
+        return torch.empty(shape, dtype=torch.float64, device="cuda")
+    return np.empty(shape, dtype=np.float64)
+
+
+# ------------------------------------------------------------------------------ entry points
+def problem_dim(p) -> int:
+    pk = pack_problem(p)
+    return int(lib().cf_problem_dim(C.byref(pk.struct)))
+
+
+def problem_nmodes(p) -> int:
+    pk = pack_problem(p)
+    return int(lib().cf_problem_nmodes(C.byref(pk.struct)))
+
+
+def cov_build(p, device=False, stage_timing=False, report=False):
+    """C = S + N as an [n][n] array (numpy, or a torch CUDA tensor when device=True)."""
+    pk = pack_problem(p, device)
+    n = int(lib().cf_problem_dim(C.byref(pk.struct)))
+    _check(0 if n > 0 else CF_EINVAL)
+    out = _alloc((n, n), device)
+    rep = cf_report()
+    ex = _exec(_torch_stream() if device else None, stage_timing)
+    n_out = C.c_int64(0)
+    st = lib().cf_cov_build(C.byref(pk.struct), _ptr(out), C.byref(n_out), C.byref(ex), C.byref(rep))
+    _check(st, rep)
+    return (out, rep.as_dict()) if report else out
+
+
+def fisher(p, bins, precision=CF_FP64, device=False, stage_timing=False, report=False, packed=None):
+    pk = packed or pack_problem(p, device)
+    bs, keep = pack_bins(bins)
+    K = len(bins.spectra) * bs.nbins
+    out = _alloc((K, K), device)
+    rep = cf_report()
+    ex = _exec(_torch_stream() if device else None, stage_timing)
+    st = lib().cf_fisher(C.byref(pk.struct), C.byref(bs), int(precision), _ptr(out), C.byref(ex),
+                         C.byref(rep))
+    _check(st, rep)
+    return (out, rep.as_dict()) if report else out
+
+
+def qml(p, bins, maps, precision=CF_FP64, device=False, stage_timing=False, report=False,
+        packed=None):
+    """Returns dict(y, bias, chat, F) for maps [nmaps][n]."""
+    pk = packed or pack_problem(p, device)
+    bs, keep = pack_bins(bins)
+    K = len(bins.spectra) * bs.nbins
+    if device:
+        import torch
+        mp = maps if _is_torch(maps) else torch.as_tensor(np.ascontiguousarray(maps, np.float64))
+        mp = mp.to("cuda", torch.float64).contiguous()
+        if mp.dim() == 1:
+            mp = mp[None]
+    else:
+        mp = np.atleast_2d(_host(maps))
+    nmaps = mp.shape[0]
+    y, b, ch, F = _alloc((nmaps, K), device), _alloc((K,), device), _alloc((nmaps, K), device), \
+        _alloc((K, K), device)
+    rep = cf_report()
+    ex = _exec(_torch_stream() if device else None, stage_timing)
+    st = lib().cf_qml(C.byref(pk.struct), C.byref(bs), _ptr(mp), nmaps, int(precision), _ptr(y),
+                      _ptr(b), _ptr(ch), _ptr(F), C.byref(ex), C.byref(rep))
+    _check(st, rep)
+    out = {"y": y, "bias": b, "chat": ch, "F": F}
+    return (out, rep.as_dict()) if report else out
+
+
+def loglike_batch(problems: Sequence, cl_points, maps: Sequence, precision=CF_FP64, device=False,
+                  stage_timing=False, report=False, packed=None):
+    """-2 ln L over a scan.  cl_points [npoints][nprob][6][lstride]; maps[p] [nmaps][n_p].
+    Returns dict(m2lnL [npoints][nprob][nmaps], chi2 (same), logdet [npoints][nprob])."""
+    pks = packed or [pack_problem(p, device) for p in problems]
+    nprob = len(pks)
+    arr = (cf_problem * nprob)(*[pk.struct for pk in pks])
+    if device:
+        import torch
+        clp = cl_points if _is_torch(cl_points) else torch.as_tensor(np.ascontiguousarray(cl_points, np.float64))
+        clp = clp.to("cuda", torch.float64).contiguous()
+        mps = [(m if _is_torch(m) else torch.as_tensor(np.ascontiguousarray(m, np.float64))).to("cuda", torch.float64).contiguous() for m in maps]
+    else:
+        clp = _host(cl_points)
+        mps = [np.atleast_2d(_host(m)) for m in maps]
+    npoints, lstride = clp.shape[0], clp.shape[-1]
+    assert clp.shape[1] == nprob and clp.shape[2] == 6
+    nmaps = mps[0].shape[0]
+    mptr = (_dp * nprob)(*[_ptr(m) for m in mps])
+    m2 = _alloc((npoints, nprob, nmaps), device)
+    x2 = _alloc((npoints, nprob, nmaps), device)
+    ld = _alloc((npoints, nprob), device)
+    rep = cf_report()
+    ex = _exec(_torch_stream() if device else None, stage_timing)
+    st = lib().cf_loglike_batch(arr, nprob, npoints, _ptr(clp), lstride, mptr, nmaps, int(precision),
+                                _ptr(m2), _ptr(x2), _ptr(ld), C.byref(ex), C.byref(rep))
+    _check(st, rep)
+    out = {"m2lnL": m2, "chi2": x2, "logdet": ld}
+    return (out, rep.as_dict()) if report else out

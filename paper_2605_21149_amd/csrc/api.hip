@@ -1,0 +1,813 @@
+// C ABI of libcf: argument validation, staging, workspace, orchestration of the kernels.
+#include "../../include/cf.h"
+#include "cf_internal.h"
+
+#include <algorithm>
+#include <climits>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace cf {
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define CF_DEV(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(_e == hipErrorOutOfMemory ? CF_ENOMEM : CF_EDEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(_e), __FILE__, __LINE__);                   \
+  } while (0)
+
+// ------------------------------------------------------------------------------- per device
+struct Device {
+  std::mutex mu;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t cap = 0;
+  int* hflags = nullptr;   // pinned host mirror of the device flags
+};
+Device g_dev[64];
+
+struct Bump {  // carves 256-byte aligned sub-buffers out of the workspace
+  char* base;
+  size_t off = 0;
+  explicit Bump(char* b) : base(b) {}
+  template <typename T>
+  T* take(size_t count) {
+    T* p = reinterpret_cast<T*>(base + off);
+    off += (count * sizeof(T) + 255) & ~size_t(255);
+    return p;
+  }
+};
+
+int ensure_ws(Device& d, size_t bytes) {
+  if (bytes <= d.cap) return CF_OK;
+  if (d.ws) CF_DEV(hipFree(d.ws));
+  d.ws = nullptr;
+  d.cap = 0;
+  size_t want = bytes + (bytes >> 4);
+  hipError_t e = hipMalloc(&d.ws, want);
+  if (e != hipSuccess) {
+    d.ws = nullptr;
+    return fail(CF_ENOMEM, "workspace of %zu bytes: %s", want, hipGetErrorString(e));
+  }
+  d.cap = want;
+  return CF_OK;
+}
+
+// Bytes a Bump would use for the given list of (count, size) pairs.
+struct Sizer {
+  size_t off = 0;
+  template <typename T>
+  void add(size_t count) { off += (count * sizeof(T) + 255) & ~size_t(255); }
+};
+
+// ------------------------------------------------------------------------------- problem
+struct HostProblem {
+  int npx = 0, nmaps = 0, has_t = 0, has_p = 0, n = 0;
+  int lmin = 0, lmax = 0, kf = 0, nfm = 0;
+  int64_t k = 0;
+  std::vector<int> ring;          // active RING indices (nside > 0)
+};
+
+bool finite_all(const double* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+int check_problem(const cf_problem* P, HostProblem& H, bool need_cl) {
+  if (!P) return fail(CF_EINVAL, "problem is NULL");
+  if (P->fields < 1 || P->fields > 3) return fail(CF_EINVAL, "fields must be CF_T, CF_QU or CF_TQU");
+  H.has_t = (P->fields & 1) != 0;
+  H.has_p = (P->fields & 2) != 0;
+  H.nmaps = (H.has_t ? 1 : 0) + (H.has_p ? 2 : 0);
+  H.nfm = H.nmaps;
+  if (P->lmin < 0 || P->lmax < P->lmin || P->lmax >= kMaxL)
+    return fail(CF_EINVAL, "l-range chain broken: need 0 <= lmin <= lmax < %d (lmin=%d lmax=%d)", kMaxL,
+                P->lmin, P->lmax);
+  if (H.has_p && P->lmin < 2)
+    return fail(CF_EINVAL, "lmin=%d below |spin|=2 with Q,U present", P->lmin);
+  H.lmin = P->lmin;
+  H.lmax = P->lmax;
+  H.kf = (P->lmax + 1) * (P->lmax + 1) - P->lmin * P->lmin;
+  H.k = (int64_t)H.nfm * H.kf;
+  if (P->nside > 0) {
+    if (P->nside > 8192) return fail(CF_EINVAL, "nside=%d too large", P->nside);
+    int64_t np = 12LL * P->nside * P->nside;
+    H.ring.clear();
+    for (int64_t i = 0; i < np; ++i)
+      if (!P->mask || P->mask[i]) H.ring.push_back((int)i);
+    H.npx = (int)H.ring.size();
+  } else if (P->nside == 0) {
+    if (P->ndir <= 0 || !P->theta || !P->phi) return fail(CF_EINVAL, "explicit directions missing");
+    if (!finite_all(P->theta, P->ndir) || !finite_all(P->phi, P->ndir))
+      return fail(CF_EINVAL, "non-finite direction");
+    H.npx = (int)P->ndir;
+  } else {
+    return fail(CF_EINVAL, "nside=%d < 0", P->nside);
+  }
+  if (H.npx <= 0) return fail(CF_EINVAL, "no retained pixels");
+  int64_t n64 = (int64_t)H.npx * H.nmaps;
+  if (n64 > (1LL << 20)) return fail(CF_EINVAL, "data dimension %lld too large", (long long)n64);
+  H.n = (int)n64;
+  const int L = P->lmax + 1;
+  if (need_cl) {
+    if (!P->cl) return fail(CF_EINVAL, "cl is NULL");
+    if (!finite_all(P->cl, 6LL * L)) return fail(CF_EINVAL, "non-finite C_l");
+  }
+  if (P->bl && !finite_all(P->bl, L)) return fail(CF_EINVAL, "non-finite beam");
+  if (P->pl && !finite_all(P->pl, L)) return fail(CF_EINVAL, "non-finite pixel window");
+  if (P->noise_kind != CF_NOISE_DIAG && P->noise_kind != CF_NOISE_DENSE)
+    return fail(CF_EINVAL, "unknown noise_kind %d", P->noise_kind);
+  if (!P->noise) return fail(CF_EINVAL, "noise is NULL");
+  if (P->noise_rank < 0 || (P->noise_rank > 0 && !P->noise_U))
+    return fail(CF_EINVAL, "noise_rank=%d with noise_U=%p", P->noise_rank, (const void*)P->noise_U);
+  if (P->mem != CF_MEM_HOST && P->mem != CF_MEM_DEVICE) return fail(CF_EINVAL, "unknown mem %d", P->mem);
+  if (P->mem == CF_MEM_HOST) {
+    int64_t nn = P->noise_kind == CF_NOISE_DENSE ? (int64_t)H.n * H.n : H.n;
+    if (!finite_all(P->noise, nn)) return fail(CF_EINVAL, "non-finite noise covariance");
+    if (P->noise_rank > 0 && !finite_all(P->noise_U, (int64_t)H.n * P->noise_rank))
+      return fail(CF_EINVAL, "non-finite noise_U");
+  }
+  return CF_OK;
+}
+
+struct HostBins {
+  int ns = 0, nb = 0;
+  int spec[6] = {0, 0, 0, 0, 0, 0};
+  std::vector<int> lo, hi;
+};
+
+int check_bins(const cf_bins* B, const HostProblem& H, HostBins& out) {
+  if (!B) return fail(CF_EINVAL, "bins is NULL");
+  if (B->nbins <= 0 || !B->lo || !B->hi) return fail(CF_EINVAL, "empty bins");
+  out.ns = 0;
+  for (int s = 0; s < 6; ++s) {
+    if (!(B->spectra & (1u << s))) continue;
+    bool needT = (s == 0 || s == 3 || s == 4), needP = (s != 0);
+    if ((needT && !H.has_t) || (needP && !H.has_p))
+      return fail(CF_EINVAL, "spectrum %d requested for an absent field", s);
+    out.spec[out.ns++] = s;
+  }
+  if (out.ns == 0) return fail(CF_EINVAL, "no spectra requested");
+  if (B->spectra & ~63u) return fail(CF_EINVAL, "unknown spectrum bits");
+  out.nb = B->nbins;
+  out.lo.assign(B->lo, B->lo + B->nbins);
+  out.hi.assign(B->hi, B->hi + B->nbins);
+  for (int b = 0; b < out.nb; ++b)
+    if (out.lo[b] < H.lmin || out.hi[b] > H.lmax || out.lo[b] > out.hi[b])
+      return fail(CF_EINVAL, "bin %d = [%d, %d] outside [lmin, lmax] = [%d, %d]", b, out.lo[b],
+                  out.hi[b], H.lmin, H.lmax);
+  return CF_OK;
+}
+
+// ------------------------------------------------------------------------------- staging
+struct Staged {
+  DevProblem P;
+  int* ring = nullptr;
+  double* theta = nullptr;
+  double* phi = nullptr;
+  double* cl = nullptr;
+  double* bl = nullptr;
+  double* pl = nullptr;
+  double* pix = nullptr;
+  double* cw = nullptr;
+  double* wl = nullptr;
+  double* lam = nullptr;
+  double* coef = nullptr;
+  const double* noise = nullptr;
+  const double* noise_U = nullptr;
+};
+
+void size_staging(Sizer& z, const cf_problem* P, const HostProblem& H) {
+  const int L = H.lmax + 1;
+  z.add<int>(H.npx);
+  z.add<double>(H.npx);
+  z.add<double>(H.npx);
+  z.add<double>(6 * L);
+  z.add<double>(L);
+  z.add<double>(L);
+  z.add<double>((size_t)H.npx * kPixRec);
+  z.add<double>(6 * L);
+  z.add<double>(L);
+  z.add<double>(6 * L);
+  z.add<double>((size_t)L * kCoef);
+  if (P->mem == CF_MEM_HOST) {
+    z.add<double>(P->noise_kind == CF_NOISE_DENSE ? (size_t)H.n * H.n : (size_t)H.n);
+    if (P->noise_rank > 0) z.add<double>((size_t)H.n * P->noise_rank);
+  }
+}
+
+int stage(Bump& bp, const cf_problem* P, const HostProblem& H, const double* cl_override,
+          hipStream_t s, Staged& S) {
+  const int L = H.lmax + 1;
+  S.ring = bp.take<int>(H.npx);
+  S.theta = bp.take<double>(H.npx);
+  S.phi = bp.take<double>(H.npx);
+  S.cl = bp.take<double>(6 * L);
+  S.bl = bp.take<double>(L);
+  S.pl = bp.take<double>(L);
+  S.pix = bp.take<double>((size_t)H.npx * kPixRec);
+  S.cw = bp.take<double>(6 * L);
+  S.wl = bp.take<double>(L);
+  S.lam = bp.take<double>(6 * L);
+  S.coef = bp.take<double>((size_t)L * kCoef);
+  if (P->nside > 0) {
+    CF_DEV(hipMemcpyAsync(S.ring, H.ring.data(), sizeof(int) * H.npx, hipMemcpyHostToDevice, s));
+  } else {
+    CF_DEV(hipMemcpyAsync(S.theta, P->theta, sizeof(double) * H.npx, hipMemcpyHostToDevice, s));
+    CF_DEV(hipMemcpyAsync(S.phi, P->phi, sizeof(double) * H.npx, hipMemcpyHostToDevice, s));
+  }
+  const double* cl = cl_override ? cl_override : P->cl;
+  if (cl) {
+    CF_DEV(hipMemcpyAsync(S.cl, cl, sizeof(double) * 6 * L, hipMemcpyHostToDevice, s));
+  } else {
+    CF_DEV(launch_fill(S.cl, 6 * L, 0.0, s));
+  }
+  if (P->bl) CF_DEV(hipMemcpyAsync(S.bl, P->bl, sizeof(double) * L, hipMemcpyHostToDevice, s));
+  else CF_DEV(launch_fill(S.bl, L, 1.0, s));
+  if (P->pl) CF_DEV(hipMemcpyAsync(S.pl, P->pl, sizeof(double) * L, hipMemcpyHostToDevice, s));
+  else CF_DEV(launch_fill(S.pl, L, 1.0, s));
+  CF_DEV(launch_geometry(S.ring, P->nside, S.theta, S.phi, H.npx, S.pix, s));
+  CF_DEV(launch_tables(S.cl, S.bl, S.pl, H.lmin, H.lmax, 1, 0, L, S.cw, S.wl, S.lam, S.coef, s));
+  if (P->mem == CF_MEM_HOST) {
+    size_t nn = P->noise_kind == CF_NOISE_DENSE ? (size_t)H.n * H.n : (size_t)H.n;
+    double* nz = bp.take<double>(nn);
+    CF_DEV(hipMemcpyAsync(nz, P->noise, sizeof(double) * nn, hipMemcpyHostToDevice, s));
+    S.noise = nz;
+    if (P->noise_rank > 0) {
+      double* u = bp.take<double>((size_t)H.n * P->noise_rank);
+      CF_DEV(hipMemcpyAsync(u, P->noise_U, sizeof(double) * H.n * P->noise_rank, hipMemcpyHostToDevice, s));
+      S.noise_U = u;
+    }
+  } else {
+    S.noise = P->noise;
+    S.noise_U = P->noise_U;
+  }
+  DevProblem& D = S.P;
+  D.npx = H.npx; D.nmaps = H.nmaps; D.has_t = H.has_t; D.has_p = H.has_p; D.n = H.n;
+  D.lmin = H.lmin; D.lmax = H.lmax; D.kf = H.kf; D.nfm = H.nfm; D.k = H.k;
+  D.pix = S.pix; D.coef = S.coef; D.cw = S.cw; D.wl = S.wl; D.lam = S.lam;
+  return CF_OK;
+}
+
+// ------------------------------------------------------------------------------- timing
+struct Timer {
+  bool on = false;
+  hipStream_t s = nullptr;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> stage;
+  void begin(bool enable, hipStream_t st) {
+    on = enable;
+    s = st;
+    if (on) mark(-1);
+  }
+  void mark(int stage_id) {
+    if (!on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+    (void)hipEventRecord(e, s);
+    ev.push_back(e);
+    stage.push_back(stage_id);
+  }
+  void finish(cf_report* rep) {
+    if (!on) return;
+    (void)hipEventSynchronize(ev.back());
+    for (size_t i = 1; i < ev.size(); ++i) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev[i - 1], ev[i]);
+      if (rep && stage[i] >= 0 && stage[i] < 8) rep->ms_stage[stage[i]] += ms;
+    }
+    float tot = 0.f;
+    (void)hipEventElapsedTime(&tot, ev.front(), ev.back());
+    if (rep) rep->ms_total = tot;
+    for (auto e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+    stage.clear();
+  }
+};
+enum { ST_BUILD = 0, ST_POTRF, ST_YBUILD, ST_TRSM, ST_SYRK, ST_REDUCE, ST_QML, ST_OTHER };
+
+struct CallCtx {
+  Device* dev = nullptr;
+  hipStream_t s = nullptr;
+  std::unique_lock<std::mutex> lock;
+  int begin(const cf_exec* ex) {
+    int id = 0;
+    CF_DEV(hipGetDevice(&id));
+    if (id < 0 || id >= 64) return fail(CF_EDEVICE, "device id %d unsupported", id);
+    dev = &g_dev[id];
+    lock = std::unique_lock<std::mutex>(dev->mu);
+    if (!dev->stream) CF_DEV(hipStreamCreateWithFlags(&dev->stream, hipStreamNonBlocking));
+    if (!dev->hflags) CF_DEV(hipHostMalloc((void**)&dev->hflags, 64 * sizeof(int), hipHostMallocDefault));
+    s = (ex && ex->stream) ? (hipStream_t)ex->stream : dev->stream;
+    return CF_OK;
+  }
+};
+
+void report_init(cf_report* rep) {
+  if (!rep) return;
+  std::memset(rep, 0, sizeof *rep);
+  rep->fail_index = -1;
+}
+
+// Copy back two device ints (cov flag, pivot failure) and turn them into a status.
+int read_flags(CallCtx& c, const int* dflags, int nflags, int* out) {
+  CF_DEV(hipMemcpyAsync(c.dev->hflags, dflags, sizeof(int) * nflags, hipMemcpyDeviceToHost, c.s));
+  CF_DEV(hipStreamSynchronize(c.s));
+  for (int i = 0; i < nflags; ++i) out[i] = c.dev->hflags[i];
+  return CF_OK;
+}
+
+// ------------------------------------------------------------------------------- Fisher core
+struct FisherBufs {
+  double *C, *Y, *G, *Z, *dinv, *ldpart, *gram, *ztr, *F;
+  int* lo;
+  int* hi;
+  int* flags;   // [0] non-finite covariance, [1] first failing pivot, [2] F pivot failure
+};
+
+size_t fisher_ws(const HostProblem& H, const HostBins& B, Sizer& z) {
+  const int nl = H.lmax - H.lmin + 1;
+  const int np = H.nfm * H.nfm, nq = np * (np + 1) / 2;
+  const int K = B.ns * B.nb;
+  z.add<double>((size_t)H.n * H.n);
+  z.add<double>((size_t)H.n * H.k);
+  z.add<double>((size_t)H.n * H.k);
+  z.add<double>((size_t)H.k * H.k);
+  z.add<double>(H.n);
+  z.add<double>((H.n + kNB - 1) / kNB);
+  z.add<double>((size_t)nl * (nl + 1) / 2 * nq);
+  z.add<double>((size_t)nl * np);
+  z.add<double>((size_t)K * K);
+  z.add<int>(B.nb);
+  z.add<int>(B.nb);
+  z.add<int>(8);
+  return z.off;
+}
+
+void fisher_take(Bump& bp, const HostProblem& H, const HostBins& B, FisherBufs& f) {
+  const int nl = H.lmax - H.lmin + 1;
+  const int np = H.nfm * H.nfm, nq = np * (np + 1) / 2;
+  const int K = B.ns * B.nb;
+  f.C = bp.take<double>((size_t)H.n * H.n);
+  f.Y = bp.take<double>((size_t)H.n * H.k);
+  f.G = bp.take<double>((size_t)H.n * H.k);
+  f.Z = bp.take<double>((size_t)H.k * H.k);
+  f.dinv = bp.take<double>(H.n);
+  f.ldpart = bp.take<double>((H.n + kNB - 1) / kNB);
+  f.gram = bp.take<double>((size_t)nl * (nl + 1) / 2 * nq);
+  f.ztr = bp.take<double>((size_t)nl * np);
+  f.F = bp.take<double>((size_t)K * K);
+  f.lo = bp.take<int>(B.nb);
+  f.hi = bp.take<int>(B.nb);
+  f.flags = bp.take<int>(8);
+}
+
+// Covariance, factor, Y, G = L^-1 Y, Z = G^T G, Gram of Z blocks.
+int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, FisherBufs& f,
+                hipStream_t s, Timer& tm) {
+  const DevProblem& P = S.P;
+  const int64_t n = H.n, k = H.k;
+  CF_DEV(launch_fill_int(f.flags, 1, 0, s));
+  CF_DEV(launch_fill_int(f.flags + 1, 2, INT_MAX, s));
+  CF_DEV(launch_cov_build(P, S.cw, 0, 1, prob->noise_kind, S.noise, prob->noise_rank, S.noise_U, f.C, n,
+                          0, 1, f.flags, s));
+  tm.mark(ST_BUILD);
+  CF_DEV(potrf_f64(f.C, n, n, 0, 1, f.dinv, 0, f.ldpart, 0, f.flags + 1, s));
+  tm.mark(ST_POTRF);
+  CF_DEV(launch_ybuild(P, f.Y, k, s));
+  tm.mark(ST_YBUILD);
+  // G = L^-1 Y.  Y is block diagonal over [T | QU]: the E,B columns are zero in the T rows, so
+  // their solve starts at the 64-row block that holds the first Q row.
+  const int64_t kT = H.has_t ? H.kf : 0;
+  const int64_t p0 = (H.has_t && H.has_p) ? (H.npx / kNB) * kNB : 0;
+  if (H.has_t && H.has_p) {
+    CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.dinv, 0, f.Y, k, 0, f.G, k, 0, kT, 0, 1, s));
+    CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.dinv, 0, f.Y + kT, k, 0, f.G + kT, k, 0, k - kT, H.npx, 1, s));
+  } else {
+    CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.dinv, 0, f.Y, k, 0, f.G, k, 0, k, 0, 1, s));
+  }
+  tm.mark(ST_TRSM);
+  GemmDesc g{};
+  g.M = k; g.N = k; g.K = n - p0;
+  g.A = f.G + p0 * k; g.lda = k; g.at = 1;
+  g.B = f.G + p0 * k; g.ldb = k; g.bt = 0;
+  g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1;
+  CF_DEV(gemm_f64(g, s));
+  if (p0 > 0) {
+    GemmDesc h{};
+    h.M = kT; h.N = kT; h.K = p0;
+    h.A = f.G; h.lda = k; h.at = 1;
+    h.B = f.G; h.ldb = k; h.bt = 0;
+    h.C = f.Z; h.ldc = k; h.alpha = 1.0; h.beta = 1.0; h.lower = 1; h.batch = 1;
+    CF_DEV(gemm_f64(h, s));
+  }
+  tm.mark(ST_SYRK);
+  CF_DEV(launch_symmetrize(f.Z, k, k, s));
+  CF_DEV(launch_gram(P, f.Z, k, f.gram, f.ztr, s));
+  tm.mark(ST_REDUCE);
+  return CF_OK;
+}
+
+SpecSel make_sel(const HostBins& B, const FisherBufs& f) {
+  SpecSel S;
+  S.ns = B.ns;
+  for (int i = 0; i < 6; ++i) S.spec[i] = B.spec[i];
+  S.nb = B.nb;
+  S.lo = f.lo;
+  S.hi = f.hi;
+  return S;
+}
+
+int check_factor_flags(CallCtx& c, const FisherBufs& f, cf_report* rep) {
+  int fl[3];
+  int st = read_flags(c, f.flags, 3, fl);
+  if (st) return st;
+  if (fl[0]) return fail(CF_EINVAL, "non-finite covariance entry (check noise and spectra)");
+  if (fl[1] != INT_MAX) {
+    if (rep) rep->fail_index = fl[1];
+    return fail(CF_ENOTPD, "covariance not positive definite at pivot %d", fl[1]);
+  }
+  return CF_OK;
+}
+
+int copy_out(double* dst, const double* src, size_t count, int mem, hipStream_t s) {
+  CF_DEV(hipMemcpyAsync(dst, src, count * sizeof(double),
+                        mem == CF_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+  return CF_OK;
+}
+
+double fisher_flops(const HostProblem& H) {
+  const double n = H.n, kT = H.has_t ? H.kf : 0, k = (double)H.k;
+  const double nP = H.has_p ? (H.has_t ? n - H.npx : n) : 0, kP = k - kT;
+  double trsm = kT * n * n + kP * nP * nP;
+  double syrk = (H.has_t && H.has_p) ? (kT * kT * n + 2 * kT * kP * nP + kP * kP * nP) : k * k * n;
+  return n * n * n / 3.0 + trsm + syrk;
+}
+
+}  // namespace
+}  // namespace cf
+
+using namespace cf;
+
+extern "C" {
+
+const char* cf_last_error(void) { return g_err.c_str(); }
+const char* cf_version(void) { return "libcf 0.1 (gfx950, FP64 path)"; }
+
+int64_t cf_problem_dim(const cf_problem* prob) {
+  HostProblem H;
+  if (check_problem(prob, H, false)) return -1;
+  return H.n;
+}
+
+int64_t cf_problem_nmodes(const cf_problem* prob) {
+  HostProblem H;
+  if (check_problem(prob, H, false)) return -1;
+  return H.k;
+}
+
+int cf_cov_build(const cf_problem* prob, double* C_out, int64_t* n_out, const cf_exec* ex,
+                 cf_report* rep) {
+  report_init(rep);
+  HostProblem H;
+  if (int st = check_problem(prob, H, true)) return st;
+  if (!C_out) return fail(CF_EINVAL, "C_out is NULL");
+  CallCtx c;
+  if (int st = c.begin(ex)) return st;
+  Sizer z;
+  size_staging(z, prob, H);
+  z.add<double>((size_t)H.n * H.n);
+  z.add<int>(8);
+  if (int st = ensure_ws(*c.dev, z.off)) return st;
+  Bump bp(c.dev->ws);
+  Staged S;
+  if (int st = stage(bp, prob, H, nullptr, c.s, S)) return st;
+  double* C = prob->mem == CF_MEM_DEVICE ? C_out : bp.take<double>((size_t)H.n * H.n);
+  int* flags = bp.take<int>(8);
+  Timer tm;
+  tm.begin(ex && ex->stage_timing, c.s);
+  CF_DEV(launch_fill_int(flags, 1, 0, c.s));
+  // lower triangle, then mirrored, so that the returned matrix is exactly symmetric
+  CF_DEV(launch_cov_build(S.P, S.cw, 0, 1, prob->noise_kind, S.noise, prob->noise_rank, S.noise_U, C,
+                          H.n, 0, 1, flags, c.s));
+  CF_DEV(launch_symmetrize(C, H.n, H.n, c.s));
+  tm.mark(ST_BUILD);
+  int fl[1];
+  if (int st = read_flags(c, flags, 1, fl)) return st;
+  if (fl[0]) return fail(CF_EINVAL, "non-finite covariance entry (check noise and spectra)");
+  if (prob->mem == CF_MEM_HOST) {
+    if (int st = copy_out(C_out, C, (size_t)H.n * H.n, CF_MEM_HOST, c.s)) return st;
+  }
+  CF_DEV(hipStreamSynchronize(c.s));
+  tm.finish(rep);
+  if (n_out) *n_out = H.n;
+  if (rep) { rep->n = H.n; rep->nmodes = H.k; }
+  return CF_OK;
+}
+
+int cf_fisher(const cf_problem* prob, const cf_bins* bins, int32_t precision, double* F_out,
+              const cf_exec* ex, cf_report* rep) {
+  report_init(rep);
+  HostProblem H;
+  if (int st = check_problem(prob, H, true)) return st;
+  HostBins B;
+  if (int st = check_bins(bins, H, B)) return st;
+  if (precision != CF_FP64) return fail(CF_EINVAL, "precision %d not available in this build", precision);
+  if (!F_out) return fail(CF_EINVAL, "F_out is NULL");
+  CallCtx c;
+  if (int st = c.begin(ex)) return st;
+  Sizer z;
+  size_staging(z, prob, H);
+  fisher_ws(H, B, z);
+  if (int st = ensure_ws(*c.dev, z.off)) return st;
+  Bump bp(c.dev->ws);
+  Staged S;
+  if (int st = stage(bp, prob, H, nullptr, c.s, S)) return st;
+  FisherBufs f;
+  fisher_take(bp, H, B, f);
+  CF_DEV(hipMemcpyAsync(f.lo, B.lo.data(), sizeof(int) * B.nb, hipMemcpyHostToDevice, c.s));
+  CF_DEV(hipMemcpyAsync(f.hi, B.hi.data(), sizeof(int) * B.nb, hipMemcpyHostToDevice, c.s));
+  Timer tm;
+  tm.begin(ex && ex->stage_timing, c.s);
+  if (int st = fisher_core(prob, H, S, f, c.s, tm)) return st;
+  const SpecSel sel = make_sel(B, f);
+  CF_DEV(launch_fisher_assemble(S.P, sel, f.gram, f.F, c.s));
+  tm.mark(ST_REDUCE);
+  if (int st = check_factor_flags(c, f, rep)) return st;
+  const int K = B.ns * B.nb;
+  if (int st = copy_out(F_out, f.F, (size_t)K * K, prob->mem, c.s)) return st;
+  CF_DEV(hipStreamSynchronize(c.s));
+  tm.finish(rep);
+  if (rep) {
+    rep->n = H.n; rep->nmodes = H.k; rep->flops = fisher_flops(H);
+  }
+  return CF_OK;
+}
+
+int cf_qml(const cf_problem* prob, const cf_bins* bins, const double* maps, int32_t nmaps,
+           int32_t precision, double* y_out, double* bias_out, double* chat_out, double* F_out,
+           const cf_exec* ex, cf_report* rep) {
+  report_init(rep);
+  HostProblem H;
+  if (int st = check_problem(prob, H, true)) return st;
+  HostBins B;
+  if (int st = check_bins(bins, H, B)) return st;
+  if (precision != CF_FP64) return fail(CF_EINVAL, "precision %d not available in this build", precision);
+  if (nmaps <= 0 || !maps) return fail(CF_EINVAL, "no maps");
+  if (!y_out || !bias_out || !chat_out) return fail(CF_EINVAL, "y_out, bias_out and chat_out are required");
+  if (prob->mem == CF_MEM_HOST && !finite_all(maps, (int64_t)nmaps * H.n))
+    return fail(CF_EINVAL, "non-finite map value");
+  CallCtx c;
+  if (int st = c.begin(ex)) return st;
+  const int K = B.ns * B.nb;
+  Sizer z;
+  size_staging(z, prob, H);
+  fisher_ws(H, B, z);
+  z.add<double>((size_t)nmaps * H.n);        // maps copy (host inputs)
+  z.add<double>((size_t)H.n * nmaps);        // D = maps^T
+  z.add<double>((size_t)H.n * nmaps);        // u = L^-1 D
+  z.add<double>((size_t)H.k * nmaps);        // w = G^T u
+  z.add<double>((size_t)nmaps * K);          // y
+  z.add<double>((size_t)K);                  // bias
+  z.add<double>((size_t)nmaps * K);          // y - b
+  z.add<double>((size_t)nmaps * K);          // chat
+  z.add<double>((size_t)K * K);              // F copy for the solve
+  if (int st = ensure_ws(*c.dev, z.off)) return st;
+  Bump bp(c.dev->ws);
+  Staged S;
+  if (int st = stage(bp, prob, H, nullptr, c.s, S)) return st;
+  FisherBufs f;
+  fisher_take(bp, H, B, f);
+  double* mcopy = bp.take<double>((size_t)nmaps * H.n);
+  double* D = bp.take<double>((size_t)H.n * nmaps);
+  double* U = bp.take<double>((size_t)H.n * nmaps);
+  double* W = bp.take<double>((size_t)H.k * nmaps);
+  double* y = bp.take<double>((size_t)nmaps * K);
+  double* bias = bp.take<double>(K);
+  double* q = bp.take<double>((size_t)nmaps * K);
+  double* chat = bp.take<double>((size_t)nmaps * K);
+  double* Fw = bp.take<double>((size_t)K * K);
+  CF_DEV(hipMemcpyAsync(f.lo, B.lo.data(), sizeof(int) * B.nb, hipMemcpyHostToDevice, c.s));
+  CF_DEV(hipMemcpyAsync(f.hi, B.hi.data(), sizeof(int) * B.nb, hipMemcpyHostToDevice, c.s));
+  const double* mdev = maps;
+  if (prob->mem == CF_MEM_HOST) {
+    CF_DEV(hipMemcpyAsync(mcopy, maps, sizeof(double) * nmaps * H.n, hipMemcpyHostToDevice, c.s));
+    mdev = mcopy;
+  }
+  Timer tm;
+  tm.begin(ex && ex->stage_timing, c.s);
+  if (int st = fisher_core(prob, H, S, f, c.s, tm)) return st;
+  const SpecSel sel = make_sel(B, f);
+  CF_DEV(launch_fisher_assemble(S.P, sel, f.gram, f.F, c.s));
+  CF_DEV(launch_bias_assemble(S.P, sel, f.gram, f.ztr, bias, c.s));
+  tm.mark(ST_REDUCE);
+  // u = L^-1 d, w = Y^T C^-1 d = G^T u (Eq. weighted_data)
+  const int64_t n = H.n, k = H.k;
+  CF_DEV(launch_transpose(mdev, nmaps, n, n, D, nmaps, c.s));
+  CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.dinv, 0, D, nmaps, 0, U, nmaps, 0, nmaps, 0, 1, c.s));
+  const int64_t kT = H.has_t ? H.kf : 0;
+  const int64_t p0 = (H.has_t && H.has_p) ? (H.npx / kNB) * kNB : 0;
+  GemmDesc g{};
+  g.M = (H.has_t && H.has_p) ? kT : k; g.N = nmaps; g.K = n;
+  g.A = f.G; g.lda = k; g.at = 1;
+  g.B = U; g.ldb = nmaps; g.bt = 0;
+  g.C = W; g.ldc = nmaps; g.alpha = 1.0; g.beta = 0.0; g.lower = 0; g.batch = 1;
+  CF_DEV(gemm_f64(g, c.s));
+  if (H.has_t && H.has_p) {
+    GemmDesc h{};
+    h.M = k - kT; h.N = nmaps; h.K = n - p0;
+    h.A = f.G + p0 * k + kT; h.lda = k; h.at = 1;
+    h.B = U + p0 * nmaps; h.ldb = nmaps; h.bt = 0;
+    h.C = W + kT * nmaps; h.ldc = nmaps; h.alpha = 1.0; h.beta = 0.0; h.lower = 0; h.batch = 1;
+    CF_DEV(gemm_f64(h, c.s));
+  }
+  CF_DEV(launch_quad_assemble(S.P, sel, W, nmaps, nmaps, y, c.s));
+  // chat = F^-1 (y - b)  (Eq. qml_estimate)
+  CF_DEV(hipMemcpyAsync(q, y, sizeof(double) * nmaps * K, hipMemcpyDeviceToDevice, c.s));
+  CF_DEV(launch_sub_bias(q, bias, K, nmaps, c.s));
+  CF_DEV(hipMemcpyAsync(Fw, f.F, sizeof(double) * K * K, hipMemcpyDeviceToDevice, c.s));
+  CF_DEV(launch_small_spd_solve(Fw, K, q, chat, nmaps, f.flags + 2, c.s));
+  tm.mark(ST_QML);
+  if (int st = check_factor_flags(c, f, rep)) return st;
+  {
+    int fl3[3];
+    if (int st = read_flags(c, f.flags, 3, fl3)) return st;
+    if (fl3[2] != INT_MAX) {
+      if (rep) rep->fail_index = fl3[2];
+      return fail(CF_ENOTPD, "Fisher matrix not positive definite at pivot %d", fl3[2]);
+    }
+  }
+  if (int st = copy_out(y_out, y, (size_t)nmaps * K, prob->mem, c.s)) return st;
+  if (int st = copy_out(bias_out, bias, (size_t)K, prob->mem, c.s)) return st;
+  if (int st = copy_out(chat_out, chat, (size_t)nmaps * K, prob->mem, c.s)) return st;
+  if (F_out)
+    if (int st = copy_out(F_out, f.F, (size_t)K * K, prob->mem, c.s)) return st;
+  CF_DEV(hipStreamSynchronize(c.s));
+  tm.finish(rep);
+  if (rep) { rep->n = H.n; rep->nmodes = H.k; rep->flops = fisher_flops(H); }
+  return CF_OK;
+}
+
+}  // extern "C"
+
+extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t npoints,
+                                const double* cl_points, int32_t lstride, const double* const* maps,
+                                int32_t nmaps, int32_t precision, double* m2lnL, double* chi2,
+                                double* logdet, const cf_exec* ex, cf_report* rep) {
+  report_init(rep);
+  if (!probs || nprob <= 0) return fail(CF_EINVAL, "no problems");
+  if (npoints <= 0 || !cl_points) return fail(CF_EINVAL, "no scan points");
+  if (nmaps <= 0 || !maps) return fail(CF_EINVAL, "no maps");
+  if (!m2lnL) return fail(CF_EINVAL, "m2lnL is NULL");
+  if (precision != CF_FP64) return fail(CF_EINVAL, "precision %d not available in this build", precision);
+  const int mem = probs[0].mem;
+  std::vector<HostProblem> H(nprob);
+  int lmax_all = 0;
+  for (int p = 0; p < nprob; ++p) {
+    if (int st = check_problem(&probs[p], H[p], false)) return st;
+    if (probs[p].mem != mem) return fail(CF_EINVAL, "problems disagree on mem");
+    if (!maps[p]) return fail(CF_EINVAL, "maps[%d] is NULL", p);
+    if (H[p].lmax > lmax_all) lmax_all = H[p].lmax;
+  }
+  if (lstride < lmax_all + 1) return fail(CF_EINVAL, "lstride %d < lmax+1 = %d", lstride, lmax_all + 1);
+  const size_t ncl = (size_t)npoints * nprob * 6 * lstride;
+  if (mem == CF_MEM_HOST) {
+    if (!finite_all(cl_points, (int64_t)ncl)) return fail(CF_EINVAL, "non-finite scan spectra");
+    for (int p = 0; p < nprob; ++p)
+      if (!finite_all(maps[p], (int64_t)nmaps * H[p].n)) return fail(CF_EINVAL, "non-finite map value");
+  }
+  CallCtx c;
+  if (int st = c.begin(ex)) return st;
+  // batch of points factorised together, sized by the largest problem
+  int nmax = 0;
+  for (int p = 0; p < nprob; ++p) nmax = H[p].n > nmax ? H[p].n : nmax;
+  const size_t per = (size_t)nmax * nmax * 8;
+  int Bt = (int)std::min<size_t>(16, std::max<size_t>(1, (size_t(6) << 30) / per));
+  if (Bt > npoints) Bt = npoints;
+  const int L = lmax_all + 1;
+  Sizer z;
+  for (int p = 0; p < nprob; ++p) size_staging(z, &probs[p], H[p]);
+  if (mem == CF_MEM_HOST) {
+    z.add<double>(ncl);
+    for (int p = 0; p < nprob; ++p) z.add<double>((size_t)nmaps * H[p].n);
+    z.add<double>((size_t)npoints * nprob * nmaps * 2 + (size_t)npoints * nprob);
+  }
+  z.add<double>((size_t)Bt * 6 * L);                   // cw per point
+  z.add<double>((size_t)Bt * nmax * nmax);             // C batch
+  z.add<double>((size_t)Bt * nmax);                    // dinv
+  z.add<double>((size_t)Bt * ((nmax + kNB - 1) / kNB)); // logdet parts
+  z.add<double>((size_t)nmax * nmaps);                 // D
+  z.add<double>((size_t)Bt * nmax * nmaps);            // Y copies
+  z.add<double>((size_t)Bt * nmax * nmaps);            // G
+  z.add<double>((size_t)Bt * nmaps);                   // chi2 batch
+  z.add<double>((size_t)Bt);                           // logdet batch
+  z.add<int>(8);
+  if (int st = ensure_ws(*c.dev, z.off)) return st;
+  Bump bp(c.dev->ws);
+  std::vector<Staged> S(nprob);
+  for (int p = 0; p < nprob; ++p)
+    if (int st = stage(bp, &probs[p], H[p], nullptr, c.s, S[p])) return st;
+  const double* cl_dev = cl_points;
+  std::vector<const double*> map_dev(maps, maps + nprob);
+  double *m2_dev = m2lnL, *chi2_dev = chi2, *ld_dev = logdet;
+  if (mem == CF_MEM_HOST) {
+    double* t = bp.take<double>(ncl);
+    CF_DEV(hipMemcpyAsync(t, cl_points, sizeof(double) * ncl, hipMemcpyHostToDevice, c.s));
+    cl_dev = t;
+    for (int p = 0; p < nprob; ++p) {
+      double* m = bp.take<double>((size_t)nmaps * H[p].n);
+      CF_DEV(hipMemcpyAsync(m, maps[p], sizeof(double) * nmaps * H[p].n, hipMemcpyHostToDevice, c.s));
+      map_dev[p] = m;
+    }
+    double* o = bp.take<double>((size_t)npoints * nprob * nmaps * 2 + (size_t)npoints * nprob);
+    m2_dev = o;
+    chi2_dev = chi2 ? o + (size_t)npoints * nprob * nmaps : nullptr;
+    ld_dev = logdet ? o + (size_t)npoints * nprob * nmaps * 2 : nullptr;
+  }
+  double* cwb = bp.take<double>((size_t)Bt * 6 * L);
+  double* Cb = bp.take<double>((size_t)Bt * nmax * nmax);
+  double* dinv = bp.take<double>((size_t)Bt * nmax);
+  double* ldp = bp.take<double>((size_t)Bt * ((nmax + kNB - 1) / kNB));
+  double* D = bp.take<double>((size_t)nmax * nmaps);
+  double* Yb = bp.take<double>((size_t)Bt * nmax * nmaps);
+  double* Gb = bp.take<double>((size_t)Bt * nmax * nmaps);
+  double* x2 = bp.take<double>((size_t)Bt * nmaps);
+  double* ldb = bp.take<double>((size_t)Bt);
+  int* flags = bp.take<int>(8);
+  CF_DEV(launch_fill_int(flags, 1, 0, c.s));
+  CF_DEV(launch_fill_int(flags + 1, 1, INT_MAX, c.s));
+  Timer tm;
+  tm.begin(ex && ex->stage_timing, c.s);
+  double flops = 0.0;
+  for (int p = 0; p < nprob; ++p) {
+    const HostProblem& h = H[p];
+    const int64_t n = h.n;
+    const int Lp = h.lmax + 1;
+    const int64_t nblk = (n + kNB - 1) / kNB;
+    CF_DEV(launch_transpose(map_dev[p], nmaps, n, n, D, nmaps, c.s));
+    for (int64_t i0 = 0; i0 < npoints; i0 += Bt) {
+      const int b = (int)std::min<int64_t>(Bt, npoints - i0);
+      // a2: per-point weights c^XY_l
+      CF_DEV(launch_tables(cl_dev + (i0 * nprob + p) * 6 * (int64_t)lstride, S[p].bl, S[p].pl, h.lmin,
+                           h.lmax, b, (int64_t)nprob * 6 * lstride, lstride, cwb, nullptr, nullptr,
+                           nullptr, c.s));
+      // a3: covariance of every point in the batch (lower triangle)
+      CF_DEV(launch_cov_build(S[p].P, cwb, 6 * (int64_t)Lp, b, probs[p].noise_kind, S[p].noise,
+                              probs[p].noise_rank, S[p].noise_U, Cb, n, n * n, 1, flags, c.s));
+      tm.mark(ST_BUILD);
+      // a4: Cholesky and log det
+      CF_DEV(potrf_f64(Cb, n, n, n * n, b, dinv, n, ldp, nblk, flags + 1, c.s));
+      tm.mark(ST_POTRF);
+      // a6: u = L^-1 d for every map, chi^2 = |u|^2
+      for (int j = 0; j < b; ++j)
+        CF_DEV(hipMemcpyAsync(Yb + (size_t)j * n * nmaps, D, sizeof(double) * n * nmaps,
+                              hipMemcpyDeviceToDevice, c.s));
+      CF_DEV(trsm_lower_f64(Cb, n, n, n * n, dinv, n, Yb, nmaps, n * nmaps, Gb, nmaps, n * nmaps, nmaps,
+                            0, b, c.s));
+      CF_DEV(launch_colsumsq(Gb, n, nmaps, nmaps, n * nmaps, b, x2, nmaps, c.s));
+      CF_DEV(launch_sum_parts(ldp, (int)nblk, nblk, b, ldb, 1, c.s));
+      CF_DEV(launch_scan_finish(x2, ldb, b, nmaps, i0, p, nprob, m2_dev, chi2_dev, ld_dev, c.s));
+      tm.mark(ST_TRSM);
+    }
+    const double nd = (double)n;
+    flops += (double)npoints * (nd * nd * nd / 3.0 + nd * nd * nmaps);
+  }
+  int fl[2];
+  if (int st = read_flags(c, flags, 2, fl)) return st;
+  if (fl[0]) return fail(CF_EINVAL, "non-finite covariance entry (check noise and scan spectra)");
+  if (fl[1] != INT_MAX) {
+    if (rep) rep->fail_index = fl[1];
+    return fail(CF_ENOTPD, "a scan covariance is not positive definite (pivot %d)", fl[1]);
+  }
+  if (mem == CF_MEM_HOST) {
+    const size_t no = (size_t)npoints * nprob * nmaps;
+    if (int st = copy_out(m2lnL, m2_dev, no, CF_MEM_HOST, c.s)) return st;
+    if (chi2) if (int st = copy_out(chi2, chi2_dev, no, CF_MEM_HOST, c.s)) return st;
+    if (logdet) if (int st = copy_out(logdet, ld_dev, (size_t)npoints * nprob, CF_MEM_HOST, c.s)) return st;
+  }
+  CF_DEV(hipStreamSynchronize(c.s));
+  tm.finish(rep);
+  if (rep) { rep->flops = flops; rep->n = H[0].n; }
+  return CF_OK;
+}

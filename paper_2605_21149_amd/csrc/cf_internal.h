@@ -1,0 +1,126 @@
+// Internal declarations of libcf (host launchers and shared device helpers).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace cf {
+
+// -------------------------------------------------------------------------------------------
+// Launch-time error plumbing: launchers return hipError_t; the API layer converts to cf_status.
+// -------------------------------------------------------------------------------------------
+#define CF_HIP_TRY(expr)                                  \
+  do {                                                    \
+    hipError_t _e = (expr);                               \
+    if (_e != hipSuccess) return _e;                      \
+  } while (0)
+
+constexpr int kMaxL = 1024;          // lmax bound of the ABI
+constexpr int kNB = 64;              // diagonal block of the blocked Cholesky / triangular solves
+constexpr int kPixRec = 10;          // doubles per pixel record: n(3), e_theta(3), e_phi(2), z, phi
+constexpr int kCoef = 8;             // doubles per multipole of the recurrence table
+
+// Per-multipole recurrence coefficients (table [lmax+1][kCoef]):
+//   0: aP, 1: gP            P_{l+1}   = aP mu P_l - gP P_{l-1}
+//   2: a2, 3: b2, 4: g2     d_{2,+-2}^{l+1} = (a2 mu -+ b2) d^l - g2 d^{l-1}
+//   5: a0, 6: g0            d_{20}^{l+1}  = a0 mu d^l - g0 d^{l-1}
+//   7: sqrt((2l+1)/(4 pi))
+
+// Device-side problem geometry / weights.
+struct DevProblem {
+  int npx;            // retained pixels
+  int nmaps;          // 1 (T), 2 (QU) or 3 (TQU)
+  int has_t, has_p;   // T present, Q/U present
+  int n;              // nmaps * npx
+  int lmin, lmax;
+  int kf;             // modes per harmonic field: (lmax+1)^2 - lmin^2
+  int nfm;            // harmonic fields: 1 (T), 2 (E,B), 3 (T,E,B)
+  int64_t k;          // total modes nfm * kf
+  const double* pix;  // [npx][kPixRec]
+  const double* coef; // [lmax+1][kCoef]
+  const double* cw;   // [6][lmax+1] c^XY_l = (2l+1)/(4pi) C^XY_l W_l (zero below lmin)
+  const double* wl;   // [lmax+1] W_l
+  const double* lam;  // [6][lmax+1] C^XY_l W_l (mode covariance)
+};
+
+// ---------------------------------------------------------------- geometry / tables
+hipError_t launch_geometry(const int* ring_idx, int nside, const double* theta, const double* phi,
+                           int npx, double* pix, hipStream_t s);
+// Items (scan points) i < nitems: spectra at cl + i*cl_stride, row x at + x*cl_ld.
+// Outputs cw, lam: [nitems][6][lmax+1]; wl, coef: item 0 only (nullable).
+hipError_t launch_tables(const double* cl, const double* bl, const double* pl, int lmin, int lmax,
+                         int nitems, int64_t cl_stride, int64_t cl_ld, double* cw, double* wl,
+                         double* lam, double* coef, hipStream_t s);
+
+// ---------------------------------------------------------------- covariance assembly
+// C (n x n, ld) = S + N for a batch: cw/C advance by cw_stride / c_stride per batch item.
+// lower_only: write only entries on or below the diagonal.  noise_kind 0 diag [n], 1 dense [n][n].
+hipError_t launch_cov_build(const DevProblem& P, const double* cw, int64_t cw_stride, int nbatch,
+                            int noise_kind, const double* noise, int noise_rank,
+                            const double* noise_U, double* C, int64_t ldc, int64_t c_stride,
+                            int lower_only, int* flag, hipStream_t s);
+
+// ---------------------------------------------------------------- dense FP64 kernels
+struct GemmDesc {
+  int64_t M, N, K;
+  const double* A; int64_t lda; int at;   // at: A(i,k) = A[k*lda+i] else A[i*lda+k]
+  const double* B; int64_t ldb; int bt;   // bt: B(k,j) = B[j*ldb+k] else B[k*ldb+j]
+  double* C; int64_t ldc;
+  double alpha, beta;
+  int lower;                              // skip output tiles strictly above the diagonal
+  int batch; int64_t sA, sB, sC;          // batch count and element strides
+};
+hipError_t gemm_f64(const GemmDesc& g, hipStream_t s);
+
+// Cholesky of the n x n lower triangle (row-major, ld) in place, batched with stride.
+// dinv[n] receives 1/L_ii, ldpart[nblocks] the per-block sums of ln L_ii, fail the first
+// non-positive pivot (atomicMin; initialise to INT_MAX).
+hipError_t potrf_f64(double* A, int64_t n, int64_t lda, int64_t sA, int batch, double* dinv,
+                     int64_t sD, double* ldpart, int64_t sL, int* fail, hipStream_t s);
+
+// Forward substitution B <- L^-1 B for rows [r0, n) of B (n x ncol, ldb), L from potrf_f64;
+// rows below r0 of B are taken as zero.  Y is consumed (used as workspace); result goes to G.
+hipError_t trsm_lower_f64(const double* L, int64_t n, int64_t ldl, int64_t sL, const double* dinv,
+                          int64_t sD, double* Y, int64_t ldy, int64_t sY, double* G, int64_t ldg,
+                          int64_t sG, int64_t ncol, int64_t r0, int batch, hipStream_t s);
+
+// ---------------------------------------------------------------- harmonic basis
+hipError_t launch_ybuild(const DevProblem& P, double* Y, int64_t ldy, hipStream_t s);
+
+// ---------------------------------------------------------------- Fisher / QML reductions
+hipError_t launch_symmetrize(double* Z, int64_t k, int64_t ldz, hipStream_t s);
+// Gram[l][l'][p][q] for l >= l' (p, q over the nfm^2 field pairs, upper-triangular q >= p).
+hipError_t launch_gram(const DevProblem& P, const double* Z, int64_t ldz, double* gram,
+                       double* ztr, hipStream_t s);
+struct SpecSel {
+  int ns;            // selected spectra
+  int spec[6];       // spectrum ids (0..5 TT,EE,BB,TE,TB,EB)
+  int nb;            // bins
+  const int* lo;     // device [nb]
+  const int* hi;     // device [nb]
+};
+hipError_t launch_fisher_assemble(const DevProblem& P, const SpecSel& S, const double* gram,
+                                  double* F, hipStream_t s);
+hipError_t launch_bias_assemble(const DevProblem& P, const SpecSel& S, const double* gram,
+                                const double* ztr, double* bias, hipStream_t s);
+hipError_t launch_quad_assemble(const DevProblem& P, const SpecSel& S, const double* w, int64_t ldw,
+                                int nmaps, double* y, hipStream_t s);
+// Cholesky solve of the small SPD system F X = R (k x k, nrhs columns given as rows [nrhs][k]).
+hipError_t launch_small_spd_solve(double* F, int k, const double* R, double* X, int nrhs, int* fail,
+                                  hipStream_t s);
+hipError_t launch_transpose(const double* A, int64_t rows, int64_t cols, int64_t lda, double* B,
+                            int64_t ldb, hipStream_t s);
+hipError_t launch_colsumsq(const double* U, int64_t rows, int64_t cols, int64_t ldu, int64_t sU,
+                           int batch, double* out, int64_t sOut, hipStream_t s);
+hipError_t launch_sum_parts(const double* parts, int nparts, int64_t sP, int batch, double* out,
+                            int64_t sOut, hipStream_t s);
+hipError_t launch_add_scalar(const double* vec, int64_t nper, int batch, const double* scal,
+                             double* out, hipStream_t s);
+hipError_t launch_sub_bias(double* q, const double* bias, int K, int nmaps, hipStream_t s);
+hipError_t launch_scan_finish(const double* chi2b, const double* ldb, int B, int nmaps, int64_t i0,
+                              int prob, int nprob, double* m2, double* chi2, double* logdet,
+                              hipStream_t s);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s);
+
+}  // namespace cf

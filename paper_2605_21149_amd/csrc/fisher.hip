@@ -1,0 +1,458 @@
+// Fisher matrix, noise bias and QML quadratic forms from Z = Y^T C^-1 Y (paper Eqs. fisher_harmonic,
+// sparse_trace, q_harmonic; App. C.1), plus the small dense helpers of the path.
+//
+// Z is ordered [field][l][m].  For every multipole pair (l >= l') one workgroup forms the Gram
+// matrix of the field blocks Z^{ad}_{ll'} (rows: field a at l, columns: field d at l'):
+//   gram[(a,d),(b,c)] = <Z^{ad}_{ll'}, Z^{bc}_{ll'}>_F ,
+// which is all the sparse trace of Eq. sparse_trace needs: for spectra XY, X'Y' with field-pair
+// sets sigma(XX) = {(X,X)}, sigma(XY) = {(X,Y),(Y,X)},
+//   F = 1/2 sum_{l in b, l' in b'} W_l W_l' sum_{(a,c) in sigma} sum_{(a',c') in sigma'} gram_{ll'}[(c,a'),(a,c')].
+// The same Gram entries give the noise bias through 1/2 tr[E_b (Z - Z Lambda Z)]:
+//   b = 1/2 sum_{l in b} W_l sum_{(a,c)} ( tr Z^{ca}_{ll} - sum_{l'} sum_{f,g} Lambda_l'[f,g] gram_{ll'}[(c,f),(a,g)] ).
+#include "cf_internal.h"
+#include <climits>
+
+namespace cf {
+namespace {
+
+__device__ __forceinline__ int qidx(int p1, int p2, int np) {   // p1 <= p2
+  return p1 * (2 * np - p1 + 1) / 2 + (p2 - p1);
+}
+
+// Z lower triangle -> full symmetric, through 32 x 32 LDS tiles.
+__global__ __launch_bounds__(256) void k_symmetrize(double* Z, int64_t k, int64_t ldz) {
+  __shared__ double t[32][33];
+  const int64_t bi = blockIdx.y, bj = blockIdx.x;   // source tile (bi, bj) with bi > bj, lower
+  if (bj >= bi) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    int64_t gr = bi * 32 + r, gc = bj * 32 + tx;
+    t[r][tx] = (gr < k && gc < k) ? Z[gr * ldz + gc] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    int64_t gr = bj * 32 + r, gc = bi * 32 + tx;     // transposed destination (upper)
+    if (gr < k && gc < k) Z[gr * ldz + gc] = t[tx][r];
+  }
+}
+// diagonal 32 x 32 tiles: copy lower to upper in place
+__global__ __launch_bounds__(256) void k_symmetrize_diag(double* Z, int64_t k, int64_t ldz) {
+  const int64_t b = blockIdx.x;
+  for (int idx = threadIdx.x; idx < 32 * 32; idx += 256) {
+    int r = idx / 32, c = idx % 32;
+    int64_t gr = b * 32 + r, gc = b * 32 + c;
+    if (c > r && gr < k && gc < k) Z[gr * ldz + gc] = Z[gc * ldz + gr];
+  }
+}
+
+template <int NF>
+__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ Z, int64_t ldz, int lmin,
+                                              int lmax, int kf, double* __restrict__ gram,
+                                              double* __restrict__ ztr) {
+  constexpr int NP = NF * NF, NQ = NP * (NP + 1) / 2;
+  __shared__ double red[NQ > NP ? NQ : NP][257];
+  const int pid = blockIdx.x;
+  // pid -> (li >= lj)
+  int li = (int)((sqrt(8.0 * pid + 1.0) - 1.0) * 0.5);
+  while (li * (li + 1) / 2 > pid) --li;
+  while ((li + 1) * (li + 2) / 2 <= pid) ++li;
+  const int lj = pid - li * (li + 1) / 2;
+  const int l = lmin + li, lp = lmin + lj;
+  const int nm = 2 * l + 1, nmp = 2 * lp + 1;
+  const int64_t rb = (int64_t)l * l - (int64_t)lmin * lmin;
+  const int64_t cb = (int64_t)lp * lp - (int64_t)lmin * lmin;
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  const int tot = nm * nmp;
+  for (int e = threadIdx.x; e < tot; e += 256) {
+    const int m = e / nmp, mp = e % nmp;
+    double z[NP];
+#pragma unroll
+    for (int a = 0; a < NF; ++a)
+#pragma unroll
+      for (int d = 0; d < NF; ++d)
+        z[a * NF + d] = Z[((int64_t)a * kf + rb + m) * ldz + (int64_t)d * kf + cb + mp];
+    int q = 0;
+#pragma unroll
+    for (int p1 = 0; p1 < NP; ++p1)
+#pragma unroll
+      for (int p2 = p1; p2 < NP; ++p2) { acc[q] = fma(z[p1], z[p2], acc[q]); ++q; }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) red[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int q = threadIdx.x; q < NQ; q += 256) {
+    double s = 0.0;
+    for (int t = 0; t < 256; ++t) s += red[q][t];
+    gram[(int64_t)pid * NQ + q] = s;
+  }
+  if (li == lj) {
+    __syncthreads();
+    double tr[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) tr[p] = 0.0;
+    for (int m = threadIdx.x; m < nm; m += 256) {
+#pragma unroll
+      for (int a = 0; a < NF; ++a)
+#pragma unroll
+        for (int d = 0; d < NF; ++d)
+          tr[a * NF + d] += Z[((int64_t)a * kf + rb + m) * ldz + (int64_t)d * kf + rb + m];
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) red[p][threadIdx.x] = tr[p];
+    __syncthreads();
+    for (int p = threadIdx.x; p < NP; p += 256) {
+      double s = 0.0;
+      for (int t = 0; t < 256; ++t) s += red[p][t];
+      ztr[(int64_t)li * NP + p] = s;
+    }
+  }
+}
+
+// spectrum id (0..5 = TT,EE,BB,TE,TB,EB) -> its absolute field letters (0 T, 1 E, 2 B)
+__device__ __forceinline__ void spec_fields(int s, int& x, int& y) {
+  const int X[6] = {0, 1, 2, 0, 0, 1}, Yv[6] = {0, 1, 2, 1, 2, 2};
+  x = X[s]; y = Yv[s];
+}
+__device__ __forceinline__ int field_pair_spec(int f, int g) {   // absolute letters -> spectrum id
+  const int tab[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+  return tab[f][g];
+}
+
+struct GramView {
+  const double* gram;
+  int lmin, nf, np, nq;
+  int off;        // absolute letter -> harmonic field index: idx = letter - off (QU: E->0, B->1)
+  __device__ double get(int l, int lp, int x, int y, int u, int v) const {
+    // <Z^{xy}_{l l'}, Z^{uv}_{l l'}> with fields as harmonic indices
+    int li = l - lmin, lj = lp - lmin;
+    int p1, p2;
+    if (li >= lj) { p1 = x * nf + y; p2 = u * nf + v; }
+    else { int t = li; li = lj; lj = t; p1 = y * nf + x; p2 = v * nf + u; }
+    if (p1 > p2) { int t = p1; p1 = p2; p2 = t; }
+    int64_t pid = (int64_t)li * (li + 1) / 2 + lj;
+    return gram[pid * nq + qidx(p1, p2, np)];
+  }
+};
+
+__global__ void k_fisher_assemble(GramView G, int ns, int s0, int s1, int s2, int s3, int s4, int s5,
+                                  int nb, const int* lo, const int* hi, const double* wl, double* F) {
+  const int K = ns * nb;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= K * K) return;
+  const int A = idx / K, B = idx % K;
+  const int specs[6] = {s0, s1, s2, s3, s4, s5};
+  const int sa = specs[A / nb], ba = A % nb, sb = specs[B / nb], bb = B % nb;
+  int xa, ya, xb, yb;
+  spec_fields(sa, xa, ya);
+  spec_fields(sb, xb, yb);
+  xa -= G.off; ya -= G.off; xb -= G.off; yb -= G.off;
+  const int npa = (xa == ya) ? 1 : 2, npb = (xb == yb) ? 1 : 2;
+  double sum = 0.0;
+  for (int l = lo[ba]; l <= hi[ba]; ++l) {
+    for (int lp = lo[bb]; lp <= hi[bb]; ++lp) {
+      double t = 0.0;
+      for (int u = 0; u < npa; ++u) {
+        const int a = u ? ya : xa, c = u ? xa : ya;
+        for (int v = 0; v < npb; ++v) {
+          const int a2 = v ? yb : xb, c2 = v ? xb : yb;
+          t += G.get(l, lp, c, a2, a, c2);
+        }
+      }
+      sum = fma(wl[l] * wl[lp], t, sum);
+    }
+  }
+  F[idx] = 0.5 * sum;
+}
+
+__global__ void k_bias_assemble(GramView G, const double* ztr, int lmin, int lmax, int ns, int s0,
+                                int s1, int s2, int s3, int s4, int s5, int nb, const int* lo,
+                                const int* hi, const double* wl, const double* lam, double* bias) {
+  const int K = ns * nb;
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= K) return;
+  const int specs[6] = {s0, s1, s2, s3, s4, s5};
+  const int sa = specs[A / nb], ba = A % nb;
+  int xa, ya;
+  spec_fields(sa, xa, ya);
+  const int L = lmax + 1;
+  const int nf = G.nf;
+  const int npa = (xa == ya) ? 1 : 2;
+  double sum = 0.0;
+  for (int l = lo[ba]; l <= hi[ba]; ++l) {
+    double t = 0.0;
+    for (int u = 0; u < npa; ++u) {
+      const int a = (u ? ya : xa) - G.off, c = (u ? xa : ya) - G.off;
+      t += ztr[(l - lmin) * nf * nf + c * nf + a];
+      for (int lp = lmin; lp <= lmax; ++lp) {
+        for (int f = 0; f < nf; ++f)
+          for (int g = 0; g < nf; ++g) {
+            const double lv = lam[field_pair_spec(f + G.off, g + G.off) * L + lp];
+            if (lv != 0.0) t -= lv * G.get(l, lp, c, f, a, g);
+          }
+      }
+    }
+    sum = fma(wl[l], t, sum);
+  }
+  bias[A] = 0.5 * sum;
+}
+
+// y[map][A] = 1/2 sum_{l in b} W_l sum_{(a,c) in sigma} sum_m w[a,l,m] w[c,l,m];  w is [k][ldw].
+__global__ void k_quad_assemble(const double* w, int64_t ldw, int nmaps, int lmin, int kf, int off,
+                                int ns, int s0, int s1, int s2, int s3, int s4, int s5, int nb,
+                                const int* lo, const int* hi, const double* wl, double* y) {
+  const int K = ns * nb;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= K * nmaps) return;
+  const int map = idx / K, A = idx % K;
+  const int specs[6] = {s0, s1, s2, s3, s4, s5};
+  const int sa = specs[A / nb], ba = A % nb;
+  int xa, ya;
+  spec_fields(sa, xa, ya);
+  xa -= off; ya -= off;
+  double sum = 0.0;
+  for (int l = lo[ba]; l <= hi[ba]; ++l) {
+    const int64_t base = (int64_t)l * l - (int64_t)lmin * lmin;
+    double t = 0.0;
+    for (int m = 0; m < 2 * l + 1; ++m) {
+      const double wa = w[((int64_t)xa * kf + base + m) * ldw + map];
+      const double wc = w[((int64_t)ya * kf + base + m) * ldw + map];
+      t = fma(wa, wc, t);
+    }
+    if (xa != ya) t *= 2.0;
+    sum = fma(wl[l], t, sum);
+  }
+  y[(int64_t)map * K + A] = 0.5 * sum;
+}
+
+// Single-workgroup Cholesky solve of a small SPD system: F (k x k, overwritten with its factor),
+// right-hand sides R [nrhs][k] -> X [nrhs][k].
+__global__ __launch_bounds__(1024) void k_small_spd_solve(double* F, int k, const double* R, double* X,
+                                                          int nrhs, int* fail) {
+  const int tid = threadIdx.x;
+  for (int j = 0; j < k; ++j) {
+    const double d = F[j * k + j];
+    const int m = k - j - 1;
+    if (m > 0) {
+      const double inv = 1.0 / d;
+      for (int idx = tid; idx < m * m; idx += blockDim.x) {
+        int r = j + 1 + idx / m, q = j + 1 + idx % m;
+        if (q <= r) F[r * k + q] -= F[r * k + j] * F[q * k + j] * inv;
+      }
+    }
+    __syncthreads();
+  }
+  // scale: L[r][q] = a[r][q] / sqrt(a[q][q]) (a[q][q] are the pivots)
+  for (int idx = tid; idx < k * k; idx += blockDim.x) {
+    int r = idx / k, q = idx % k;
+    if (q < r) F[r * k + q] /= sqrt(F[q * k + q]);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int j = 0; j < k; ++j) {
+      double d = F[j * k + j];
+      if (!(d > 0.0) || !isfinite(d)) { atomicMin(fail, j); break; }
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < k; idx += blockDim.x) F[idx * k + idx] = sqrt(F[idx * k + idx]);
+  __syncthreads();
+  for (int r = tid; r < nrhs; r += blockDim.x) {
+    const double* b = R + (int64_t)r * k;
+    double* x = X + (int64_t)r * k;
+    for (int i = 0; i < k; ++i) {          // L y = b
+      double s = b[i];
+      for (int q = 0; q < i; ++q) s -= F[i * k + q] * x[q];
+      x[i] = s / F[i * k + i];
+    }
+    for (int i = k - 1; i >= 0; --i) {     // L^T x = y
+      double s = x[i];
+      for (int q = i + 1; q < k; ++q) s -= F[q * k + i] * x[q];
+      x[i] = s / F[i * k + i];
+    }
+  }
+}
+
+__global__ void k_transpose(const double* A, int64_t rows, int64_t cols, int64_t lda, double* B,
+                            int64_t ldb) {
+  __shared__ double t[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  for (int r = ty; r < 32; r += 8)
+    t[r][tx] = (r0 + r < rows && c0 + tx < cols) ? A[(r0 + r) * lda + c0 + tx] : 0.0;
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8)
+    if (c0 + r < cols && r0 + tx < rows) B[(c0 + r) * ldb + r0 + tx] = t[tx][r];
+}
+
+// out[b][j] = sum_i U[b][i][j]^2 (fixed summation order)
+__global__ void k_colsumsq(const double* U, int64_t rows, int64_t cols, int64_t ldu, int64_t sU,
+                           double* out, int64_t sOut) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  const double* u = U + blockIdx.z * sU + j;
+  double s = 0.0;
+  for (int64_t i = 0; i < rows; ++i) { double v = u[i * ldu]; s = fma(v, v, s); }
+  out[blockIdx.z * sOut + j] = s;
+}
+
+__global__ void k_sum_parts(const double* parts, int nparts, int64_t sP, double* out, int64_t sOut) {
+  if (threadIdx.x != 0) return;
+  const double* p = parts + blockIdx.x * sP;
+  double s = 0.0;
+  for (int i = 0; i < nparts; ++i) s += p[i];
+  out[blockIdx.x * sOut] = 2.0 * s;
+}
+
+__global__ void k_add_scalar(const double* vec, int64_t nper, const double* scal, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nper) return;
+  out[blockIdx.y * nper + i] = vec[blockIdx.y * nper + i] + scal[blockIdx.y];
+}
+
+__global__ void k_sub_bias(double* q, const double* bias, int K, int nmaps) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < K * nmaps) q[i] -= bias[i % K];
+}
+
+// Scatter a batch of per-point chi^2 [B][nmaps] and ln|C| [B] into the scan outputs
+// [npoints][nprob][nmaps] (m2lnL, chi2) and [npoints][nprob] (logdet).
+__global__ void k_scan_finish(const double* chi2b, const double* ldb, int B, int nmaps, int64_t i0,
+                              int prob, int nprob, double* m2, double* chi2, double* logdet) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= B * nmaps) return;
+  const int b = idx / nmaps, j = idx % nmaps;
+  const int64_t row = (i0 + b) * nprob + prob;
+  const double x = chi2b[idx], l = ldb[b];
+  m2[row * nmaps + j] = x + l;
+  if (chi2) chi2[row * nmaps + j] = x;
+  if (logdet && j == 0) logdet[row] = l;
+}
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_int(int* p, int64_t n, int v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+GramView make_view(const DevProblem& P, const double* gram) {
+  GramView G;
+  G.gram = gram; G.lmin = P.lmin; G.nf = P.nfm; G.np = P.nfm * P.nfm;
+  G.nq = G.np * (G.np + 1) / 2;
+  G.off = P.has_t ? 0 : 1;   // QU only: E is harmonic field 0
+  return G;
+}
+
+}  // namespace
+
+hipError_t launch_symmetrize(double* Z, int64_t k, int64_t ldz, hipStream_t s) {
+  const int64_t nt = (k + 31) / 32;
+  hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)nt, (unsigned)nt), dim3(256), 0, s, Z, k, ldz);
+  CF_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_symmetrize_diag, dim3((unsigned)nt), dim3(256), 0, s, Z, k, ldz);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(const DevProblem& P, const double* Z, int64_t ldz, double* gram, double* ztr,
+                       hipStream_t s) {
+  const int nl = P.lmax - P.lmin + 1;
+  const unsigned npairs = (unsigned)(nl * (nl + 1) / 2);
+  switch (P.nfm) {
+    case 1: hipLaunchKernelGGL(k_gram<1>, dim3(npairs), dim3(256), 0, s, Z, ldz, P.lmin, P.lmax, P.kf, gram, ztr); break;
+    case 2: hipLaunchKernelGGL(k_gram<2>, dim3(npairs), dim3(256), 0, s, Z, ldz, P.lmin, P.lmax, P.kf, gram, ztr); break;
+    case 3: hipLaunchKernelGGL(k_gram<3>, dim3(npairs), dim3(256), 0, s, Z, ldz, P.lmin, P.lmax, P.kf, gram, ztr); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fisher_assemble(const DevProblem& P, const SpecSel& S, const double* gram,
+                                  double* F, hipStream_t s) {
+  const int K = S.ns * S.nb;
+  hipLaunchKernelGGL(k_fisher_assemble, dim3(blocks((int64_t)K * K, 128)), dim3(128), 0, s,
+                     make_view(P, gram), S.ns, S.spec[0], S.spec[1], S.spec[2], S.spec[3], S.spec[4],
+                     S.spec[5], S.nb, S.lo, S.hi, P.wl, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_bias_assemble(const DevProblem& P, const SpecSel& S, const double* gram,
+                                const double* ztr, double* bias, hipStream_t s) {
+  const int K = S.ns * S.nb;
+  hipLaunchKernelGGL(k_bias_assemble, dim3(blocks(K, 64)), dim3(64), 0, s, make_view(P, gram), ztr,
+                     P.lmin, P.lmax, S.ns, S.spec[0], S.spec[1], S.spec[2], S.spec[3], S.spec[4],
+                     S.spec[5], S.nb, S.lo, S.hi, P.wl, P.lam, bias);
+  return hipGetLastError();
+}
+
+hipError_t launch_quad_assemble(const DevProblem& P, const SpecSel& S, const double* w, int64_t ldw,
+                                int nmaps, double* y, hipStream_t s) {
+  const int K = S.ns * S.nb;
+  hipLaunchKernelGGL(k_quad_assemble, dim3(blocks((int64_t)K * nmaps, 128)), dim3(128), 0, s, w, ldw,
+                     nmaps, P.lmin, P.kf, P.has_t ? 0 : 1, S.ns, S.spec[0], S.spec[1], S.spec[2],
+                     S.spec[3], S.spec[4], S.spec[5], S.nb, S.lo, S.hi, P.wl, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_spd_solve(double* F, int k, const double* R, double* X, int nrhs, int* fail,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_small_spd_solve, dim3(1), dim3(1024), 0, s, F, k, R, X, nrhs, fail);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const double* A, int64_t rows, int64_t cols, int64_t lda, double* B,
+                            int64_t ldb, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose, dim3(blocks(cols, 32), blocks(rows, 32)), dim3(256), 0, s, A, rows,
+                     cols, lda, B, ldb);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsumsq(const double* U, int64_t rows, int64_t cols, int64_t ldu, int64_t sU,
+                           int batch, double* out, int64_t sOut, hipStream_t s) {
+  hipLaunchKernelGGL(k_colsumsq, dim3(blocks(cols, 64), 1, batch), dim3(64), 0, s, U, rows, cols, ldu,
+                     sU, out, sOut);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_parts(const double* parts, int nparts, int64_t sP, int batch, double* out,
+                            int64_t sOut, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_parts, dim3(batch), dim3(64), 0, s, parts, nparts, sP, out, sOut);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_scalar(const double* vec, int64_t nper, int batch, const double* scal,
+                             double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_scalar, dim3(blocks(nper, 64), batch), dim3(64), 0, s, vec, nper, scal, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_bias(double* q, const double* bias, int K, int nmaps, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_bias, dim3(blocks((int64_t)K * nmaps, 256)), dim3(256), 0, s, q, bias, K, nmaps);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_finish(const double* chi2b, const double* ldb, int B, int nmaps, int64_t i0,
+                              int prob, int nprob, double* m2, double* chi2, double* logdet,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_finish, dim3(blocks((int64_t)B * nmaps, 256)), dim3(256), 0, s, chi2b, ldb,
+                     B, nmaps, i0, prob, nprob, m2, chi2, logdet);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(blocks(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_int, dim3(blocks(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace cf

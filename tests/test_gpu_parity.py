@@ -1,0 +1,179 @@
+"""GPU parity: libcf's HIP path against the FP64 CPU oracle on the same seeded inputs.
+
+FP64 bar (the benchmark spec's tolerance): every metric <= 1e-10, relative / in units of the
+estimator's Fisher errors (see gpu_common).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import covariance as cv
+from oracle import healpix, likelihood, qml
+from paper_2605_21149_amd import cf
+from paper_2605_21149_amd import inputs as I
+
+from gpu_common import metric_C, metric_chat, metric_F, metric_vec_fisher, say, to_np
+from oracle_cases import gl_problem, tiny_healpix
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cf.lib()
+
+
+def _maps(p, C, nmaps, seed):
+    L = np.linalg.cholesky(C)
+    return (L @ np.random.default_rng(seed).standard_normal((p.n, nmaps))).T
+
+
+# ----------------------------------------------------------------------------------- C = S + N
+@pytest.mark.parametrize("fields", ["T", "QU", "TQU"])
+def test_cov_build_tiny_all_spectra(fields):
+    p = tiny_healpix(fields, nside=2, lmax=7, cut=-1.0, lowrank=3)   # full sky: antipodal pairs
+    say("cov_build tiny", fields, p.n)
+    ref = cv.total_covariance(p)
+    got = to_np(cf.cov_build(p, device=True))
+    assert got.shape == ref.shape
+    m = metric_C(got, ref)
+    say("  M_C", m)
+    assert m < TOL
+    assert np.array_equal(got, got.T)
+
+
+def test_cov_build_dense_noise_host_path():
+    p = tiny_healpix("TQU", nside=2, lmax=6, cut=0.3, lowrank=2)
+    p.noise_dense = p.noise_matrix()
+    say("cov_build host path", p.n)
+    got = cf.cov_build(p, device=False)
+    assert metric_C(got, cv.total_covariance(p)) < TOL
+
+
+def test_cov_build_spin0_nside8():
+    p = I.spin0_problem_nside8()
+    say("cov_build spin0 nside8", p.n)
+    m = metric_C(to_np(cf.cov_build(p, device=True)), cv.total_covariance(p))
+    say("  M_C", m)
+    assert m < TOL
+
+
+def test_cov_build_tqu_nside16_sampled_rows():
+    """Full-size TQU N_side 16 (n = 5952): sampled pixel rows against the oracle's pair route."""
+    p = I.tqu_problem_nside16(dense_noise=True)
+    say("cov_build tqu nside16", p.n)
+    got = to_np(cf.cov_build(p, device=True))
+    th, ph = healpix.active_directions(p.nside, p.mask)
+    rows = np.array([0, 1, 17, 500, 991, 992, 1500, 1983])
+    S = cv.signal_pairs(th, ph, "TQU", p.cl, p.bl, p.pl, p.lmin, p.lmax, rows=rows)
+    npx = p.npix
+    ridx = np.concatenate([rows + a * npx for a in range(3)])
+    ref = S + p.noise_dense[ridx]
+    d = np.sqrt(np.diag(got))
+    m = float(np.max(np.abs(got[ridx] - ref) / np.outer(d[ridx], d)))
+    say("  M_C sampled", m)
+    assert m < TOL
+    assert np.array_equal(got, got.T)
+
+
+# ----------------------------------------------------------------------------------- Fisher / QML
+def _qml_case(p, spectra, lo, hi, nmaps=2, seed=5):
+    C = cv.total_covariance(p)
+    maps = _maps(p, C, nmaps, seed)
+    ref = qml.qml_harmonic(p, spectra, lo, hi, maps, C)
+    bins = I.Bins(np.asarray(lo, np.int32), np.asarray(hi, np.int32), tuple(spectra))
+    got = cf.qml(p, bins, maps, device=True)
+    got = {k: to_np(v) for k, v in got.items()}
+    F = ref["F"]
+    res = {"F": metric_F(got["F"], F), "y": metric_vec_fisher(got["y"], ref["y"], F),
+           "bias": metric_vec_fisher(got["bias"], ref["bias"], F),
+           "chat": metric_chat(got["chat"], ref["chat"], F)}
+    return res, got, ref
+
+
+@pytest.mark.parametrize("fields", ["T", "QU", "TQU"])
+def test_qml_tiny_masked(fields):
+    p = tiny_healpix(fields, nside=4, lmax=9, cut=0.25, lowrank=2)
+    spectra = I.spectra_for_fields(fields)
+    lo = np.array([2, 4, 5, 8]); hi = np.array([3, 4, 7, 9])
+    say("qml tiny", fields, p.n)
+    res, got, ref = _qml_case(p, spectra, lo, hi)
+    say("  metrics", res)
+    assert max(res.values()) < TOL
+    np.testing.assert_allclose(got["F"], got["F"].T, rtol=0, atol=1e-14 * np.max(np.abs(got["F"])))
+
+
+def test_fisher_spin0_nside8_unbinned():
+    """The spin-0 N_side 8 workload: unbinned TT Fisher, l in [2, 24], one seeded map."""
+    p = I.spin0_problem_nside8()
+    lo = np.arange(2, 25)
+    say("qml spin0 nside8", p.n)
+    res, got, ref = _qml_case(p, ("TT",), lo, lo, nmaps=1, seed=101)
+    say("  metrics", res)
+    assert max(res.values()) < TOL
+
+
+def test_fisher_gl_closed_form_on_gpu():
+    """Exact-quadrature full-sky grid given as explicit directions: the GPU Fisher equals
+    (2l+1)/2 W^2/(W C + nu)^2 (TT) and is zero off the l-diagonal."""
+    lmax, nu = 8, 0.3
+    p = gl_problem("T", lmax, nu, beam_fwhm=1200.0)
+    lo = np.arange(2, lmax + 1)
+    say("fisher GL closed form", p.n)
+    F = to_np(cf.fisher(p, I.Bins(lo.astype(np.int32), lo.astype(np.int32), ("TT",)), device=True))
+    W = cv.window(p.bl, p.pl)[2:]
+    ref = (2 * lo + 1) / 2 * W ** 2 / (W * p.cl[0, 2:] + nu) ** 2
+    np.testing.assert_allclose(np.diag(F), ref, rtol=1e-10)
+    off = F - np.diag(np.diag(F))
+    assert np.max(np.abs(off)) < 1e-10 * np.max(ref)
+
+
+# ----------------------------------------------------------------------------------- likelihood
+def test_loglike_batch_small():
+    p = tiny_healpix("QU", nside=4, lmax=9, cut=0.25, lowrank=2)
+    C = cv.total_covariance(p)
+    maps = _maps(p, C, 3, 17)
+    pts = I.scan_points(5, seed=3)
+    clp = I.scan_spectra(pts, p.cl)[:, None]            # [npoints][1][6][L]
+    say("loglike tiny", p.n)
+    got = cf.loglike_batch([p], clp, [maps], device=True)
+    m2 = to_np(got["m2lnL"])[:, 0]
+    ld = to_np(got["logdet"])[:, 0]
+    ref_m2, ref_ld = likelihood.scan(p, maps, clp[:, 0])
+    say("  max rel", np.max(np.abs(m2 - ref_m2) / np.abs(ref_m2)))
+    np.testing.assert_allclose(m2, ref_m2, rtol=TOL)
+    np.testing.assert_allclose(ld, ref_ld, rtol=TOL)
+
+
+def test_loglike_two_uneven_problems():
+    """Two QU problems of different size in one call (the mixed N_side 8 / 16 scan, reduced)."""
+    pa = tiny_healpix("QU", nside=2, lmax=6, cut=0.2, lowrank=1)
+    pb = tiny_healpix("QU", nside=4, lmax=9, cut=0.3, lowrank=2)
+    maps = [_maps(pa, cv.total_covariance(pa), 2, 1), _maps(pb, cv.total_covariance(pb), 2, 2)]
+    pts = I.scan_points(4, seed=8)
+    L = pb.lmax + 1
+    clp = np.zeros((4, 2, 6, L))
+    clp[:, 0, :, :pa.lmax + 1] = I.scan_spectra(pts, pa.cl)
+    clp[:, 1] = I.scan_spectra(pts, pb.cl)
+    say("loglike two problems", pa.n, pb.n)
+    got = cf.loglike_batch([pa, pb], clp, maps, device=True)
+    m2 = to_np(got["m2lnL"])
+    for k, p in enumerate((pa, pb)):
+        ref, _ = likelihood.scan(p, maps[k], clp[:, k, :, :p.lmax + 1])
+        np.testing.assert_allclose(m2[:, k], ref, rtol=TOL)
+
+
+def test_not_positive_definite_reports_pivot():
+    p = tiny_healpix("T", nside=2, lmax=5, cut=-1.0)
+    p.noise_diag = p.noise_diag.copy()
+    p.noise_diag[:] = -50.0
+    say("ENOTPD case")
+    with pytest.raises(cf.CFError) as e:
+        cf.fisher(p, I.uniform_bins(2, 5, 1, ("TT",)), device=True)
+    assert e.value.status == cf.CF_ENOTPD
+    assert e.value.report["fail_index"] >= 0
