@@ -1,0 +1,162 @@
+"""Benchmark of the hot path on the TQU N_side = 16 workload (|b| > 20 deg mask, n = 5952,
+l in [2, 47], 6 spectra x 12 bins of width 4, dense N = 2 I + U U^T with 20 smooth modes).
+
+One step = one pass of the whole path on one batch of synthetic input:
+  Fisher + QML of one map (covariance assembly, Cholesky, harmonic basis, triangular solves,
+  Z = Y^T C^-1 Y, Fisher block reduction, y, noise bias, C_hat)
+  + the likelihood -2 ln L of SCAN_POINTS parameter points x 64 maps (per point: covariance
+    rebuild, Cholesky, log det, 64 triangular solves, chi^2).
+Inputs are resident in device memory before the timed region.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+SCAN_POINTS = 8
+NMAPS_SCAN = 64
+PEAK_FP64_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(problem, bins, cl_points, maps_qml, maps_scan):
+    """The CPU oracle timed on a bounded sample of one step: one covariance + factorisation +
+    Z + Fisher rows 0..5 of 72 + QML, and one likelihood point; extrapolated linearly to a full
+    step (72 Fisher rows, SCAN_POINTS likelihood points)."""
+    from oracle import covariance as cv, likelihood, qml
+    from threadpoolctl import threadpool_info
+    t0 = time.perf_counter()
+    C = cv.total_covariance(problem)
+    t_cov = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Z, Y, modes, fac = qml.projected_inverse(problem, C)
+    t_z = time.perf_counter() - t0
+    coo = qml.coo_derivatives(problem, modes, bins.spectra, bins.lo, bins.hi)
+    rows = 6
+    t0 = time.perf_counter()
+    qml.fisher_from_z(Z, coo[:rows])
+    t_f = (time.perf_counter() - t0) * (len(coo) / rows) ** 2
+    t0 = time.perf_counter()
+    w = (Y.T @ __import__("scipy.linalg", fromlist=["cho_solve"]).cho_solve(fac, maps_qml.T)).T
+    qml.quadratic_from_w(w, coo)
+    t_q = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    import copy
+    p1 = copy.copy(problem)
+    p1.cl = cl_points[0, 0]
+    C1 = cv.total_covariance(p1)
+    likelihood.chi2_logdet(C1, maps_scan)
+    t_pt = time.perf_counter() - t0
+    step = t_cov + t_z + t_f + t_q + SCAN_POINTS * t_pt
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": 1.0 / step, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"one Fisher+QML pass with Fisher rows 0-5 of 72 timed and scaled by 144, "
+                       f"one of {SCAN_POINTS} likelihood points timed and scaled; "
+                       f"measured {t_cov + t_z + t_f / 144 + t_q + t_pt:.1f} s, "
+                       f"extrapolated step {step:.1f} s (host BLAS threads {threads})")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              f"(multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2605_21149_amd import cf
+    from paper_2605_21149_amd import inputs as I
+
+    dev = torch.device("cuda:0")
+    problem = I.tqu_problem_nside16(dense_noise=True)
+    bins = I.uniform_bins(2, 47, 4, I.SPEC_NAMES)
+    n = problem.n
+    maps_qml = I.white_maps(n, 1, 202, rms=3.0)
+    maps_scan = I.white_maps(n, NMAPS_SCAN, 403, rms=3.0)
+    pts = I.scan_points(SCAN_POINTS, seed=401)
+    cl_points = I.scan_spectra(pts, problem.cl)[:, None]      # [P][1][6][48]
+    # device-resident inputs
+    packed = cf.pack_problem(problem, device=True)
+    d_maps_qml = torch.as_tensor(maps_qml).to(dev)
+    d_maps_scan = torch.as_tensor(maps_scan).to(dev)
+    d_cl = torch.as_tensor(np.ascontiguousarray(cl_points)).to(dev)
+    torch.cuda.synchronize()
+
+    def step(timing):
+        q, rq = cf.qml(problem, bins, d_maps_qml, device=True, stage_timing=timing, report=True,
+                       packed=packed)
+        s, rs = cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True, stage_timing=timing,
+                                 report=True, packed=[packed])
+        return rq, rs
+
+    for _ in range(args.warmup):
+        step(True)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * args.steps)]
+    reps = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[3 * k].record()
+        rq = cf.qml(problem, bins, d_maps_qml, device=True, stage_timing=True, report=True,
+                    packed=packed)[1]
+        ev[3 * k + 1].record()
+        rs = cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True, stage_timing=True,
+                              report=True, packed=[packed])[1]
+        ev[3 * k + 2].record()
+        reps.append((rq, rs))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    qml_ms = [ev[3 * k].elapsed_time(ev[3 * k + 1]) for k in range(args.steps)]
+    scan_ms = [ev[3 * k + 1].elapsed_time(ev[3 * k + 2]) for k in range(args.steps)]
+    ms_step = 1000.0 * wall / args.steps
+    stage = np.mean([r[0]["ms_stage"] for r in reps], axis=0)
+    scan_stage = np.mean([r[1]["ms_stage"] for r in reps], axis=0)
+    # dominant kernel: the FP64 MFMA GEMM forming Z = G^T G (two launches: all columns over the
+    # Q,U rows, then the T x T block over the T rows); algorithmic flops count only the Z blocks
+    # that are not identically zero, each symmetric pair once.
+    npx = problem.npix
+    kT, kP = 2300, 4600
+    p0 = (npx // 64) * 64
+    syrk_flops = (kT * (kT + 1) + 2 * kT * kP + kP * (kP + 1)) * (n - p0) + kT * (kT + 1) * p0
+    syrk_ms = stage[4]
+    achieved = syrk_flops / (syrk_ms * 1e-3) / 1e12
+    out = {
+        "metric": "Fisher wall time & −2lnL evals/s, FP64 vs mixed/emulator, Nside16 TQU",
+        "value": 1000.0 / ms_step,
+        "unit": "steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": ("TQU N_side 16, |b|>20 deg (n=5952), l 2-47, 6 spectra x 12 bins; "
+                                f"step = Fisher+QML (1 map) + -2lnL at {SCAN_POINTS} points x "
+                                f"{NMAPS_SCAN} maps"),
+                   "precision": "fp64", "n": n, "nmodes": 6900, "scan_points_per_step": SCAN_POINTS,
+                   "maps_per_point": NMAPS_SCAN},
+        "fisher_qml_ms": float(np.median(qml_ms)),
+        "loglike_ms": float(np.median(scan_ms)),
+        "loglike_points_per_s": SCAN_POINTS / (np.median(scan_ms) * 1e-3),
+        "loglike_map_evals_per_s": SCAN_POINTS * NMAPS_SCAN / (np.median(scan_ms) * 1e-3),
+        "stages_fisher_qml_ms": dict(zip(cf.STAGES, [round(float(x), 4) for x in stage])),
+        "stages_loglike_ms": dict(zip(cf.STAGES, [round(float(x), 4) for x in scan_stage])),
+        "roofline": {"bound": "mfma", "kernel": "k_gemm FP64 (Z = G^T G)",
+                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(problem, bins, cl_points, maps_qml, maps_scan)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

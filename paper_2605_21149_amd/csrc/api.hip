@@ -340,7 +340,7 @@ int read_flags(CallCtx& c, const int* dflags, int nflags, int* out) {
 
 // ------------------------------------------------------------------------------- Fisher core
 struct FisherBufs {
-  double *C, *Y, *G, *Z, *dinv, *ldpart, *gram, *ztr, *F;
+  double *C, *Y, *G, *Z, *Linv, *ldpart, *gram, *ztr, *F;
   int* lo;
   int* hi;
   int* flags;   // [0] non-finite covariance, [1] first failing pivot, [2] F pivot failure
@@ -354,7 +354,7 @@ size_t fisher_ws(const HostProblem& H, const HostBins& B, Sizer& z) {
   z.add<double>((size_t)H.n * H.k);
   z.add<double>((size_t)H.n * H.k);
   z.add<double>((size_t)H.k * H.k);
-  z.add<double>(H.n);
+  z.add<double>((size_t)((H.n + kNB - 1) / kNB) * kNB * kNB);
   z.add<double>((H.n + kNB - 1) / kNB);
   z.add<double>((size_t)nl * (nl + 1) / 2 * nq);
   z.add<double>((size_t)nl * np);
@@ -373,7 +373,7 @@ void fisher_take(Bump& bp, const HostProblem& H, const HostBins& B, FisherBufs& 
   f.Y = bp.take<double>((size_t)H.n * H.k);
   f.G = bp.take<double>((size_t)H.n * H.k);
   f.Z = bp.take<double>((size_t)H.k * H.k);
-  f.dinv = bp.take<double>(H.n);
+  f.Linv = bp.take<double>((size_t)((H.n + kNB - 1) / kNB) * kNB * kNB);
   f.ldpart = bp.take<double>((H.n + kNB - 1) / kNB);
   f.gram = bp.take<double>((size_t)nl * (nl + 1) / 2 * nq);
   f.ztr = bp.take<double>((size_t)nl * np);
@@ -393,7 +393,7 @@ int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, F
   CF_DEV(launch_cov_build(P, S.cw, 0, 1, prob->noise_kind, S.noise, prob->noise_rank, S.noise_U, f.C, n,
                           0, 1, f.flags, s));
   tm.mark(ST_BUILD);
-  CF_DEV(potrf_f64(f.C, n, n, 0, 1, f.dinv, 0, f.ldpart, 0, f.flags + 1, s));
+  CF_DEV(potrf_f64(f.C, n, n, 0, 1, f.Linv, 0, f.ldpart, 0, f.flags + 1, s));
   tm.mark(ST_POTRF);
   CF_DEV(launch_ybuild(P, f.Y, k, s));
   tm.mark(ST_YBUILD);
@@ -402,10 +402,10 @@ int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, F
   const int64_t kT = H.has_t ? H.kf : 0;
   const int64_t p0 = (H.has_t && H.has_p) ? (H.npx / kNB) * kNB : 0;
   if (H.has_t && H.has_p) {
-    CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.dinv, 0, f.Y, k, 0, f.G, k, 0, kT, 0, 1, s));
-    CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.dinv, 0, f.Y + kT, k, 0, f.G + kT, k, 0, k - kT, H.npx, 1, s));
+    CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.Linv, 0, f.Y, k, 0, f.G, k, 0, kT, 0, 1, s));
+    CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.Linv, 0, f.Y + kT, k, 0, f.G + kT, k, 0, k - kT, H.npx, 1, s));
   } else {
-    CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.dinv, 0, f.Y, k, 0, f.G, k, 0, k, 0, 1, s));
+    CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.Linv, 0, f.Y, k, 0, f.G, k, 0, k, 0, 1, s));
   }
   tm.mark(ST_TRSM);
   GemmDesc g{};
@@ -625,7 +625,7 @@ int cf_qml(const cf_problem* prob, const cf_bins* bins, const double* maps, int3
   // u = L^-1 d, w = Y^T C^-1 d = G^T u (Eq. weighted_data)
   const int64_t n = H.n, k = H.k;
   CF_DEV(launch_transpose(mdev, nmaps, n, n, D, nmaps, c.s));
-  CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.dinv, 0, D, nmaps, 0, U, nmaps, 0, nmaps, 0, 1, c.s));
+  CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.Linv, 0, D, nmaps, 0, U, nmaps, 0, nmaps, 0, 1, c.s));
   const int64_t kT = H.has_t ? H.kf : 0;
   const int64_t p0 = (H.has_t && H.has_p) ? (H.npx / kNB) * kNB : 0;
   GemmDesc g{};
@@ -715,7 +715,7 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   }
   z.add<double>((size_t)Bt * 6 * L);                   // cw per point
   z.add<double>((size_t)Bt * nmax * nmax);             // C batch
-  z.add<double>((size_t)Bt * nmax);                    // dinv
+  z.add<double>((size_t)Bt * ((nmax + kNB - 1) / kNB) * kNB * kNB);   // inverted diagonal blocks
   z.add<double>((size_t)Bt * ((nmax + kNB - 1) / kNB)); // logdet parts
   z.add<double>((size_t)nmax * nmaps);                 // D
   z.add<double>((size_t)Bt * nmax * nmaps);            // Y copies
@@ -747,7 +747,7 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   }
   double* cwb = bp.take<double>((size_t)Bt * 6 * L);
   double* Cb = bp.take<double>((size_t)Bt * nmax * nmax);
-  double* dinv = bp.take<double>((size_t)Bt * nmax);
+  double* Linv = bp.take<double>((size_t)Bt * ((nmax + kNB - 1) / kNB) * kNB * kNB);
   double* ldp = bp.take<double>((size_t)Bt * ((nmax + kNB - 1) / kNB));
   double* D = bp.take<double>((size_t)nmax * nmaps);
   double* Yb = bp.take<double>((size_t)Bt * nmax * nmaps);
@@ -777,13 +777,13 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
                               probs[p].noise_rank, S[p].noise_U, Cb, n, n * n, 1, flags, c.s));
       tm.mark(ST_BUILD);
       // a4: Cholesky and log det
-      CF_DEV(potrf_f64(Cb, n, n, n * n, b, dinv, n, ldp, nblk, flags + 1, c.s));
+      CF_DEV(potrf_f64(Cb, n, n, n * n, b, Linv, nblk * kNB * kNB, ldp, nblk, flags + 1, c.s));
       tm.mark(ST_POTRF);
       // a6: u = L^-1 d for every map, chi^2 = |u|^2
       for (int j = 0; j < b; ++j)
         CF_DEV(hipMemcpyAsync(Yb + (size_t)j * n * nmaps, D, sizeof(double) * n * nmaps,
                               hipMemcpyDeviceToDevice, c.s));
-      CF_DEV(trsm_lower_f64(Cb, n, n, n * n, dinv, n, Yb, nmaps, n * nmaps, Gb, nmaps, n * nmaps, nmaps,
+      CF_DEV(trsm_lower_f64(Cb, n, n, n * n, Linv, nblk * kNB * kNB, Yb, nmaps, n * nmaps, Gb, nmaps, n * nmaps, nmaps,
                             0, b, c.s));
       CF_DEV(launch_colsumsq(Gb, n, nmaps, nmaps, n * nmaps, b, x2, nmaps, c.s));
       CF_DEV(launch_sum_parts(ldp, (int)nblk, nblk, b, ldb, 1, c.s));

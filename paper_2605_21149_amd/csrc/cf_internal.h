@@ -73,15 +73,15 @@ struct GemmDesc {
 hipError_t gemm_f64(const GemmDesc& g, hipStream_t s);
 
 // Cholesky of the n x n lower triangle (row-major, ld) in place, batched with stride.
-// dinv[n] receives 1/L_ii, ldpart[nblocks] the per-block sums of ln L_ii, fail the first
-// non-positive pivot (atomicMin; initialise to INT_MAX).
-hipError_t potrf_f64(double* A, int64_t n, int64_t lda, int64_t sA, int batch, double* dinv,
-                     int64_t sD, double* ldpart, int64_t sL, int* fail, hipStream_t s);
+// Linv[nblocks][64][64] receives the inverses of the 64 x 64 diagonal blocks of L, ldpart[nblocks]
+// the per-block sums of ln L_ii, fail the first non-positive pivot (atomicMin; initialise INT_MAX).
+hipError_t potrf_f64(double* A, int64_t n, int64_t lda, int64_t sA, int batch, double* Linv,
+                     int64_t sLi, double* ldpart, int64_t sL, int* fail, hipStream_t s);
 
-// Forward substitution B <- L^-1 B for rows [r0, n) of B (n x ncol, ldb), L from potrf_f64;
-// rows below r0 of B are taken as zero.  Y is consumed (used as workspace); result goes to G.
-hipError_t trsm_lower_f64(const double* L, int64_t n, int64_t ldl, int64_t sL, const double* dinv,
-                          int64_t sD, double* Y, int64_t ldy, int64_t sY, double* G, int64_t ldg,
+// Forward substitution G = L^-1 Y for rows [r0, n) (rows of Y below r0 are taken as zero;
+// the solve starts at the 64-row block holding r0).  Y (n x ncol, ldy) is consumed as workspace.
+hipError_t trsm_lower_f64(const double* L, int64_t n, int64_t ldl, int64_t sL, const double* Linv,
+                          int64_t sLi, double* Y, int64_t ldy, int64_t sY, double* G, int64_t ldg,
                           int64_t sG, int64_t ncol, int64_t r0, int batch, hipStream_t s);
 
 // ---------------------------------------------------------------- harmonic basis

@@ -286,15 +286,21 @@ __global__ void k_transpose(const double* A, int64_t rows, int64_t cols, int64_t
     if (c0 + r < cols && r0 + tx < rows) B[(c0 + r) * ldb + r0 + tx] = t[tx][r];
 }
 
-// out[b][j] = sum_i U[b][i][j]^2 (fixed summation order)
-__global__ void k_colsumsq(const double* U, int64_t rows, int64_t cols, int64_t ldu, int64_t sU,
-                           double* out, int64_t sOut) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cols) return;
+// out[b][j] = sum_i U[b][i][j]^2: one workgroup per (column, batch item), fixed-order tree sum.
+__global__ __launch_bounds__(256) void k_colsumsq(const double* U, int64_t rows, int64_t cols, int64_t ldu,
+                                                  int64_t sU, double* out, int64_t sOut) {
+  __shared__ double red[256];
+  const int64_t j = blockIdx.x;
   const double* u = U + blockIdx.z * sU + j;
   double s = 0.0;
-  for (int64_t i = 0; i < rows; ++i) { double v = u[i * ldu]; s = fma(v, v, s); }
-  out[blockIdx.z * sOut + j] = s;
+  for (int64_t i = threadIdx.x; i < rows; i += 256) { const double v = u[i * ldu]; s = fma(v, v, s); }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.z * sOut + j] = red[0];
 }
 
 __global__ void k_sum_parts(const double* parts, int nparts, int64_t sP, double* out, int64_t sOut) {
@@ -414,7 +420,7 @@ hipError_t launch_transpose(const double* A, int64_t rows, int64_t cols, int64_t
 
 hipError_t launch_colsumsq(const double* U, int64_t rows, int64_t cols, int64_t ldu, int64_t sU,
                            int batch, double* out, int64_t sOut, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsumsq, dim3(blocks(cols, 64), 1, batch), dim3(64), 0, s, U, rows, cols, ldu,
+  hipLaunchKernelGGL(k_colsumsq, dim3((unsigned)cols, 1, batch), dim3(256), 0, s, U, rows, cols, ldu,
                      sU, out, sOut);
   return hipGetLastError();
 }

@@ -27,12 +27,19 @@ struct GemmArgs {
 };
 
 template <int BM, int BN, bool AT, bool BT>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  constexpr int BK = 16, PAD = 1;
+__global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
+  constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2, MI = WM / 16, NI = WN / 16;
   constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
-  __shared__ double As[2][BK][BM + PAD];
-  __shared__ double Bs[2][BK][BN + PAD];
+  // LDS layouts follow the global contiguity of each operand, so that tile stores are plain
+  // copies: A^T-stored operands as [k][i], row-stored ones as [i][k] (odd padded strides keep the
+  // fragment reads of 16 rows on distinct banks).
+  constexpr int SA = AT ? (BM + 1) : (BK + 1);        // row stride of As
+  constexpr int SB = BT ? (BK + 1) : (BN + 1);        // row stride of Bs
+  constexpr int NA = AT ? BK * SA : BM * SA;
+  constexpr int NBs = BT ? BN * SB : BK * SB;
+  __shared__ double As[2][NA];
+  __shared__ double Bs[2][NBs];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -40,44 +47,56 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   const int64_t i0 = (int64_t)tile_m * BM, j0 = (int64_t)tile_n * BN;
   if (g.lower && j0 >= i0 + BM) return;            // tile strictly above the diagonal
   const int64_t z = blockIdx.z;
-  const double* __restrict__ A = g.A + z * g.sA;
-  const double* __restrict__ B = g.B + z * g.sB;
-  double* __restrict__ C = g.C + z * g.sC;
+  const double* A = g.A + z * g.sA;
+  const double* B = g.B + z * g.sB;
+  double* C = g.C + z * g.sC;
   const int64_t M = g.M, N = g.N, K = g.K;
+
+  // Per-thread base pointers: every load of a slab is base + (uniform offset), so only one
+  // 64-bit address per operand stays live across the MFMA loop.
+  //   row-stored operand (k contiguous): thread covers row (tid / BK) + p * (256 / BK), column tid % BK
+  //   transposed operand (i contiguous):  thread covers k-row (tid / BM) + p * (256 / BM), column tid % BM
+  constexpr int RA = AT ? 256 / BM : 256 / BK;       // rows advanced per load step p
+  constexpr int RB = BT ? 256 / BK : 256 / BN;
+  const int a_r = AT ? tid / BM : tid / BK, a_c = AT ? tid % BM : tid % BK;
+  const int b_r = BT ? tid / BK : tid / BN, b_c = BT ? tid % BK : tid % BN;
+  const double* pa = AT ? A + (int64_t)a_r * g.lda + i0 + a_c : A + (i0 + a_r) * g.lda + a_c;
+  const double* pb = BT ? B + (j0 + b_r) * g.ldb + b_c : B + (int64_t)b_r * g.ldb + j0 + b_c;
+  const int64_t lda = g.lda, ldb = g.ldb;
 
   double ra[LA], rb[LB];
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int p = 0; p < LA; ++p) {
-      int idx = p * 256 + tid;
-      int ii = AT ? (idx % BM) : (idx / BK);
-      int kk = AT ? (idx / BM) : (idx % BK);
-      int64_t gi = i0 + ii, gk = k0 + kk;
-      ra[p] = (gi < M && gk < K) ? (AT ? A[gk * g.lda + gi] : A[gi * g.lda + gk]) : 0.0;
+      if (AT) {   // element (i0 + a_c, k0 + a_r + p*RA)
+        const int64_t gk = k0 + a_r + p * RA;
+        ra[p] = (i0 + a_c < M && gk < K) ? pa[(k0 + p * RA) * lda] : 0.0;
+      } else {    // element (i0 + a_r + p*RA, k0 + a_c)
+        const int64_t gi = i0 + a_r + p * RA;
+        ra[p] = (gi < M && k0 + a_c < K) ? pa[(int64_t)p * RA * lda + k0] : 0.0;
+      }
     }
 #pragma unroll
     for (int p = 0; p < LB; ++p) {
-      int idx = p * 256 + tid;
-      int jj = BT ? (idx / BK) : (idx % BN);
-      int kk = BT ? (idx % BK) : (idx / BN);
-      int64_t gj = j0 + jj, gk = k0 + kk;
-      rb[p] = (gj < N && gk < K) ? (BT ? B[gj * g.ldb + gk] : B[gk * g.ldb + gj]) : 0.0;
+      if (BT) {   // element (k0 + b_c, j0 + b_r + p*RB)
+        const int64_t gj = j0 + b_r + p * RB;
+        rb[p] = (gj < N && k0 + b_c < K) ? pb[(int64_t)p * RB * ldb + k0] : 0.0;
+      } else {    // element (k0 + b_r + p*RB, j0 + b_c)
+        const int64_t gk = k0 + b_r + p * RB;
+        rb[p] = (j0 + b_c < N && gk < K) ? pb[(k0 + p * RB) * ldb] : 0.0;
+      }
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int p = 0; p < LA; ++p) {
-      int idx = p * 256 + tid;
-      int ii = AT ? (idx % BM) : (idx / BK);
-      int kk = AT ? (idx / BM) : (idx % BK);
-      As[buf][kk][ii] = ra[p];
+      const int r = a_r + p * RA;   // k-row (AT) or i-row
+      As[buf][r * SA + a_c] = ra[p];
     }
 #pragma unroll
     for (int p = 0; p < LB; ++p) {
-      int idx = p * 256 + tid;
-      int jj = BT ? (idx / BK) : (idx % BN);
-      int kk = BT ? (idx % BK) : (idx / BN);
-      Bs[buf][kk][jj] = rb[p];
+      const int r = b_r + p * RB;   // j-row (BT) or k-row
+      Bs[buf][r * SB + b_c] = rb[p];
     }
   };
 
@@ -99,9 +118,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       const int kr = kq * 4 + (lane >> 4);
       double av[MI], bv[NI];
 #pragma unroll
-      for (int a = 0; a < MI; ++a) av[a] = As[cur][kr][wr * WM + a * 16 + (lane & 15)];
+      for (int a = 0; a < MI; ++a) {
+        const int ii = wr * WM + a * 16 + (lane & 15);
+        av[a] = As[cur][AT ? kr * SA + ii : ii * SA + kr];
+      }
 #pragma unroll
-      for (int b = 0; b < NI; ++b) bv[b] = Bs[cur][kr][wc * WN + b * 16 + (lane & 15)];
+      for (int b = 0; b < NI; ++b) {
+        const int jj = wc * WN + b * 16 + (lane & 15);
+        bv[b] = Bs[cur][BT ? jj * SB + kr : kr * SB + jj];
+      }
 #pragma unroll
       for (int a = 0; a < MI; ++a)
 #pragma unroll
