@@ -37,9 +37,16 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 // ------------------------------------------------------------------------------- per device
+constexpr int kEvents = 16;
 struct Device {
   std::mutex mu;
   hipStream_t stream = nullptr;
+  hipStream_t aux[2] = {nullptr, nullptr};   // side streams for independent work (default priority)
+  // Cholesky streams: the critical path (diagonal blocks, panels, lookahead columns) runs on a
+  // small reserved set of CUs so that the bulk trailing update, which owns the rest, never delays
+  // it.  Both are plain streams when CU masks are unavailable.
+  hipStream_t crit = nullptr, bulk = nullptr;
+  hipEvent_t ev[kEvents] = {};               // ordering events between the streams
   char* ws = nullptr;
   size_t cap = 0;
   int* hflags = nullptr;   // pinned host mirror of the device flags
@@ -171,6 +178,8 @@ int check_bins(const cf_bins* B, const HostProblem& H, HostBins& out) {
   if (out.ns == 0) return fail(CF_EINVAL, "no spectra requested");
   if (B->spectra & ~63u) return fail(CF_EINVAL, "unknown spectrum bits");
   out.nb = B->nbins;
+  if ((int64_t)out.ns * out.nb > 1024)
+    return fail(CF_EINVAL, "%d spectra x %d bins exceeds the 1024 Fisher parameters supported", out.ns, out.nb);
   out.lo.assign(B->lo, B->lo + B->nbins);
   out.hi.assign(B->hi, B->hi + B->nbins);
   for (int b = 0; b < out.nb; ++b)
@@ -274,38 +283,116 @@ int stage(Bump& bp, const cf_problem* P, const HostProblem& H, const double* cl_
 struct Timer {
   bool on = false;
   hipStream_t s = nullptr;
-  std::vector<hipEvent_t> ev;
-  std::vector<int> stage;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  struct Iv { int stage; hipEvent_t a, b; };
+  std::vector<Iv> iv;
+  std::vector<std::pair<int, hipEvent_t>> marks;   // sequential marks on the main stream
+  hipEvent_t make() {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) { on = false; return nullptr; }
+    return e;
+  }
   void begin(bool enable, hipStream_t st) {
     on = enable;
     s = st;
-    if (on) mark(-1);
+    if (!on) return;
+    t0 = make();
+    if (t0) (void)hipEventRecord(t0, s);
+    marks.push_back({-1, t0});
   }
+  // main-stream stage boundary: the interval since the previous mark is charged to stage_id
   void mark(int stage_id) {
     if (!on) return;
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+    hipEvent_t e = make();
+    if (!e) return;
     (void)hipEventRecord(e, s);
-    ev.push_back(e);
-    stage.push_back(stage_id);
+    marks.push_back({stage_id, e});
+  }
+  // explicit interval on any stream
+  hipEvent_t open(hipStream_t st) {
+    if (!on) return nullptr;
+    hipEvent_t e = make();
+    if (e) (void)hipEventRecord(e, st);
+    return e;
+  }
+  void close(int stage_id, hipEvent_t a, hipStream_t st) {
+    if (!on || !a) return;
+    hipEvent_t b = make();
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    iv.push_back({stage_id, a, b});
   }
   void finish(cf_report* rep) {
     if (!on) return;
-    (void)hipEventSynchronize(ev.back());
-    for (size_t i = 1; i < ev.size(); ++i) {
+    t1 = make();
+    if (!t1) return;
+    (void)hipEventRecord(t1, s);
+    (void)hipEventSynchronize(t1);
+    for (size_t i = 1; i < marks.size(); ++i) {
       float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, ev[i - 1], ev[i]);
-      if (rep && stage[i] >= 0 && stage[i] < 8) rep->ms_stage[stage[i]] += ms;
+      (void)hipEventElapsedTime(&ms, marks[i - 1].second, marks[i].second);
+      if (rep && marks[i].first >= 0 && marks[i].first < 8) rep->ms_stage[marks[i].first] += ms;
+    }
+    for (auto& x : iv) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, x.a, x.b);
+      if (rep && x.stage >= 0 && x.stage < 8) rep->ms_stage[x.stage] += ms;
     }
     float tot = 0.f;
-    (void)hipEventElapsedTime(&tot, ev.front(), ev.back());
+    (void)hipEventElapsedTime(&tot, t0, t1);
     if (rep) rep->ms_total = tot;
-    for (auto e : ev) (void)hipEventDestroy(e);
-    ev.clear();
-    stage.clear();
+    for (auto& m : marks) (void)hipEventDestroy(m.second);
+    for (auto& x : iv) { (void)hipEventDestroy(x.a); (void)hipEventDestroy(x.b); }
+    (void)hipEventDestroy(t1);
+    marks.clear();
+    iv.clear();
   }
 };
 enum { ST_BUILD = 0, ST_POTRF, ST_YBUILD, ST_TRSM, ST_SYRK, ST_REDUCE, ST_QML, ST_OTHER };
+
+// Reserve 4 CUs per XCD (32 of 256) for the critical path.  With 32 CUs per XCD the CU index i
+// lies on XCD i / 32 if CUs are numbered XCD by XCD, or on XCD i % 8 if they alternate; the set
+// {i : i % 8 == (i / 32) % 8} holds 4 CUs of every XCD under either numbering.
+void make_cholesky_streams(Device& d, int id) {
+  hipDeviceProp_t prop;
+  d.crit = d.bulk = nullptr;
+  if (hipGetDeviceProperties(&prop, id) != hipSuccess) return;
+  const int ncu = prop.multiProcessorCount;
+  if (ncu < 64 || ncu % 8 || ncu > 1024) return;
+  const int per = ncu / 8;
+  std::vector<uint32_t> mc((ncu + 31) / 32, 0u), mb((ncu + 31) / 32, 0u);
+  for (int i = 0; i < ncu; ++i) {
+    const bool c = (i % 8) == ((i / per) % 8);
+    (c ? mc : mb)[i / 32] |= 1u << (i % 32);
+  }
+  hipStream_t a = nullptr, b = nullptr;
+  if (hipExtStreamCreateWithCUMask(&a, (uint32_t)mc.size(), mc.data()) != hipSuccess) return;
+  if (hipExtStreamCreateWithCUMask(&b, (uint32_t)mb.size(), mb.data()) != hipSuccess) {
+    (void)hipStreamDestroy(a);
+    return;
+  }
+  d.crit = a;
+  d.bulk = b;
+}
+
+// Factorisation on the reserved-CU streams, ordered after and joined back into s.
+int potrf_on(Device& d, Factor& F, double* scratch, hipStream_t s, hipStream_t side, hipEvent_t* ev) {
+  // A batch of factorisations is bound by its bulk updates, not by the chain of diagonal blocks:
+  // it keeps every CU for the bulk work.
+  if (!d.crit || F.batch > 1) {
+    Streams st{s, d.aux[0], side, ev[0], ev[1], ev[2]};
+    CF_DEV(potrf_f64(F, scratch, st));
+    return CF_OK;
+  }
+  CF_DEV(hipEventRecord(ev[3], s));
+  CF_DEV(hipStreamWaitEvent(d.crit, ev[3], 0));
+  CF_DEV(hipStreamWaitEvent(d.bulk, ev[3], 0));
+  Streams st{d.crit, d.bulk, side, ev[0], ev[1], ev[2]};
+  CF_DEV(potrf_f64(F, scratch, st));
+  CF_DEV(hipEventRecord(ev[4], d.crit));
+  CF_DEV(hipStreamWaitEvent(s, ev[4], 0));
+  return CF_OK;
+}
 
 struct CallCtx {
   Device* dev = nullptr;
@@ -317,7 +404,12 @@ struct CallCtx {
     if (id < 0 || id >= 64) return fail(CF_EDEVICE, "device id %d unsupported", id);
     dev = &g_dev[id];
     lock = std::unique_lock<std::mutex>(dev->mu);
-    if (!dev->stream) CF_DEV(hipStreamCreateWithFlags(&dev->stream, hipStreamNonBlocking));
+    if (!dev->stream) {
+      CF_DEV(hipStreamCreateWithFlags(&dev->stream, hipStreamNonBlocking));
+      for (auto& a : dev->aux) CF_DEV(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+      for (auto& e : dev->ev) CF_DEV(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      make_cholesky_streams(*dev, id);
+    }
     if (!dev->hflags) CF_DEV(hipHostMalloc((void**)&dev->hflags, 64 * sizeof(int), hipHostMallocDefault));
     s = (ex && ex->stream) ? (hipStream_t)ex->stream : dev->stream;
     return CF_OK;
@@ -340,7 +432,7 @@ int read_flags(CallCtx& c, const int* dflags, int nflags, int* out) {
 
 // ------------------------------------------------------------------------------- Fisher core
 struct FisherBufs {
-  double *C, *Y, *G, *Z, *Linv, *ldpart, *gram, *ztr, *F;
+  double *C, *Y, *G, *Z, *Linv, *Li256, *scratch, *ldpart, *gram, *ztr, *F;
   int* lo;
   int* hi;
   int* flags;   // [0] non-finite covariance, [1] first failing pivot, [2] F pivot failure
@@ -355,6 +447,8 @@ size_t fisher_ws(const HostProblem& H, const HostBins& B, Sizer& z) {
   z.add<double>((size_t)H.n * H.k);
   z.add<double>((size_t)H.k * H.k);
   z.add<double>((size_t)((H.n + kNB - 1) / kNB) * kNB * kNB);
+  z.add<double>((size_t)(H.n / 256) * 256 * 256);
+  z.add<double>((size_t)potrf_scratch(1));
   z.add<double>((H.n + kNB - 1) / kNB);
   z.add<double>((size_t)nl * (nl + 1) / 2 * nq);
   z.add<double>((size_t)nl * np);
@@ -374,6 +468,8 @@ void fisher_take(Bump& bp, const HostProblem& H, const HostBins& B, FisherBufs& 
   f.G = bp.take<double>((size_t)H.n * H.k);
   f.Z = bp.take<double>((size_t)H.k * H.k);
   f.Linv = bp.take<double>((size_t)((H.n + kNB - 1) / kNB) * kNB * kNB);
+  f.Li256 = bp.take<double>((size_t)(H.n / 256) * 256 * 256);
+  f.scratch = bp.take<double>((size_t)potrf_scratch(1));
   f.ldpart = bp.take<double>((H.n + kNB - 1) / kNB);
   f.gram = bp.take<double>((size_t)nl * (nl + 1) / 2 * nq);
   f.ztr = bp.take<double>((size_t)nl * np);
@@ -383,46 +479,134 @@ void fisher_take(Bump& bp, const HostProblem& H, const HostBins& B, FisherBufs& 
   f.flags = bp.take<int>(8);
 }
 
-// Covariance, factor, Y, G = L^-1 Y, Z = G^T G, Gram of Z blocks.
+Factor make_factor(const FisherBufs& f, int64_t n) {
+  Factor F;
+  F.L = f.C; F.n = n; F.ld = n; F.sL = 0;
+  F.Li64 = f.Linv; F.sLi64 = 0;
+  F.Li256 = (n >= 256) ? f.Li256 : nullptr; F.sLi256 = 0;
+  F.ldpart = f.ldpart; F.sPart = 0;
+  F.fail = f.flags + 1;
+  F.batch = 1;
+  return F;
+}
+
+// Optional QML part of a Fisher call: maps and the buffers of u = L^-1 d and w = G^T u.
+struct QmlBufs {
+  const double* maps = nullptr;   // device [nmaps][n]
+  int nmaps = 0;
+  double *D = nullptr, *U = nullptr, *W = nullptr, *part = nullptr;
+};
+
+// W (M x nmaps) = A^T U with A = rows [0, K) of a row-major matrix (ld lda) and U (K x nmaps):
+// a skinny product for a few maps, the MFMA GEMM otherwise.
+hipError_t weighted_maps(const double* A, int64_t lda, int64_t M, int64_t K, const double* U, int nmaps,
+                         double* W, double* part, hipStream_t s) {
+  if (nmaps <= 8) return gemv_tn(A, lda, M, K, U, nmaps, W, nmaps, part, s);
+  GemmDesc w{};
+  w.M = M; w.N = nmaps; w.K = K;
+  w.A = A; w.lda = lda; w.at = 1;
+  w.B = U; w.ldb = nmaps; w.bt = 0;
+  w.C = W; w.ldc = nmaps; w.alpha = 1.0; w.beta = 0.0; w.batch = 1;
+  return gemm_f64(w, s);
+}
+
+// Covariance, factor, Y, G = L^-1 Y, Z = G^T G (+ u = L^-1 d, w = G^T u), Gram of Z blocks.
+// Three streams: the caller's stream s carries the covariance, the factorisation and the T part;
+// aux[0] builds Y (concurrently with the factorisation) and then carries the E,B part; aux[1]
+// solves the maps.  Events order the hand-offs; everything is joined back into s.
 int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, FisherBufs& f,
-                hipStream_t s, Timer& tm) {
+                QmlBufs* qb, CallCtx& cc, Timer& tm) {
   const DevProblem& P = S.P;
   const int64_t n = H.n, k = H.k;
+  hipStream_t s = cc.s, s1 = cc.dev->aux[0], s2 = cc.dev->aux[1];
+  hipEvent_t* ev = cc.dev->ev;
+  enum { E_START = 0, E_Y, E_L, E_T, E_EB, E_S1, E_S2 };
+  CF_DEV(hipEventRecord(ev[E_START], s));
+  CF_DEV(hipStreamWaitEvent(s1, ev[E_START], 0));
+  CF_DEV(hipStreamWaitEvent(s2, ev[E_START], 0));
+  // aux[0]: harmonic basis, independent of the covariance
+  hipEvent_t ty = tm.open(s1);
+  CF_DEV(launch_ybuild(P, f.Y, k, s1));
+  tm.close(ST_YBUILD, ty, s1);
+  CF_DEV(hipEventRecord(ev[E_Y], s1));
+  // s: covariance and Cholesky factor
   CF_DEV(launch_fill_int(f.flags, 1, 0, s));
   CF_DEV(launch_fill_int(f.flags + 1, 2, INT_MAX, s));
   CF_DEV(launch_cov_build(P, S.cw, 0, 1, prob->noise_kind, S.noise, prob->noise_rank, S.noise_U, f.C, n,
                           0, 1, f.flags, s));
   tm.mark(ST_BUILD);
-  CF_DEV(potrf_f64(f.C, n, n, 0, 1, f.Linv, 0, f.ldpart, 0, f.flags + 1, s));
+  Factor F = make_factor(f, n);
+  if (int st = potrf_on(*cc.dev, F, f.scratch, s, s2, ev + 8)) return st;
   tm.mark(ST_POTRF);
-  CF_DEV(launch_ybuild(P, f.Y, k, s));
-  tm.mark(ST_YBUILD);
-  // G = L^-1 Y.  Y is block diagonal over [T | QU]: the E,B columns are zero in the T rows, so
-  // their solve starts at the 64-row block that holds the first Q row.
-  const int64_t kT = H.has_t ? H.kf : 0;
-  const int64_t p0 = (H.has_t && H.has_p) ? (H.npx / kNB) * kNB : 0;
-  if (H.has_t && H.has_p) {
-    CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.Linv, 0, f.Y, k, 0, f.G, k, 0, kT, 0, 1, s));
-    CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.Linv, 0, f.Y + kT, k, 0, f.G + kT, k, 0, k - kT, H.npx, 1, s));
-  } else {
-    CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.Linv, 0, f.Y, k, 0, f.G, k, 0, k, 0, 1, s));
+  CF_DEV(hipEventRecord(ev[E_L], s));
+  // aux[1]: u = L^-1 d for the maps
+  if (qb) {
+    CF_DEV(hipStreamWaitEvent(s2, ev[E_L], 0));
+    CF_DEV(launch_transpose(qb->maps, qb->nmaps, n, n, qb->D, qb->nmaps, s2));
+    CF_DEV(trsm_lower_f64(F, qb->D, qb->nmaps, 0, qb->U, qb->nmaps, 0, qb->nmaps, 0, s2));
   }
-  tm.mark(ST_TRSM);
-  GemmDesc g{};
-  g.M = k; g.N = k; g.K = n - p0;
-  g.A = f.G + p0 * k; g.lda = k; g.at = 1;
-  g.B = f.G + p0 * k; g.ldb = k; g.bt = 0;
-  g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1;
-  CF_DEV(gemm_f64(g, s));
-  if (p0 > 0) {
+  const bool split = H.has_t && H.has_p;
+  const int64_t kT = H.has_t ? H.kf : 0, kP = k - kT;
+  // Y is block diagonal over [T | QU]: the E,B columns vanish on the T rows, so their solve
+  // starts at the 64-row block p0 holding the first Q row, and G's E,B columns above p0 are zero.
+  const int64_t p0 = split ? (H.npx / kNB) * kNB : 0;
+  CF_DEV(hipStreamWaitEvent(s, ev[E_Y], 0));
+  if (split) {
+    CF_DEV(hipStreamWaitEvent(s1, ev[E_L], 0));
+    CF_DEV(trsm_lower_f64(F, f.Y + kT, k, 0, f.G + kT, k, 0, kP, H.npx, s1));
+    CF_DEV(hipEventRecord(ev[E_EB], s1));
+    CF_DEV(trsm_lower_f64(F, f.Y, k, 0, f.G, k, 0, kT, 0, s));
+    CF_DEV(hipEventRecord(ev[E_T], s));
+    tm.mark(ST_TRSM);
+    // Z_TT = G_T^T G_T over all rows (s)
+    GemmDesc g{};
+    g.M = kT; g.N = kT; g.K = n;
+    g.A = f.G; g.lda = k; g.at = 1;
+    g.B = f.G; g.ldb = k; g.bt = 0;
+    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1;
+    CF_DEV(gemm_f64(g, s));
+    // Z rows of E,B against all columns (lower part), over rows >= p0 (aux[0])
+    CF_DEV(hipStreamWaitEvent(s1, ev[E_T], 0));
     GemmDesc h{};
-    h.M = kT; h.N = kT; h.K = p0;
-    h.A = f.G; h.lda = k; h.at = 1;
-    h.B = f.G; h.ldb = k; h.bt = 0;
-    h.C = f.Z; h.ldc = k; h.alpha = 1.0; h.beta = 1.0; h.lower = 1; h.batch = 1;
-    CF_DEV(gemm_f64(h, s));
+    h.M = kP; h.N = k; h.K = n - p0;
+    h.A = f.G + p0 * k + kT; h.lda = k; h.at = 1;
+    h.B = f.G + p0 * k; h.ldb = k; h.bt = 0;
+    h.C = f.Z + kT * k; h.ldc = k; h.alpha = 1.0; h.beta = 0.0; h.lower = 1; h.diag_off = kT;
+    h.batch = 1;
+    hipEvent_t tz = tm.open(s1);
+    CF_DEV(gemm_f64(h, s1));
+    tm.close(ST_SYRK, tz, s1);
+    CF_DEV(hipEventRecord(ev[E_S1], s1));
+    if (qb) {   // w = G^T u
+      CF_DEV(hipStreamWaitEvent(s2, ev[E_T], 0));
+      CF_DEV(hipStreamWaitEvent(s2, ev[E_EB], 0));
+      CF_DEV(weighted_maps(f.G, k, kT, n, qb->U, qb->nmaps, qb->W, qb->part, s2));
+      CF_DEV(weighted_maps(f.G + p0 * k + kT, k, kP, n - p0, qb->U + p0 * qb->nmaps, qb->nmaps,
+                           qb->W + kT * qb->nmaps, qb->part, s2));
+      CF_DEV(hipEventRecord(ev[E_S2], s2));
+      CF_DEV(hipStreamWaitEvent(s, ev[E_S2], 0));
+    }
+    CF_DEV(hipStreamWaitEvent(s, ev[E_S1], 0));
+  } else {
+    CF_DEV(trsm_lower_f64(F, f.Y, k, 0, f.G, k, 0, k, 0, s));
+    CF_DEV(hipEventRecord(ev[E_T], s));
+    tm.mark(ST_TRSM);
+    GemmDesc g{};
+    g.M = k; g.N = k; g.K = n;
+    g.A = f.G; g.lda = k; g.at = 1;
+    g.B = f.G; g.ldb = k; g.bt = 0;
+    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1;
+    hipEvent_t tz = tm.open(s);
+    CF_DEV(gemm_f64(g, s));
+    tm.close(ST_SYRK, tz, s);
+    if (qb) {
+      CF_DEV(hipStreamWaitEvent(s2, ev[E_T], 0));
+      CF_DEV(weighted_maps(f.G, k, k, n, qb->U, qb->nmaps, qb->W, qb->part, s2));
+      CF_DEV(hipEventRecord(ev[E_S2], s2));
+      CF_DEV(hipStreamWaitEvent(s, ev[E_S2], 0));
+    }
   }
-  tm.mark(ST_SYRK);
+  tm.mark(ST_OTHER);
   CF_DEV(launch_symmetrize(f.Z, k, k, s));
   CF_DEV(launch_gram(P, f.Z, k, f.gram, f.ztr, s));
   tm.mark(ST_REDUCE);
@@ -550,7 +734,7 @@ int cf_fisher(const cf_problem* prob, const cf_bins* bins, int32_t precision, do
   CF_DEV(hipMemcpyAsync(f.hi, B.hi.data(), sizeof(int) * B.nb, hipMemcpyHostToDevice, c.s));
   Timer tm;
   tm.begin(ex && ex->stage_timing, c.s);
-  if (int st = fisher_core(prob, H, S, f, c.s, tm)) return st;
+  if (int st = fisher_core(prob, H, S, f, nullptr, c, tm)) return st;
   const SpecSel sel = make_sel(B, f);
   CF_DEV(launch_fisher_assemble(S.P, sel, f.gram, f.F, c.s));
   tm.mark(ST_REDUCE);
@@ -588,6 +772,7 @@ int cf_qml(const cf_problem* prob, const cf_bins* bins, const double* maps, int3
   z.add<double>((size_t)H.n * nmaps);        // D = maps^T
   z.add<double>((size_t)H.n * nmaps);        // u = L^-1 D
   z.add<double>((size_t)H.k * nmaps);        // w = G^T u
+  z.add<double>((size_t)32 * H.k * nmaps);   // partial sums of the skinny product
   z.add<double>((size_t)nmaps * K);          // y
   z.add<double>((size_t)K);                  // bias
   z.add<double>((size_t)nmaps * K);          // y - b
@@ -603,6 +788,7 @@ int cf_qml(const cf_problem* prob, const cf_bins* bins, const double* maps, int3
   double* D = bp.take<double>((size_t)H.n * nmaps);
   double* U = bp.take<double>((size_t)H.n * nmaps);
   double* W = bp.take<double>((size_t)H.k * nmaps);
+  double* part = bp.take<double>((size_t)32 * H.k * nmaps);
   double* y = bp.take<double>((size_t)nmaps * K);
   double* bias = bp.take<double>(K);
   double* q = bp.take<double>((size_t)nmaps * K);
@@ -617,31 +803,13 @@ int cf_qml(const cf_problem* prob, const cf_bins* bins, const double* maps, int3
   }
   Timer tm;
   tm.begin(ex && ex->stage_timing, c.s);
-  if (int st = fisher_core(prob, H, S, f, c.s, tm)) return st;
+  QmlBufs qb;
+  qb.maps = mdev; qb.nmaps = nmaps; qb.D = D; qb.U = U; qb.W = W; qb.part = part;
+  if (int st = fisher_core(prob, H, S, f, &qb, c, tm)) return st;
   const SpecSel sel = make_sel(B, f);
   CF_DEV(launch_fisher_assemble(S.P, sel, f.gram, f.F, c.s));
   CF_DEV(launch_bias_assemble(S.P, sel, f.gram, f.ztr, bias, c.s));
   tm.mark(ST_REDUCE);
-  // u = L^-1 d, w = Y^T C^-1 d = G^T u (Eq. weighted_data)
-  const int64_t n = H.n, k = H.k;
-  CF_DEV(launch_transpose(mdev, nmaps, n, n, D, nmaps, c.s));
-  CF_DEV(trsm_lower_f64(f.C, n, n, 0, f.Linv, 0, D, nmaps, 0, U, nmaps, 0, nmaps, 0, 1, c.s));
-  const int64_t kT = H.has_t ? H.kf : 0;
-  const int64_t p0 = (H.has_t && H.has_p) ? (H.npx / kNB) * kNB : 0;
-  GemmDesc g{};
-  g.M = (H.has_t && H.has_p) ? kT : k; g.N = nmaps; g.K = n;
-  g.A = f.G; g.lda = k; g.at = 1;
-  g.B = U; g.ldb = nmaps; g.bt = 0;
-  g.C = W; g.ldc = nmaps; g.alpha = 1.0; g.beta = 0.0; g.lower = 0; g.batch = 1;
-  CF_DEV(gemm_f64(g, c.s));
-  if (H.has_t && H.has_p) {
-    GemmDesc h{};
-    h.M = k - kT; h.N = nmaps; h.K = n - p0;
-    h.A = f.G + p0 * k + kT; h.lda = k; h.at = 1;
-    h.B = U + p0 * nmaps; h.ldb = nmaps; h.bt = 0;
-    h.C = W + kT * nmaps; h.ldc = nmaps; h.alpha = 1.0; h.beta = 0.0; h.lower = 0; h.batch = 1;
-    CF_DEV(gemm_f64(h, c.s));
-  }
   CF_DEV(launch_quad_assemble(S.P, sel, W, nmaps, nmaps, y, c.s));
   // chat = F^-1 (y - b)  (Eq. qml_estimate)
   CF_DEV(hipMemcpyAsync(q, y, sizeof(double) * nmaps * K, hipMemcpyDeviceToDevice, c.s));
@@ -716,6 +884,8 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   z.add<double>((size_t)Bt * 6 * L);                   // cw per point
   z.add<double>((size_t)Bt * nmax * nmax);             // C batch
   z.add<double>((size_t)Bt * ((nmax + kNB - 1) / kNB) * kNB * kNB);   // inverted diagonal blocks
+  z.add<double>((size_t)Bt * (nmax / 256) * 256 * 256);               // inverted 256-blocks
+  z.add<double>((size_t)potrf_scratch(Bt));
   z.add<double>((size_t)Bt * ((nmax + kNB - 1) / kNB)); // logdet parts
   z.add<double>((size_t)nmax * nmaps);                 // D
   z.add<double>((size_t)Bt * nmax * nmaps);            // Y copies
@@ -748,6 +918,8 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   double* cwb = bp.take<double>((size_t)Bt * 6 * L);
   double* Cb = bp.take<double>((size_t)Bt * nmax * nmax);
   double* Linv = bp.take<double>((size_t)Bt * ((nmax + kNB - 1) / kNB) * kNB * kNB);
+  double* Li256 = bp.take<double>((size_t)Bt * (nmax / 256) * 256 * 256);
+  double* pscr = bp.take<double>((size_t)potrf_scratch(Bt));
   double* ldp = bp.take<double>((size_t)Bt * ((nmax + kNB - 1) / kNB));
   double* D = bp.take<double>((size_t)nmax * nmaps);
   double* Yb = bp.take<double>((size_t)Bt * nmax * nmaps);
@@ -777,14 +949,19 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
                               probs[p].noise_rank, S[p].noise_U, Cb, n, n * n, 1, flags, c.s));
       tm.mark(ST_BUILD);
       // a4: Cholesky and log det
-      CF_DEV(potrf_f64(Cb, n, n, n * n, b, Linv, nblk * kNB * kNB, ldp, nblk, flags + 1, c.s));
+      Factor F;
+      F.L = Cb; F.n = n; F.ld = n; F.sL = n * n;
+      F.Li64 = Linv; F.sLi64 = nblk * kNB * kNB;
+      F.Li256 = (n >= 256) ? Li256 : nullptr; F.sLi256 = (n / 256) * 256 * 256;
+      F.ldpart = ldp; F.sPart = nblk;
+      F.fail = flags + 1; F.batch = b;
+      if (int st = potrf_on(*c.dev, F, pscr, c.s, c.dev->aux[1], c.dev->ev + 8)) return st;
       tm.mark(ST_POTRF);
       // a6: u = L^-1 d for every map, chi^2 = |u|^2
       for (int j = 0; j < b; ++j)
         CF_DEV(hipMemcpyAsync(Yb + (size_t)j * n * nmaps, D, sizeof(double) * n * nmaps,
                               hipMemcpyDeviceToDevice, c.s));
-      CF_DEV(trsm_lower_f64(Cb, n, n, n * n, Linv, nblk * kNB * kNB, Yb, nmaps, n * nmaps, Gb, nmaps, n * nmaps, nmaps,
-                            0, b, c.s));
+      CF_DEV(trsm_lower_f64(F, Yb, nmaps, n * nmaps, Gb, nmaps, n * nmaps, nmaps, 0, c.s));
       CF_DEV(launch_colsumsq(Gb, n, nmaps, nmaps, n * nmaps, b, x2, nmaps, c.s));
       CF_DEV(launch_sum_parts(ldp, (int)nblk, nblk, b, ldb, 1, c.s));
       CF_DEV(launch_scan_finish(x2, ldb, b, nmaps, i0, p, nprob, m2_dev, chi2_dev, ld_dev, c.s));

@@ -68,21 +68,41 @@ struct GemmDesc {
   double* C; int64_t ldc;
   double alpha, beta;
   int lower;                              // skip output tiles strictly above the diagonal
+  int64_t diag_off;                       // with lower: the diagonal is col = row + diag_off
   int batch; int64_t sA, sB, sC;          // batch count and element strides
 };
 hipError_t gemm_f64(const GemmDesc& g, hipStream_t s);
 
-// Cholesky of the n x n lower triangle (row-major, ld) in place, batched with stride.
-// Linv[nblocks][64][64] receives the inverses of the 64 x 64 diagonal blocks of L, ldpart[nblocks]
-// the per-block sums of ln L_ii, fail the first non-positive pivot (atomicMin; initialise INT_MAX).
-hipError_t potrf_f64(double* A, int64_t n, int64_t lda, int64_t sA, int batch, double* Linv,
-                     int64_t sLi, double* ldpart, int64_t sL, int* fail, hipStream_t s);
+// A (batched) Cholesky factor with the inverses of its diagonal blocks.
+struct Factor {
+  double* L = nullptr; int64_t n = 0, ld = 0, sL = 0;   // row-major, lower; batch stride sL
+  double* Li64 = nullptr; int64_t sLi64 = 0;           // [ceil(n/64)][64][64] inverted 64-blocks
+  double* Li256 = nullptr; int64_t sLi256 = 0;         // [n/256][256][256] inverted full 256-blocks (nullable)
+  double* ldpart = nullptr; int64_t sPart = 0;         // [ceil(n/64)] per-block sums of ln L_ii
+  int* fail = nullptr;                                 // first non-positive pivot (atomicMin)
+  int batch = 1;
+};
+// Streams for the factorisation: s carries the critical path (diagonal blocks, panels and the
+// lookahead column update), s1 the bulk trailing updates, s2 the 256-block inverses.
+struct Streams {
+  hipStream_t s, s1, s2;
+  hipEvent_t eL, eB, eI;
+};
+// Scratch for the 256-block inverses: batch * (2*64*64 + 128*128) doubles.
+inline int64_t potrf_scratch(int batch) { return (int64_t)batch * (2 * 64 * 64 + 128 * 128); }
+// Factor F.L in place (right-looking, lookahead of one 256-column panel); on return every stream
+// of st has been joined into st.s.
+hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st);
 
 // Forward substitution G = L^-1 Y for rows [r0, n) (rows of Y below r0 are taken as zero;
 // the solve starts at the 64-row block holding r0).  Y (n x ncol, ldy) is consumed as workspace.
-hipError_t trsm_lower_f64(const double* L, int64_t n, int64_t ldl, int64_t sL, const double* Linv,
-                          int64_t sLi, double* Y, int64_t ldy, int64_t sY, double* G, int64_t ldg,
-                          int64_t sG, int64_t ncol, int64_t r0, int batch, hipStream_t s);
+hipError_t trsm_lower_f64(const Factor& F, double* Y, int64_t ldy, int64_t sY, double* G, int64_t ldg,
+                          int64_t sG, int64_t ncol, int64_t r0, hipStream_t s);
+
+// W[j][m] = sum_{i < K} A[i][j] U[i][m] for skinny U (nmaps <= 8): partial sums over 32 row chunks
+// in `part` ([32][M][nmaps]) reduced in a fixed order.
+hipError_t gemv_tn(const double* A, int64_t lda, int64_t M, int64_t K, const double* U, int nmaps,
+                   double* W, int64_t ldw, double* part, hipStream_t s);
 
 // ---------------------------------------------------------------- harmonic basis
 hipError_t launch_ybuild(const DevProblem& P, double* Y, int64_t ldy, hipStream_t s);

@@ -166,36 +166,49 @@ __global__ void k_fisher_assemble(GramView G, int ns, int s0, int s1, int s2, in
   F[idx] = 0.5 * sum;
 }
 
-__global__ void k_bias_assemble(GramView G, const double* ztr, int lmin, int lmax, int ns, int s0,
-                                int s1, int s2, int s3, int s4, int s5, int nb, const int* lo,
-                                const int* hi, const double* wl, const double* lam, double* bias) {
-  const int K = ns * nb;
-  const int A = blockIdx.x * blockDim.x + threadIdx.x;
-  if (A >= K) return;
+// One workgroup per parameter A: the (l, sigma, l', f, g) terms are spread over the threads and
+// reduced in a fixed order.
+__global__ __launch_bounds__(256) void k_bias_assemble(GramView G, const double* ztr, int lmin, int lmax,
+                                                       int ns, int s0, int s1, int s2, int s3, int s4,
+                                                       int s5, int nb, const int* lo, const int* hi,
+                                                       const double* wl, const double* lam,
+                                                       double* bias) {
+  __shared__ double red[256];
+  const int A = blockIdx.x;
   const int specs[6] = {s0, s1, s2, s3, s4, s5};
   const int sa = specs[A / nb], ba = A % nb;
   int xa, ya;
   spec_fields(sa, xa, ya);
-  const int L = lmax + 1;
-  const int nf = G.nf;
+  const int L = lmax + 1, nl = lmax - lmin + 1;
+  const int nf = G.nf, nff = nf * nf;
   const int npa = (xa == ya) ? 1 : 2;
-  double sum = 0.0;
-  for (int l = lo[ba]; l <= hi[ba]; ++l) {
-    double t = 0.0;
-    for (int u = 0; u < npa; ++u) {
-      const int a = (u ? ya : xa) - G.off, c = (u ? xa : ya) - G.off;
-      t += ztr[(l - lmin) * nf * nf + c * nf + a];
-      for (int lp = lmin; lp <= lmax; ++lp) {
-        for (int f = 0; f < nf; ++f)
-          for (int g = 0; g < nf; ++g) {
-            const double lv = lam[field_pair_spec(f + G.off, g + G.off) * L + lp];
-            if (lv != 0.0) t -= lv * G.get(l, lp, c, f, a, g);
-          }
-      }
-    }
-    sum = fma(wl[l], t, sum);
+  const int l0 = lo[ba], nlb = hi[ba] - lo[ba] + 1;
+  // term index t = ((lb * npa + u) * nl + lpi) * nff + fg ; plus the trace terms
+  const int nterm = nlb * npa * nl * nff;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < nterm; t += 256) {
+    const int fg = t % nff, r1 = t / nff;
+    const int lpi = r1 % nl, r2 = r1 / nl;
+    const int u = r2 % npa, lb = r2 / npa;
+    const int l = l0 + lb, lp = lmin + lpi;
+    const int f = fg / nf, g = fg % nf;
+    const double lv = lam[field_pair_spec(f + G.off, g + G.off) * L + lp];
+    if (lv == 0.0) continue;
+    const int a = (u ? ya : xa) - G.off, c = (u ? xa : ya) - G.off;
+    acc -= wl[l] * lv * G.get(l, lp, c, f, a, g);
   }
-  bias[A] = 0.5 * sum;
+  for (int t = threadIdx.x; t < nlb * npa; t += 256) {
+    const int u = t % npa, lb = t / npa, l = l0 + lb;
+    const int a = (u ? ya : xa) - G.off, c = (u ? xa : ya) - G.off;
+    acc += wl[l] * ztr[(l - lmin) * nff + c * nf + a];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bias[A] = 0.5 * red[0];
 }
 
 // y[map][A] = 1/2 sum_{l in b} W_l sum_{(a,c) in sigma} sum_m w[a,l,m] w[c,l,m];  w is [k][ldw].
@@ -227,50 +240,58 @@ __global__ void k_quad_assemble(const double* w, int64_t ldw, int nmaps, int lmi
 }
 
 // Single-workgroup Cholesky solve of a small SPD system: F (k x k, overwritten with its factor),
-// right-hand sides R [nrhs][k] -> X [nrhs][k].
+// right-hand sides R [nrhs][k] -> X [nrhs][k].  The factorisation is right-looking with one
+// barrier per column (threads on a 32 x 32 grid of row/column strides); the substitutions run one
+// right-hand side per wave with the dot products reduced across the wave.
 __global__ __launch_bounds__(1024) void k_small_spd_solve(double* F, int k, const double* R, double* X,
                                                           int nrhs, int* fail) {
-  const int tid = threadIdx.x;
+  __shared__ double xs[16][1024];
+  const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
   for (int j = 0; j < k; ++j) {
     const double d = F[j * k + j];
-    const int m = k - j - 1;
-    if (m > 0) {
-      const double inv = 1.0 / d;
-      for (int idx = tid; idx < m * m; idx += blockDim.x) {
-        int r = j + 1 + idx / m, q = j + 1 + idx % m;
-        if (q <= r) F[r * k + q] -= F[r * k + j] * F[q * k + j] * inv;
-      }
+    const double inv = 1.0 / d;
+    for (int r = j + 1 + ty; r < k; r += 32) {
+      const double fr = F[r * k + j] * inv;
+      for (int q = j + 1 + tx; q <= r; q += 32) F[r * k + q] -= fr * F[q * k + j];
     }
     __syncthreads();
   }
-  // scale: L[r][q] = a[r][q] / sqrt(a[q][q]) (a[q][q] are the pivots)
   for (int idx = tid; idx < k * k; idx += blockDim.x) {
-    int r = idx / k, q = idx % k;
+    const int r = idx / k, q = idx % k;
     if (q < r) F[r * k + q] /= sqrt(F[q * k + q]);
   }
   __syncthreads();
   if (tid == 0) {
     for (int j = 0; j < k; ++j) {
-      double d = F[j * k + j];
+      const double d = F[j * k + j];
       if (!(d > 0.0) || !isfinite(d)) { atomicMin(fail, j); break; }
     }
   }
   __syncthreads();
   for (int idx = tid; idx < k; idx += blockDim.x) F[idx * k + idx] = sqrt(F[idx * k + idx]);
   __syncthreads();
-  for (int r = tid; r < nrhs; r += blockDim.x) {
-    const double* b = R + (int64_t)r * k;
-    double* x = X + (int64_t)r * k;
-    for (int i = 0; i < k; ++i) {          // L y = b
-      double s = b[i];
-      for (int q = 0; q < i; ++q) s -= F[i * k + q] * x[q];
-      x[i] = s / F[i * k + i];
+  const int wave = tid >> 6, lane = tid & 63;
+  double* x = xs[wave];
+  for (int rr = wave; rr < nrhs; rr += 16) {
+    const double* b = R + (int64_t)rr * k;
+    for (int i = 0; i < k; ++i) {            // L y = b
+      double p = 0.0;
+      for (int q = lane; q < i; q += 64) p = fma(F[i * k + q], x[q], p);
+      for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o);
+      if (lane == 0) x[i] = (b[i] - p) / F[i * k + i];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     }
-    for (int i = k - 1; i >= 0; --i) {     // L^T x = y
-      double s = x[i];
-      for (int q = i + 1; q < k; ++q) s -= F[q * k + i] * x[q];
-      x[i] = s / F[i * k + i];
+    for (int i = k - 1; i >= 0; --i) {       // L^T x = y
+      double p = 0.0;
+      for (int q = i + 1 + lane; q < k; q += 64) p = fma(F[q * k + i], x[q], p);
+      for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o);
+      if (lane == 0) x[i] = (x[i] - p) / F[i * k + i];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     }
+    for (int i = lane; i < k; i += 64) X[(int64_t)rr * k + i] = x[i];
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -336,6 +357,37 @@ __global__ void k_scan_finish(const double* chi2b, const double* ldb, int B, int
   if (logdet && j == 0) logdet[row] = l;
 }
 
+// Skinny A^T U: part[chunk][j][m] = sum over the chunk's rows i of A[i][j] U[i][m].
+template <int NM>
+__global__ __launch_bounds__(256) void k_gemv_tn_part(const double* __restrict__ A, int64_t lda, int64_t M,
+                                                      int64_t K, const double* __restrict__ U,
+                                                      double* __restrict__ part, int64_t rows_per) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * rows_per;
+  const int64_t i1 = (i0 + rows_per < K) ? i0 + rows_per : K;
+  double acc[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) acc[m] = 0.0;
+  if (j < M) {
+    for (int64_t i = i0; i < i1; ++i) {
+      const double a = A[i * lda + j];
+#pragma unroll
+      for (int m = 0; m < NM; ++m) acc[m] = fma(a, U[i * NM + m], acc[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < NM; ++m) part[((int64_t)blockIdx.y * M + j) * NM + m] = acc[m];
+  }
+}
+__global__ void k_gemv_tn_reduce(const double* part, int64_t M, int nm, int nchunk, double* W, int64_t ldw) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * nm) return;
+  const int64_t j = idx / nm;
+  const int m = (int)(idx % nm);
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[((int64_t)c * M + j) * nm + m];
+  W[j * ldw + m] = s;
+}
+
 __global__ void k_fill(double* p, int64_t n, double v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -390,7 +442,7 @@ hipError_t launch_fisher_assemble(const DevProblem& P, const SpecSel& S, const d
 hipError_t launch_bias_assemble(const DevProblem& P, const SpecSel& S, const double* gram,
                                 const double* ztr, double* bias, hipStream_t s) {
   const int K = S.ns * S.nb;
-  hipLaunchKernelGGL(k_bias_assemble, dim3(blocks(K, 64)), dim3(64), 0, s, make_view(P, gram), ztr,
+  hipLaunchKernelGGL(k_bias_assemble, dim3(K), dim3(256), 0, s, make_view(P, gram), ztr,
                      P.lmin, P.lmax, S.ns, S.spec[0], S.spec[1], S.spec[2], S.spec[3], S.spec[4],
                      S.spec[5], S.nb, S.lo, S.hi, P.wl, P.lam, bias);
   return hipGetLastError();
@@ -447,6 +499,22 @@ hipError_t launch_scan_finish(const double* chi2b, const double* ldb, int B, int
                               hipStream_t s) {
   hipLaunchKernelGGL(k_scan_finish, dim3(blocks((int64_t)B * nmaps, 256)), dim3(256), 0, s, chi2b, ldb,
                      B, nmaps, i0, prob, nprob, m2, chi2, logdet);
+  return hipGetLastError();
+}
+
+hipError_t gemv_tn(const double* A, int64_t lda, int64_t M, int64_t K, const double* U, int nmaps,
+                   double* W, int64_t ldw, double* part, hipStream_t s) {
+  constexpr int NCH = 32;
+  const int64_t rows_per = (K + NCH - 1) / NCH;
+  dim3 grid(blocks(M, 256), NCH);
+  switch (nmaps) {
+#define CF_GV(NMv) case NMv: hipLaunchKernelGGL(k_gemv_tn_part<NMv>, grid, dim3(256), 0, s, A, lda, M, K, U, part, rows_per); break;
+    CF_GV(1) CF_GV(2) CF_GV(3) CF_GV(4) CF_GV(5) CF_GV(6) CF_GV(7) CF_GV(8)
+#undef CF_GV
+    default: return hipErrorInvalidValue;
+  }
+  CF_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_gemv_tn_reduce, dim3(blocks(M * nmaps, 256)), dim3(256), 0, s, part, M, nmaps, NCH, W, ldw);
   return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ struct GemmArgs {
   double* C; int64_t ldc;
   double alpha, beta;
   int lower;
+  int64_t diag_off;
   int64_t sA, sB, sC;
   int tiles_n;
 };
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   const int wr = wave >> 1, wc = wave & 1;
   const int tile_m = blockIdx.x / g.tiles_n, tile_n = blockIdx.x % g.tiles_n;
   const int64_t i0 = (int64_t)tile_m * BM, j0 = (int64_t)tile_n * BN;
-  if (g.lower && j0 >= i0 + BM) return;            // tile strictly above the diagonal
+  if (g.lower && j0 >= i0 + g.diag_off + BM) return;   // tile strictly above the diagonal
   const int64_t z = blockIdx.z;
   const double* A = g.A + z * g.sA;
   const double* B = g.B + z * g.sB;
@@ -162,7 +163,7 @@ hipError_t launch_tile(const GemmDesc& d, hipStream_t s) {
   GemmArgs g;
   g.M = d.M; g.N = d.N; g.K = d.K;
   g.A = d.A; g.lda = d.lda; g.B = d.B; g.ldb = d.ldb; g.C = d.C; g.ldc = d.ldc;
-  g.alpha = d.alpha; g.beta = d.beta; g.lower = d.lower;
+  g.alpha = d.alpha; g.beta = d.beta; g.lower = d.lower; g.diag_off = d.diag_off;
   g.sA = d.sA; g.sB = d.sB; g.sC = d.sC;
   const int64_t tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
   g.tiles_n = (int)tn;

@@ -15,14 +15,22 @@ namespace {
 constexpr int NB = kNB;          // 64
 constexpr int OUTER = 256;       // outer panel width
 
-// Factor the b x b (b <= 64) diagonal block at (c, c) and invert the factor.
-// 256 threads in a 16 x 16 grid; thread (ty, tx) keeps the 4 x 4 sub-block rows 4ty.., columns
-// 4tx.. in registers.  Column j of the right-looking factorisation is published through LDS
-// (double-buffered, one barrier per column) and applied as a rank-1 update with the unscaled
-// column, a_rq -= a_rj a_qj / a_jj.  The inverse X = L^-1 then follows by the same scheme, row k
-// of X and column k of L published per step.  Rows and columns beyond b are padded with the
-// identity.  Outputs: L11 (lower) in place, L11^-1 as a full 64 x 64 block, the block's
-// sum of ln L_jj, and the first non-positive pivot.
+// Factor the b x b (b <= 64) diagonal block at (c, c) and invert the factor in the same sweep.
+// 256 threads on a 16 x 16 grid; thread (ty, tx) keeps the 4 x 4 sub-block (rows 4ty.., columns
+// 4tx..) of the matrix A and of X = L^-1 in registers.  Step j publishes, behind one barrier,
+// column j of A (unscaled) and row j of X (already scaled by 1/L_jj); then
+//   A: a_rq -= a_rj a_qj / a_jj      (q > j, right-looking Cholesky with the unscaled column)
+//   X: x_r. -= (a_rj / L_jj) x_j.    (r > j, right-looking forward substitution on the identity)
+// Both updates only need column j, final at step j, so factorisation and inversion share their
+// 64 barriers.  Reciprocals use the hardware estimate refined by two Newton steps.  Rows and
+// columns beyond b are padded with the identity.  Outputs: L11 (lower) in place, L11^-1 as a full
+// 64 x 64 block, the block's sum of ln L_jj and the first non-positive pivot.
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
 __global__ __launch_bounds__(256) void k_potrf_diag(double* A_base, int64_t lda, int64_t sA, int64_t c,
                                                     int b, double* Li_base, int64_t sLi,
                                                     double* ldpart_base, int64_t sL, int blk,
@@ -30,102 +38,77 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A_base, int64_t lda,
   __shared__ double colb[2][NB];
   __shared__ double rowb[2][NB];
   __shared__ double piv[NB];
-  __shared__ double rsq[NB];
   __shared__ double lg[NB];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   double* A = A_base + blockIdx.z * sA + c * lda + c;
-  double a[4][4];
+  double a[4][4], x[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int r = 4 * ty + i, q = 4 * tx + j;
       a[i][j] = (r < b && q < b) ? (q <= r ? A[r * lda + q] : 0.0) : (r == q ? 1.0 : 0.0);
+      x[i][j] = (r == q) ? 1.0 : 0.0;
     }
-  // ---- factorisation; the masks (row > j, column > j) are applied as factors, not branches
   for (int j4 = 0; j4 < NB; j4 += 4) {
 #pragma unroll
     for (int jj0 = 0; jj0 < 4; ++jj0) {
       const int j = j4 + jj0, buf = j & 1;
-      if (tx == (j4 >> 2)) {
+      const bool own_col = (tx == (j4 >> 2)), own_row = (ty == (j4 >> 2));
+      if (own_col) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) colb[buf][4 * ty + i] = a[i][jj0];
       }
+      if (own_row) {   // row j of X: complete except for its scaling by 1/L_jj
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) rowb[buf][4 * tx + jj] = x[jj0][jj];
+      }
       __syncthreads();
       const double d = colb[buf][j];
+      const double inv = rcp_nr(d);
+      const double rs = rcp_nr(sqrt(d));                 // 1 / L_jj
       if (tid == 0) piv[j] = d;
-      const double inv = 1.0 / d;
-      double cr[4], cq[4];
+      if (own_row) {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) x[jj0][jj] *= rs;
+      }
+      double cr[4], cq[4], xr[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        cr[i] = (4 * ty + i > j) ? colb[buf][4 * ty + i] * inv : 0.0;
-        cq[i] = (4 * tx + i > j) ? colb[buf][4 * tx + i] : 0.0;
+        cr[i] = (4 * ty + i > j) ? colb[buf][4 * ty + i] : 0.0;   // a_rj, rows below j
+        cq[i] = (4 * tx + i > j) ? colb[buf][4 * tx + i] : 0.0;   // a_qj, columns right of j
+        xr[i] = rowb[buf][4 * tx + i] * rs;                       // row j of X
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i) {
+        const double f = cr[i] * inv, l = cr[i] * rs;
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) a[i][jj] = fma(-cr[i], cq[jj], a[i][jj]);
+        for (int jj = 0; jj < 4; ++jj) {
+          a[i][jj] = fma(-f, cq[jj], a[i][jj]);
+          x[i][jj] = fma(-l, xr[jj], x[i][jj]);
+        }
+      }
     }
   }
   __syncthreads();
-  if (tid < NB) {
-    const double d = piv[tid];
-    rsq[tid] = 1.0 / sqrt(d);
-    lg[tid] = (tid < b) ? 0.5 * log(d) : 0.0;
-  }
-  __syncthreads();
-  // ---- scale to L and write it back
-  double l[4][4];
+  if (tid < NB) lg[tid] = (tid < b) ? 0.5 * log(piv[tid]) : 0.0;
+  // scale the stored columns: L_rq = a_rq / sqrt(a_qq) below the diagonal, sqrt(a_qq) on it
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
       const int r = 4 * ty + i, q = 4 * tx + jj;
-      l[i][jj] = (q < r) ? a[i][jj] * rsq[q] : (q == r ? sqrt(piv[q]) : 0.0);
-      if (r < b && q < b && q <= r) A[r * lda + q] = l[i][jj];
+      const double sq = sqrt(piv[q]);
+      const double l = (q < r) ? a[i][jj] / sq : sq;
+      if (r < b && q < b && q <= r) A[r * lda + q] = l;
     }
-  // ---- X = L^-1 (right-looking forward substitution on the identity)
-  double x[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) x[i][jj] = (4 * ty + i == 4 * tx + jj) ? 1.0 : 0.0;
-  for (int k4 = 0; k4 < NB; k4 += 4) {
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int k = k4 + kk, buf = k & 1;
-      if (ty == (k4 >> 2)) {
-        const double dk = rsq[k];
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          x[kk][jj] *= dk;
-          rowb[buf][4 * tx + jj] = x[kk][jj];
-        }
-      }
-      if (tx == (k4 >> 2)) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) colb[buf][4 * ty + i] = l[i][kk];
-      }
-      __syncthreads();
-      double lr[4], xk[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        lr[i] = (4 * ty + i > k) ? colb[buf][4 * ty + i] : 0.0;
-        xk[i] = rowb[buf][4 * tx + i];
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) x[i][jj] = fma(-lr[i], xk[jj], x[i][jj]);
-    }
-  }
   double* Li = Li_base + blockIdx.z * sLi + (int64_t)blk * NB * NB;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) Li[(4 * ty + i) * NB + 4 * tx + jj] = x[i][jj];
+  __syncthreads();
   if (tid == 0) {
-    // fixed-order sum of the block's ln L_jj; first non-positive pivot
     double acc = 0.0;
     int bad = INT_MAX;
     for (int j = 0; j < b; ++j) {
@@ -140,93 +123,178 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A_base, int64_t lda,
 
 }  // namespace
 
-hipError_t potrf_f64(double* A, int64_t n, int64_t lda, int64_t sA, int batch, double* Linv,
-                     int64_t sLi, double* ldpart, int64_t sL, int* fail, hipStream_t s) {
+namespace {
+
+// Li256 block p: the four inverted 64-blocks on the diagonal, zeros elsewhere.
+__global__ void k_tri256_init(const double* Li64_base, int64_t sLi64, double* Li256_base, int64_t sLi256,
+                              int p) {
+  const double* Li64 = Li64_base + blockIdx.z * sLi64 + (int64_t)(4 * p) * NB * NB;
+  double* D = Li256_base + blockIdx.z * sLi256 + (int64_t)p * 256 * 256;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < 256 * 256; idx += gridDim.x * blockDim.x) {
+    const int r = idx >> 8, c = idx & 255;
+    const int br = r >> 6, bc = c >> 6;
+    D[idx] = (br == bc) ? Li64[(int64_t)br * NB * NB + (r & 63) * NB + (c & 63)] : 0.0;
+  }
+}
+
+hipError_t gemm_plain(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, int64_t sA,
+                      const double* B, int64_t ldb, int64_t sB, double* C, int64_t ldc, int64_t sC,
+                      double alpha, int batch, hipStream_t s) {
+  GemmDesc g{};
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.alpha = alpha; g.beta = 0.0; g.batch = batch; g.sA = sA; g.sB = sB; g.sC = sC;
+  return gemm_f64(g, s);
+}
+
+// Inverse of the full 256 x 256 diagonal block of panel p from its 64-block inverses:
+// [A 0; B C]^-1 = [A^-1 0; -C^-1 B A^-1  C^-1], applied at 128 and then at 256.
+hipError_t tri256(const Factor& F, int p, double* scratch, hipStream_t s) {
+  const int nb = F.batch;
+  const int64_t c = (int64_t)p * 256, ld = F.ld;
+  double* D = F.Li256 + (int64_t)p * 256 * 256;
+  hipLaunchKernelGGL(k_tri256_init, dim3(64, 1, nb), dim3(256), 0, s, F.Li64, F.sLi64, F.Li256, F.sLi256, p);
+  CF_HIP_TRY(hipGetLastError());
+  const int64_t sS = 2 * 64 * 64 + 128 * 128;
+  for (int h = 0; h < 2; ++h) {
+    const int64_t o = c + 128 * h;
+    const double* Bh = F.L + (o + 64) * ld + o;                        // L[o+64 : o+128, o : o+64]
+    const double* Ainv = D + (128 * h) * 256 + 128 * h;                // 64 x 64 at (128h, 128h)
+    const double* Cinv = D + (128 * h + 64) * 256 + 128 * h + 64;      // at (128h+64, 128h+64)
+    double* T = scratch + h * 64 * 64;
+    CF_HIP_TRY(gemm_plain(64, 64, 64, Bh, ld, F.sL, Ainv, 256, F.sLi256, T, 64, sS, 1.0, nb, s));
+    CF_HIP_TRY(gemm_plain(64, 64, 64, Cinv, 256, F.sLi256, T, 64, sS, D + (128 * h + 64) * 256 + 128 * h,
+                          256, F.sLi256, -1.0, nb, s));
+  }
+  const double* B2 = F.L + (c + 128) * ld + c;                         // L[c+128 : c+256, c : c+128]
+  double* T = scratch + 2 * 64 * 64;
+  CF_HIP_TRY(gemm_plain(128, 128, 128, B2, ld, F.sL, D, 256, F.sLi256, T, 128, sS, 1.0, nb, s));
+  CF_HIP_TRY(gemm_plain(128, 128, 128, D + 128 * 256 + 128, 256, F.sLi256, T, 128, sS, D + 128 * 256, 256,
+                        F.sLi256, -1.0, nb, s));
+  return hipSuccess;
+}
+
+GemmDesc upd(const Factor& F, int64_t r0, int64_t c0, int64_t M, int64_t N, int64_t k0, int64_t K) {
+  // C[r0.., c0..] -= L[r0.., k0..k0+K] L[c0.., k0..k0+K]^T  (lower tiles relative to the diagonal)
+  GemmDesc g{};
+  g.M = M; g.N = N; g.K = K;
+  g.A = F.L + r0 * F.ld + k0; g.lda = F.ld; g.at = 0;
+  g.B = F.L + c0 * F.ld + k0; g.ldb = F.ld; g.bt = 1;
+  g.C = F.L + r0 * F.ld + c0; g.ldc = F.ld;
+  g.alpha = -1.0; g.beta = 1.0; g.lower = 1; g.diag_off = c0 - r0;
+  g.batch = F.batch; g.sA = F.sL; g.sB = F.sL; g.sC = F.sL;
+  return g;
+}
+
+}  // namespace
+
+hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
+  const int64_t n = F.n, lda = F.ld;
   if (n <= 0) return hipSuccess;
-  const unsigned nb = batch > 0 ? batch : 1;
+  const unsigned nb = F.batch > 0 ? F.batch : 1;
+  hipStream_t s = st.s;
+  bool pending_b = false, pending_i = false;
   for (int64_t c = 0; c < n; c += OUTER) {
     const int64_t pe = (c + OUTER < n) ? c + OUTER : n;
+    // ---- critical path: the diagonal blocks and panels of this outer panel
     for (int64_t q = c; q < pe; q += NB) {
       const int b = (int)((n - q) < NB ? (n - q) : NB);
       const int blk = (int)(q / NB);
-      hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, nb), dim3(256), 0, s, A, lda, sA, q, b, Linv, sLi,
-                         ldpart, sL, blk, fail);
+      hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, nb), dim3(256), 0, s, F.L, lda, F.sL, q, b, F.Li64,
+                         F.sLi64, F.ldpart, F.sPart, blk, F.fail);
       CF_HIP_TRY(hipGetLastError());
       const int64_t below = n - (q + b);
       if (below <= 0) continue;
       {   // column panel below the block: X <- X L11^-T, in place (each tile owns its rows)
         GemmDesc g{};
         g.M = below; g.N = b; g.K = b;
-        g.A = A + (q + b) * lda + q; g.lda = lda; g.at = 0;
-        g.B = Linv + (int64_t)blk * NB * NB; g.ldb = NB; g.bt = 1;
-        g.C = A + (q + b) * lda + q; g.ldc = lda;
+        g.A = F.L + (q + b) * lda + q; g.lda = lda; g.at = 0;
+        g.B = F.Li64 + (int64_t)blk * NB * NB; g.ldb = NB; g.bt = 1;
+        g.C = F.L + (q + b) * lda + q; g.ldc = lda;
         g.alpha = 1.0; g.beta = 0.0; g.lower = 0;
-        g.batch = nb; g.sA = sA; g.sB = sLi; g.sC = sA;
+        g.batch = nb; g.sA = F.sL; g.sB = F.sLi64; g.sC = F.sL;
         CF_HIP_TRY(gemm_f64(g, s));
       }
-      if (q + b < pe) {   // rest of the outer panel
-        GemmDesc g{};
-        g.M = below; g.N = pe - (q + b); g.K = b;
-        g.A = A + (q + b) * lda + q; g.lda = lda; g.at = 0;
-        g.B = A + (q + b) * lda + q; g.ldb = lda; g.bt = 1;
-        g.C = A + (q + b) * lda + (q + b); g.ldc = lda;
-        g.alpha = -1.0; g.beta = 1.0; g.lower = 1;
-        g.batch = nb; g.sA = sA; g.sB = sA; g.sC = sA;
-        CF_HIP_TRY(gemm_f64(g, s));
-      }
+      if (q + b < pe) CF_HIP_TRY(gemm_f64(upd(F, q + b, q + b, below, pe - (q + b), q, b), s));
     }
-    if (pe < n) {           // trailing matrix
-      GemmDesc g{};
-      g.M = n - pe; g.N = n - pe; g.K = pe - c;
-      g.A = A + pe * lda + c; g.lda = lda; g.at = 0;
-      g.B = A + pe * lda + c; g.ldb = lda; g.bt = 1;
-      g.C = A + pe * lda + pe; g.ldc = lda;
-      g.alpha = -1.0; g.beta = 1.0; g.lower = 1;
-      g.batch = nb; g.sA = sA; g.sB = sA; g.sC = sA;
-      CF_HIP_TRY(gemm_f64(g, s));
+    CF_HIP_TRY(hipEventRecord(st.eL, s));
+    // ---- 256-block inverse for the solves (side stream)
+    if (F.Li256 && pe - c == OUTER) {
+      CF_HIP_TRY(hipStreamWaitEvent(st.s2, st.eL, 0));
+      CF_HIP_TRY(tri256(F, (int)(c / OUTER), scratch, st.s2));
+      pending_i = true;
     }
+    if (pe >= n) break;
+    const int64_t pn = (pe + OUTER < n) ? pe + OUTER : n;    // end of the next panel
+    // ---- lookahead: the next panel's columns on the critical path, after the previous bulk update
+    if (pending_b) CF_HIP_TRY(hipStreamWaitEvent(s, st.eB, 0));
+    CF_HIP_TRY(gemm_f64(upd(F, pe, pe, n - pe, pn - pe, c, pe - c), s));
+    // ---- bulk trailing update beyond the next panel (side stream, overlaps the next panel)
+    if (pn < n) {
+      CF_HIP_TRY(hipStreamWaitEvent(st.s1, st.eL, 0));
+      CF_HIP_TRY(gemm_f64(upd(F, pn, pn, n - pn, n - pn, c, pe - c), st.s1));
+      CF_HIP_TRY(hipEventRecord(st.eB, st.s1));
+      pending_b = true;
+    }
+  }
+  if (pending_b) CF_HIP_TRY(hipStreamWaitEvent(s, st.eB, 0));
+  if (pending_i) {
+    CF_HIP_TRY(hipEventRecord(st.eI, st.s2));
+    CF_HIP_TRY(hipStreamWaitEvent(s, st.eI, 0));
   }
   return hipSuccess;
 }
 
 namespace {
-// Leaves: G[r0:r0+b] = L11^-1 Y[r0:r0+b] (GEMM with the inverted diagonal block); interior
-// nodes: Y[mid:r1] -= L[mid:r1, r0:mid] G[r0:mid].
-hipError_t trsm_rec(const double* L, int64_t ldl, int64_t sL, const double* Linv, int64_t sLi,
-                    double* Y, int64_t ldy, int64_t sY, double* G, int64_t ldg, int64_t sG,
-                    int64_t ncol, int64_t r0, int64_t r1, int batch, hipStream_t s) {
-  if (r1 - r0 <= NB) {
+// Leaves multiply by an inverted diagonal block (256 rows when an aligned full 256-block inverse
+// exists, else 64); interior nodes are GEMM updates Y[mid:r1] -= L[mid:r1, r0:mid] G[r0:mid].
+hipError_t trsm_rec(const Factor& F, double* Y, int64_t ldy, int64_t sY, double* G, int64_t ldg,
+                    int64_t sG, int64_t ncol, int64_t r0, int64_t r1, hipStream_t s) {
+  const int batch = F.batch > 0 ? F.batch : 1;
+  const bool leaf256 = F.Li256 && (r0 % 256) == 0 && r1 - r0 == 256;
+  if (r1 - r0 <= NB || leaf256) {
+    const int64_t m = r1 - r0;
     GemmDesc g{};
-    g.M = r1 - r0; g.N = ncol; g.K = r1 - r0;
-    g.A = Linv + (r0 / NB) * NB * NB; g.lda = NB; g.at = 0;
+    g.M = m; g.N = ncol; g.K = m;
+    if (leaf256) { g.A = F.Li256 + (r0 / 256) * 256 * 256; g.lda = 256; g.sA = F.sLi256; }
+    else { g.A = F.Li64 + (r0 / NB) * NB * NB; g.lda = NB; g.sA = F.sLi64; }
+    g.at = 0;
     g.B = Y + r0 * ldy; g.ldb = ldy; g.bt = 0;
     g.C = G + r0 * ldg; g.ldc = ldg;
     g.alpha = 1.0; g.beta = 0.0; g.lower = 0;
-    g.batch = batch; g.sA = sLi; g.sB = sY; g.sC = sG;
+    g.batch = batch; g.sB = sY; g.sC = sG;
     return gemm_f64(g, s);
   }
-  int64_t nblk = (r1 - r0 + NB - 1) / NB;
-  int64_t mid = r0 + ((nblk + 1) / 2) * NB;
-  CF_HIP_TRY(trsm_rec(L, ldl, sL, Linv, sLi, Y, ldy, sY, G, ldg, sG, ncol, r0, mid, batch, s));
+  int64_t mid;
+  const int64_t up = ((r0 + 255) / 256) * 256;
+  if (F.Li256 && r0 % 256 != 0 && up < r1) {
+    mid = up;                                    // reach a 256-aligned row first
+  } else if (F.Li256 && r0 % 256 == 0 && r1 - r0 > 256) {
+    const int64_t n256 = (r1 - r0 + 255) / 256;
+    mid = r0 + ((n256 + 1) / 2) * 256;
+    if (mid >= r1) mid = r0 + 256;
+  } else {
+    const int64_t nblk = (r1 - r0 + NB - 1) / NB;
+    mid = r0 + ((nblk + 1) / 2) * NB;
+  }
+  CF_HIP_TRY(trsm_rec(F, Y, ldy, sY, G, ldg, sG, ncol, r0, mid, s));
   GemmDesc g{};
   g.M = r1 - mid; g.N = ncol; g.K = mid - r0;
-  g.A = L + mid * ldl + r0; g.lda = ldl; g.at = 0;
+  g.A = F.L + mid * F.ld + r0; g.lda = F.ld; g.at = 0;
   g.B = G + r0 * ldg; g.ldb = ldg; g.bt = 0;
   g.C = Y + mid * ldy; g.ldc = ldy;
   g.alpha = -1.0; g.beta = 1.0; g.lower = 0;
-  g.batch = batch; g.sA = sL; g.sB = sG; g.sC = sY;
+  g.batch = batch; g.sA = F.sL; g.sB = sG; g.sC = sY;
   CF_HIP_TRY(gemm_f64(g, s));
-  return trsm_rec(L, ldl, sL, Linv, sLi, Y, ldy, sY, G, ldg, sG, ncol, mid, r1, batch, s);
+  return trsm_rec(F, Y, ldy, sY, G, ldg, sG, ncol, mid, r1, s);
 }
 }  // namespace
 
-hipError_t trsm_lower_f64(const double* L, int64_t n, int64_t ldl, int64_t sL, const double* Linv,
-                          int64_t sLi, double* Y, int64_t ldy, int64_t sY, double* G, int64_t ldg,
-                          int64_t sG, int64_t ncol, int64_t r0, int batch, hipStream_t s) {
-  if (ncol <= 0 || n <= 0) return hipSuccess;
-  int64_t start = (r0 / NB) * NB;
-  return trsm_rec(L, ldl, sL, Linv, sLi, Y, ldy, sY, G, ldg, sG, ncol, start, n,
-                  batch > 0 ? batch : 1, s);
+hipError_t trsm_lower_f64(const Factor& F, double* Y, int64_t ldy, int64_t sY, double* G, int64_t ldg,
+                          int64_t sG, int64_t ncol, int64_t r0, hipStream_t s) {
+  if (ncol <= 0 || F.n <= 0) return hipSuccess;
+  const int64_t start = (r0 / NB) * NB;
+  return trsm_rec(F, Y, ldy, sY, G, ldg, sG, ncol, start, F.n, s);
 }
 
 }  // namespace cf
