@@ -432,17 +432,18 @@ int read_flags(CallCtx& c, const int* dflags, int nflags, int* out) {
 
 // ------------------------------------------------------------------------------- Fisher core
 struct FisherBufs {
-  double *C, *Y, *G, *Z, *Linv, *Li256, *scratch, *ldpart, *gram, *ztr, *F;
+  double *C, *C0, *Y, *G, *Z, *Linv, *Li256, *scratch, *ldpart, *gram, *ztr, *F;
   int* lo;
   int* hi;
   int* flags;   // [0] non-finite covariance, [1] first failing pivot, [2] F pivot failure
 };
 
-size_t fisher_ws(const HostProblem& H, const HostBins& B, Sizer& z) {
+size_t fisher_ws(const HostProblem& H, const HostBins& B, Sizer& z, int mode) {
   const int nl = H.lmax - H.lmin + 1;
   const int np = H.nfm * H.nfm, nq = np * (np + 1) / 2;
   const int K = B.ns * B.nb;
   z.add<double>((size_t)H.n * H.n);
+  z.add<double>(mode ? (size_t)H.n * H.n : 1);
   z.add<double>((size_t)H.n * H.k);
   z.add<double>((size_t)H.n * H.k);
   z.add<double>((size_t)H.k * H.k);
@@ -459,11 +460,12 @@ size_t fisher_ws(const HostProblem& H, const HostBins& B, Sizer& z) {
   return z.off;
 }
 
-void fisher_take(Bump& bp, const HostProblem& H, const HostBins& B, FisherBufs& f) {
+void fisher_take(Bump& bp, const HostProblem& H, const HostBins& B, FisherBufs& f, int mode) {
   const int nl = H.lmax - H.lmin + 1;
   const int np = H.nfm * H.nfm, nq = np * (np + 1) / 2;
   const int K = B.ns * B.nb;
   f.C = bp.take<double>((size_t)H.n * H.n);
+  f.C0 = bp.take<double>(mode ? (size_t)H.n * H.n : 1);
   f.Y = bp.take<double>((size_t)H.n * H.k);
   f.G = bp.take<double>((size_t)H.n * H.k);
   f.Z = bp.take<double>((size_t)H.k * H.k);
@@ -479,7 +481,7 @@ void fisher_take(Bump& bp, const HostProblem& H, const HostBins& B, FisherBufs& 
   f.flags = bp.take<int>(8);
 }
 
-Factor make_factor(const FisherBufs& f, int64_t n) {
+Factor make_factor(const FisherBufs& f, int64_t n, int mode) {
   Factor F;
   F.L = f.C; F.n = n; F.ld = n; F.sL = 0;
   F.Li64 = f.Linv; F.sLi64 = 0;
@@ -487,6 +489,7 @@ Factor make_factor(const FisherBufs& f, int64_t n) {
   F.ldpart = f.ldpart; F.sPart = 0;
   F.fail = f.flags + 1;
   F.batch = 1;
+  F.mode = mode;
   return F;
 }
 
@@ -495,6 +498,8 @@ struct QmlBufs {
   const double* maps = nullptr;   // device [nmaps][n]
   int nmaps = 0;
   double *D = nullptr, *U = nullptr, *W = nullptr, *part = nullptr;
+  double *D0 = nullptr, *X = nullptr, *R = nullptr;   // mixed precision: d, C^-1 d, residual
+  int refine = 0;
 };
 
 // W (M x nmaps) = A^T U with A = rows [0, K) of a row-major matrix (ld lda) and U (K x nmaps):
@@ -515,7 +520,7 @@ hipError_t weighted_maps(const double* A, int64_t lda, int64_t M, int64_t K, con
 // aux[0] builds Y (concurrently with the factorisation) and then carries the E,B part; aux[1]
 // solves the maps.  Events order the hand-offs; everything is joined back into s.
 int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, FisherBufs& f,
-                QmlBufs* qb, CallCtx& cc, Timer& tm) {
+                QmlBufs* qb, CallCtx& cc, Timer& tm, int mode) {
   const DevProblem& P = S.P;
   const int64_t n = H.n, k = H.k;
   hipStream_t s = cc.s, s1 = cc.dev->aux[0], s2 = cc.dev->aux[1];
@@ -532,18 +537,38 @@ int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, F
   // s: covariance and Cholesky factor
   CF_DEV(launch_fill_int(f.flags, 1, 0, s));
   CF_DEV(launch_fill_int(f.flags + 1, 2, INT_MAX, s));
+  // the mixed path keeps the full FP64 covariance for its refinement residuals
   CF_DEV(launch_cov_build(P, S.cw, 0, 1, prob->noise_kind, S.noise, prob->noise_rank, S.noise_U, f.C, n,
-                          0, 1, f.flags, s));
+                          0, mode ? 0 : 1, f.flags, s));
+  if (mode) CF_DEV(hipMemcpyAsync(f.C0, f.C, sizeof(double) * n * n, hipMemcpyDeviceToDevice, s));
   tm.mark(ST_BUILD);
-  Factor F = make_factor(f, n);
+  Factor F = make_factor(f, n, mode);
   if (int st = potrf_on(*cc.dev, F, f.scratch, s, s2, ev + 8)) return st;
   tm.mark(ST_POTRF);
   CF_DEV(hipEventRecord(ev[E_L], s));
-  // aux[1]: u = L^-1 d for the maps
+  // aux[1]: u = L^-1 d for the maps (FP64); x = C^-1 d refined with FP64 residuals (mixed)
   if (qb) {
+    const int nm = qb->nmaps;
     CF_DEV(hipStreamWaitEvent(s2, ev[E_L], 0));
-    CF_DEV(launch_transpose(qb->maps, qb->nmaps, n, n, qb->D, qb->nmaps, s2));
-    CF_DEV(trsm_lower_f64(F, qb->D, qb->nmaps, 0, qb->U, qb->nmaps, 0, qb->nmaps, 0, s2));
+    CF_DEV(launch_transpose(qb->maps, nm, n, n, qb->D, nm, s2));
+    if (mode) {
+      CF_DEV(hipMemcpyAsync(qb->D0, qb->D, sizeof(double) * n * nm, hipMemcpyDeviceToDevice, s2));
+      CF_DEV(trsm_lower_f64(F, qb->D, nm, 0, qb->U, nm, 0, nm, 0, s2));
+      CF_DEV(trsm_lower_t_f64(F, qb->U, nm, 0, qb->X, nm, 0, nm, s2));
+      for (int it = 0; it < qb->refine; ++it) {
+        CF_DEV(hipMemcpyAsync(qb->R, qb->D0, sizeof(double) * n * nm, hipMemcpyDeviceToDevice, s2));
+        GemmDesc r{};
+        r.M = n; r.N = nm; r.K = n;
+        r.A = f.C0; r.lda = n; r.B = qb->X; r.ldb = nm; r.C = qb->R; r.ldc = nm;
+        r.alpha = -1.0; r.beta = 1.0; r.batch = 1;
+        CF_DEV(gemm_f64(r, s2));                                   // r = d - C x (FP64)
+        CF_DEV(trsm_lower_f64(F, qb->R, nm, 0, qb->U, nm, 0, nm, 0, s2));
+        CF_DEV(trsm_lower_t_f64(F, qb->U, nm, 0, qb->R, nm, 0, nm, s2));
+        CF_DEV(launch_axpy(qb->X, qb->R, 1.0, n * nm, s2));        // x += C~^-1 r
+      }
+    } else {
+      CF_DEV(trsm_lower_f64(F, qb->D, nm, 0, qb->U, nm, 0, nm, 0, s2));
+    }
   }
   const bool split = H.has_t && H.has_p;
   const int64_t kT = H.has_t ? H.kf : 0, kP = k - kT;
@@ -563,7 +588,7 @@ int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, F
     g.M = kT; g.N = kT; g.K = n;
     g.A = f.G; g.lda = k; g.at = 1;
     g.B = f.G; g.ldb = k; g.bt = 0;
-    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1;
+    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1; g.mode = mode;
     CF_DEV(gemm_f64(g, s));
     // Z rows of E,B against all columns (lower part), over rows >= p0 (aux[0])
     CF_DEV(hipStreamWaitEvent(s1, ev[E_T], 0));
@@ -572,12 +597,19 @@ int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, F
     h.A = f.G + p0 * k + kT; h.lda = k; h.at = 1;
     h.B = f.G + p0 * k; h.ldb = k; h.bt = 0;
     h.C = f.Z + kT * k; h.ldc = k; h.alpha = 1.0; h.beta = 0.0; h.lower = 1; h.diag_off = kT;
-    h.batch = 1;
+    h.batch = 1; h.mode = mode;
     hipEvent_t tz = tm.open(s1);
     CF_DEV(gemm_f64(h, s1));
     tm.close(ST_SYRK, tz, s1);
     CF_DEV(hipEventRecord(ev[E_S1], s1));
-    if (qb) {   // w = G^T u
+    if (qb && mode) {   // w = Y^T x with Y rebuilt (the solves consumed it)
+      CF_DEV(hipStreamWaitEvent(s2, ev[E_T], 0));
+      CF_DEV(hipStreamWaitEvent(s2, ev[E_EB], 0));
+      CF_DEV(launch_ybuild(P, f.Y, k, s2));
+      CF_DEV(weighted_maps(f.Y, k, k, n, qb->X, qb->nmaps, qb->W, qb->part, s2));
+      CF_DEV(hipEventRecord(ev[E_S2], s2));
+      CF_DEV(hipStreamWaitEvent(s, ev[E_S2], 0));
+    } else if (qb) {   // w = G^T u
       CF_DEV(hipStreamWaitEvent(s2, ev[E_T], 0));
       CF_DEV(hipStreamWaitEvent(s2, ev[E_EB], 0));
       CF_DEV(weighted_maps(f.G, k, kT, n, qb->U, qb->nmaps, qb->W, qb->part, s2));
@@ -595,11 +627,17 @@ int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, F
     g.M = k; g.N = k; g.K = n;
     g.A = f.G; g.lda = k; g.at = 1;
     g.B = f.G; g.ldb = k; g.bt = 0;
-    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1;
+    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1; g.mode = mode;
     hipEvent_t tz = tm.open(s);
     CF_DEV(gemm_f64(g, s));
     tm.close(ST_SYRK, tz, s);
-    if (qb) {
+    if (qb && mode) {
+      CF_DEV(hipStreamWaitEvent(s2, ev[E_T], 0));
+      CF_DEV(launch_ybuild(P, f.Y, k, s2));
+      CF_DEV(weighted_maps(f.Y, k, k, n, qb->X, qb->nmaps, qb->W, qb->part, s2));
+      CF_DEV(hipEventRecord(ev[E_S2], s2));
+      CF_DEV(hipStreamWaitEvent(s, ev[E_S2], 0));
+    } else if (qb) {
       CF_DEV(hipStreamWaitEvent(s2, ev[E_T], 0));
       CF_DEV(weighted_maps(f.G, k, k, n, qb->U, qb->nmaps, qb->W, qb->part, s2));
       CF_DEV(hipEventRecord(ev[E_S2], s2));
@@ -657,7 +695,7 @@ using namespace cf;
 extern "C" {
 
 const char* cf_last_error(void) { return g_err.c_str(); }
-const char* cf_version(void) { return "libcf 0.1 (gfx950, FP64 path)"; }
+const char* cf_version(void) { return "libcf 0.2 (gfx950; FP64, FP32-MFMA and split-BF16 mixed paths)"; }
 
 int64_t cf_problem_dim(const cf_problem* prob) {
   HostProblem H;
@@ -717,24 +755,25 @@ int cf_fisher(const cf_problem* prob, const cf_bins* bins, int32_t precision, do
   if (int st = check_problem(prob, H, true)) return st;
   HostBins B;
   if (int st = check_bins(bins, H, B)) return st;
-  if (precision != CF_FP64) return fail(CF_EINVAL, "precision %d not available in this build", precision);
+  if (precision < CF_FP64 || precision > CF_MIXED_BF16X3) return fail(CF_EINVAL, "unknown precision %d", precision);
+  const int mode = precision;
   if (!F_out) return fail(CF_EINVAL, "F_out is NULL");
   CallCtx c;
   if (int st = c.begin(ex)) return st;
   Sizer z;
   size_staging(z, prob, H);
-  fisher_ws(H, B, z);
+  fisher_ws(H, B, z, mode);
   if (int st = ensure_ws(*c.dev, z.off)) return st;
   Bump bp(c.dev->ws);
   Staged S;
   if (int st = stage(bp, prob, H, nullptr, c.s, S)) return st;
   FisherBufs f;
-  fisher_take(bp, H, B, f);
+  fisher_take(bp, H, B, f, mode);
   CF_DEV(hipMemcpyAsync(f.lo, B.lo.data(), sizeof(int) * B.nb, hipMemcpyHostToDevice, c.s));
   CF_DEV(hipMemcpyAsync(f.hi, B.hi.data(), sizeof(int) * B.nb, hipMemcpyHostToDevice, c.s));
   Timer tm;
   tm.begin(ex && ex->stage_timing, c.s);
-  if (int st = fisher_core(prob, H, S, f, nullptr, c, tm)) return st;
+  if (int st = fisher_core(prob, H, S, f, nullptr, c, tm, mode)) return st;
   const SpecSel sel = make_sel(B, f);
   CF_DEV(launch_fisher_assemble(S.P, sel, f.gram, f.F, c.s));
   tm.mark(ST_REDUCE);
@@ -757,7 +796,9 @@ int cf_qml(const cf_problem* prob, const cf_bins* bins, const double* maps, int3
   if (int st = check_problem(prob, H, true)) return st;
   HostBins B;
   if (int st = check_bins(bins, H, B)) return st;
-  if (precision != CF_FP64) return fail(CF_EINVAL, "precision %d not available in this build", precision);
+  if (precision < CF_FP64 || precision > CF_MIXED_BF16X3) return fail(CF_EINVAL, "unknown precision %d", precision);
+  const int mode = precision;
+  const int refine = (ex && ex->refine_max >= 0) ? ex->refine_max : (mode == 2 ? 3 : 2);
   if (nmaps <= 0 || !maps) return fail(CF_EINVAL, "no maps");
   if (!y_out || !bias_out || !chat_out) return fail(CF_EINVAL, "y_out, bias_out and chat_out are required");
   if (prob->mem == CF_MEM_HOST && !finite_all(maps, (int64_t)nmaps * H.n))
@@ -767,8 +808,9 @@ int cf_qml(const cf_problem* prob, const cf_bins* bins, const double* maps, int3
   const int K = B.ns * B.nb;
   Sizer z;
   size_staging(z, prob, H);
-  fisher_ws(H, B, z);
+  fisher_ws(H, B, z, mode);
   z.add<double>((size_t)nmaps * H.n);        // maps copy (host inputs)
+  z.add<double>((size_t)H.n * nmaps * 3);    // mixed: d, x, residual
   z.add<double>((size_t)H.n * nmaps);        // D = maps^T
   z.add<double>((size_t)H.n * nmaps);        // u = L^-1 D
   z.add<double>((size_t)H.k * nmaps);        // w = G^T u
@@ -783,8 +825,9 @@ int cf_qml(const cf_problem* prob, const cf_bins* bins, const double* maps, int3
   Staged S;
   if (int st = stage(bp, prob, H, nullptr, c.s, S)) return st;
   FisherBufs f;
-  fisher_take(bp, H, B, f);
+  fisher_take(bp, H, B, f, mode);
   double* mcopy = bp.take<double>((size_t)nmaps * H.n);
+  double* mix = bp.take<double>((size_t)H.n * nmaps * 3);
   double* D = bp.take<double>((size_t)H.n * nmaps);
   double* U = bp.take<double>((size_t)H.n * nmaps);
   double* W = bp.take<double>((size_t)H.k * nmaps);
@@ -805,7 +848,9 @@ int cf_qml(const cf_problem* prob, const cf_bins* bins, const double* maps, int3
   tm.begin(ex && ex->stage_timing, c.s);
   QmlBufs qb;
   qb.maps = mdev; qb.nmaps = nmaps; qb.D = D; qb.U = U; qb.W = W; qb.part = part;
-  if (int st = fisher_core(prob, H, S, f, &qb, c, tm)) return st;
+  qb.D0 = mix; qb.X = mix + (size_t)H.n * nmaps; qb.R = mix + (size_t)2 * H.n * nmaps;
+  qb.refine = refine;
+  if (int st = fisher_core(prob, H, S, f, &qb, c, tm, mode)) return st;
   const SpecSel sel = make_sel(B, f);
   CF_DEV(launch_fisher_assemble(S.P, sel, f.gram, f.F, c.s));
   CF_DEV(launch_bias_assemble(S.P, sel, f.gram, f.ztr, bias, c.s));
@@ -833,7 +878,7 @@ int cf_qml(const cf_problem* prob, const cf_bins* bins, const double* maps, int3
     if (int st = copy_out(F_out, f.F, (size_t)K * K, prob->mem, c.s)) return st;
   CF_DEV(hipStreamSynchronize(c.s));
   tm.finish(rep);
-  if (rep) { rep->n = H.n; rep->nmodes = H.k; rep->flops = fisher_flops(H); }
+  if (rep) { rep->n = H.n; rep->nmodes = H.k; rep->flops = fisher_flops(H); rep->ir_iters = mode ? refine : 0; }
   return CF_OK;
 }
 
@@ -848,7 +893,9 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   if (npoints <= 0 || !cl_points) return fail(CF_EINVAL, "no scan points");
   if (nmaps <= 0 || !maps) return fail(CF_EINVAL, "no maps");
   if (!m2lnL) return fail(CF_EINVAL, "m2lnL is NULL");
-  if (precision != CF_FP64) return fail(CF_EINVAL, "precision %d not available in this build", precision);
+  if (precision < CF_FP64 || precision > CF_MIXED_BF16X3) return fail(CF_EINVAL, "unknown precision %d", precision);
+  const int mode = precision;
+  const int refine = (ex && ex->refine_max >= 0) ? ex->refine_max : (mode == 2 ? 3 : 2);
   const int mem = probs[0].mem;
   std::vector<HostProblem> H(nprob);
   int lmax_all = 0;
@@ -870,7 +917,7 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   // batch of points factorised together, sized by the largest problem
   int nmax = 0;
   for (int p = 0; p < nprob; ++p) nmax = H[p].n > nmax ? H[p].n : nmax;
-  const size_t per = (size_t)nmax * nmax * 8;
+  const size_t per = (size_t)nmax * nmax * 8 * (mode ? 2 : 1);
   int Bt = (int)std::min<size_t>(16, std::max<size_t>(1, (size_t(6) << 30) / per));
   if (Bt > npoints) Bt = npoints;
   const int L = lmax_all + 1;
@@ -890,6 +937,9 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   z.add<double>((size_t)nmax * nmaps);                 // D
   z.add<double>((size_t)Bt * nmax * nmaps);            // Y copies
   z.add<double>((size_t)Bt * nmax * nmaps);            // G
+  z.add<double>(mode ? (size_t)Bt * nmax * nmax : 1);  // FP64 covariance copies (mixed)
+  z.add<double>(mode ? (size_t)Bt * nmax * nmaps : 1);  // x = C^-1 d (mixed)
+  z.add<double>(mode ? (size_t)Bt * nmax * nmaps : 1);  // residuals (mixed)
   z.add<double>((size_t)Bt * nmaps);                   // chi2 batch
   z.add<double>((size_t)Bt);                           // logdet batch
   z.add<int>(8);
@@ -924,6 +974,9 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   double* D = bp.take<double>((size_t)nmax * nmaps);
   double* Yb = bp.take<double>((size_t)Bt * nmax * nmaps);
   double* Gb = bp.take<double>((size_t)Bt * nmax * nmaps);
+  double* C0b = bp.take<double>(mode ? (size_t)Bt * nmax * nmax : 1);
+  double* Xb = bp.take<double>(mode ? (size_t)Bt * nmax * nmaps : 1);
+  double* Rb = bp.take<double>(mode ? (size_t)Bt * nmax * nmaps : 1);
   double* x2 = bp.take<double>((size_t)Bt * nmaps);
   double* ldb = bp.take<double>((size_t)Bt);
   int* flags = bp.take<int>(8);
@@ -946,7 +999,9 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
                            nullptr, c.s));
       // a3: covariance of every point in the batch (lower triangle)
       CF_DEV(launch_cov_build(S[p].P, cwb, 6 * (int64_t)Lp, b, probs[p].noise_kind, S[p].noise,
-                              probs[p].noise_rank, S[p].noise_U, Cb, n, n * n, 1, flags, c.s));
+                              probs[p].noise_rank, S[p].noise_U, Cb, n, n * n, mode ? 0 : 1, flags, c.s));
+      if (mode)
+        CF_DEV(hipMemcpyAsync(C0b, Cb, sizeof(double) * b * n * n, hipMemcpyDeviceToDevice, c.s));
       tm.mark(ST_BUILD);
       // a4: Cholesky and log det
       Factor F;
@@ -954,7 +1009,7 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
       F.Li64 = Linv; F.sLi64 = nblk * kNB * kNB;
       F.Li256 = (n >= 256) ? Li256 : nullptr; F.sLi256 = (n / 256) * 256 * 256;
       F.ldpart = ldp; F.sPart = nblk;
-      F.fail = flags + 1; F.batch = b;
+      F.fail = flags + 1; F.batch = b; F.mode = mode;
       if (int st = potrf_on(*c.dev, F, pscr, c.s, c.dev->aux[1], c.dev->ev + 8)) return st;
       tm.mark(ST_POTRF);
       // a6: u = L^-1 d for every map, chi^2 = |u|^2
@@ -962,7 +1017,26 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
         CF_DEV(hipMemcpyAsync(Yb + (size_t)j * n * nmaps, D, sizeof(double) * n * nmaps,
                               hipMemcpyDeviceToDevice, c.s));
       CF_DEV(trsm_lower_f64(F, Yb, nmaps, n * nmaps, Gb, nmaps, n * nmaps, nmaps, 0, c.s));
-      CF_DEV(launch_colsumsq(Gb, n, nmaps, nmaps, n * nmaps, b, x2, nmaps, c.s));
+      if (!mode) {
+        CF_DEV(launch_colsumsq(Gb, n, nmaps, nmaps, n * nmaps, b, x2, nmaps, c.s));
+      } else {
+        // x = C~^-1 d, then x += C~^-1 (d - C x) with the FP64 covariance; chi^2 = d^T x
+        CF_DEV(trsm_lower_t_f64(F, Gb, nmaps, n * nmaps, Xb, nmaps, n * nmaps, nmaps, c.s));
+        for (int it = 0; it < refine; ++it) {
+          for (int j = 0; j < b; ++j)
+            CF_DEV(hipMemcpyAsync(Rb + (size_t)j * n * nmaps, D, sizeof(double) * n * nmaps,
+                                  hipMemcpyDeviceToDevice, c.s));
+          GemmDesc r{};
+          r.M = n; r.N = nmaps; r.K = n;
+          r.A = C0b; r.lda = n; r.B = Xb; r.ldb = nmaps; r.C = Rb; r.ldc = nmaps;
+          r.alpha = -1.0; r.beta = 1.0; r.batch = b; r.sA = n * n; r.sB = n * nmaps; r.sC = n * nmaps;
+          CF_DEV(gemm_f64(r, c.s));
+          CF_DEV(trsm_lower_f64(F, Rb, nmaps, n * nmaps, Gb, nmaps, n * nmaps, nmaps, 0, c.s));
+          CF_DEV(trsm_lower_t_f64(F, Gb, nmaps, n * nmaps, Rb, nmaps, n * nmaps, nmaps, c.s));
+          CF_DEV(launch_axpy(Xb, Rb, 1.0, (int64_t)b * n * nmaps, c.s));
+        }
+        CF_DEV(launch_coldot(D, Xb, n, nmaps, nmaps, 0, n * nmaps, b, x2, nmaps, c.s));
+      }
       CF_DEV(launch_sum_parts(ldp, (int)nblk, nblk, b, ldb, 1, c.s));
       CF_DEV(launch_scan_finish(x2, ldb, b, nmaps, i0, p, nprob, m2_dev, chi2_dev, ld_dev, c.s));
       tm.mark(ST_TRSM);
@@ -985,6 +1059,6 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   }
   CF_DEV(hipStreamSynchronize(c.s));
   tm.finish(rep);
-  if (rep) { rep->flops = flops; rep->n = H[0].n; }
+  if (rep) { rep->flops = flops; rep->n = H[0].n; rep->ir_iters = mode ? refine : 0; }
   return CF_OK;
 }

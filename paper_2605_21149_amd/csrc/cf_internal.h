@@ -70,6 +70,7 @@ struct GemmDesc {
   int lower;                              // skip output tiles strictly above the diagonal
   int64_t diag_off;                       // with lower: the diagonal is col = row + diag_off
   int batch; int64_t sA, sB, sC;          // batch count and element strides
+  int mode;                               // 0 FP64 MFMA, 1 FP32 MFMA, 2 split-BF16 x3 MFMA
 };
 hipError_t gemm_f64(const GemmDesc& g, hipStream_t s);
 
@@ -81,6 +82,7 @@ struct Factor {
   double* ldpart = nullptr; int64_t sPart = 0;         // [ceil(n/64)] per-block sums of ln L_ii
   int* fail = nullptr;                                 // first non-positive pivot (atomicMin)
   int batch = 1;
+  int mode = 0;                                        // GEMM mode of the bulk updates and solves
 };
 // Streams for the factorisation: s carries the critical path (diagonal blocks, panels and the
 // lookahead column update), s1 the bulk trailing updates, s2 the 256-block inverses.
@@ -98,6 +100,10 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st);
 // the solve starts at the 64-row block holding r0).  Y (n x ncol, ldy) is consumed as workspace.
 hipError_t trsm_lower_f64(const Factor& F, double* Y, int64_t ldy, int64_t sY, double* G, int64_t ldg,
                           int64_t sG, int64_t ncol, int64_t r0, hipStream_t s);
+
+// Backward substitution X = L^-T B (B, n x ncol, consumed as workspace; result in X).
+hipError_t trsm_lower_t_f64(const Factor& F, double* B, int64_t ldb, int64_t sB, double* X, int64_t ldx,
+                            int64_t sX, int64_t ncol, hipStream_t s);
 
 // W[j][m] = sum_{i < K} A[i][j] U[i][m] for skinny U (nmaps <= 8): partial sums over 32 row chunks
 // in `part` ([32][M][nmaps]) reduced in a fixed order.
@@ -132,6 +138,9 @@ hipError_t launch_transpose(const double* A, int64_t rows, int64_t cols, int64_t
                             int64_t ldb, hipStream_t s);
 hipError_t launch_colsumsq(const double* U, int64_t rows, int64_t cols, int64_t ldu, int64_t sU,
                            int batch, double* out, int64_t sOut, hipStream_t s);
+hipError_t launch_coldot(const double* U, const double* V, int64_t rows, int64_t cols, int64_t ld,
+                         int64_t sU, int64_t sV, int batch, double* out, int64_t sOut, hipStream_t s);
+hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s);
 hipError_t launch_sum_parts(const double* parts, int nparts, int64_t sP, int batch, double* out,
                             int64_t sOut, hipStream_t s);
 hipError_t launch_add_scalar(const double* vec, int64_t nper, int batch, const double* scal,

@@ -324,6 +324,29 @@ __global__ __launch_bounds__(256) void k_colsumsq(const double* U, int64_t rows,
   if (threadIdx.x == 0) out[blockIdx.z * sOut + j] = red[0];
 }
 
+// out[b][j] = sum_i U[b][i][j] V[b][i][j]: one workgroup per (column, batch item), fixed order.
+__global__ __launch_bounds__(256) void k_coldot(const double* U, const double* V, int64_t rows, int64_t ld,
+                                                int64_t sU, int64_t sV, double* out, int64_t sOut) {
+  __shared__ double red[256];
+  const int64_t j = blockIdx.x;
+  const double* u = U + blockIdx.z * sU + j;
+  const double* v = V + blockIdx.z * sV + j;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < rows; i += 256) s = fma(u[i * ld], v[i * ld], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.z * sOut + j] = red[0];
+}
+
+__global__ void k_axpy(double* y, const double* x, double a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = fma(a, x[i], y[i]);
+}
+
 __global__ void k_sum_parts(const double* parts, int nparts, int64_t sP, double* out, int64_t sOut) {
   if (threadIdx.x != 0) return;
   const double* p = parts + blockIdx.x * sP;
@@ -474,6 +497,18 @@ hipError_t launch_colsumsq(const double* U, int64_t rows, int64_t cols, int64_t 
                            int batch, double* out, int64_t sOut, hipStream_t s) {
   hipLaunchKernelGGL(k_colsumsq, dim3((unsigned)cols, 1, batch), dim3(256), 0, s, U, rows, cols, ldu,
                      sU, out, sOut);
+  return hipGetLastError();
+}
+
+hipError_t launch_coldot(const double* U, const double* V, int64_t rows, int64_t cols, int64_t ld,
+                         int64_t sU, int64_t sV, int batch, double* out, int64_t sOut, hipStream_t s) {
+  hipLaunchKernelGGL(k_coldot, dim3((unsigned)cols, 1, batch), dim3(256), 0, s, U, V, rows, ld, sU, sV, out, sOut);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy, dim3(blocks(n, 256)), dim3(256), 0, s, y, x, a, n);
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@
 // FP64 MFMA lane layout (measured on gfx950): lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // output register r of lane l is D[l/16 + 4r][l%16].
 #include "cf_internal.h"
+#include <type_traits>
 
 namespace cf {
 namespace {
@@ -158,6 +159,189 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   }
 }
 
+// Low-precision variants for the mixed-precision path.  Operands are read in FP64 and rounded
+// on the way into LDS: MODE 1 to FP32 (v_mfma_f32_16x16x4_f32), MODE 2 to a split hi + lo pair of
+// bfloat16 values (x = hi + lo + O(2^-17 |x|)) whose products hi*hi + hi*lo + lo*hi run on
+// v_mfma_f32_16x16x32_bf16.  Accumulation is FP32 within the tile; the epilogue adds into the
+// FP64 output.  FP32/BF16 MFMA lane layout (measured): output register r of lane l is
+// D[4*(l/16) + r][l%16]; for bf16, lane l supplies A[l%16][8*(l/16) + 0..7] and
+// B[8*(l/16) + 0..7][l%16].
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int BM, int BN, bool AT, bool BT, int MODE>
+__device__ __forceinline__ void k_gemm_lp_body(GemmArgs g) {
+  constexpr int BK = (MODE == 2) ? 32 : 16;
+  constexpr int WM = BM / 2, WN = BN / 2, MI = WM / 16, NI = WN / 16;
+  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
+  // MODE 1: FP32 LDS tiles laid out like the FP64 kernel.  MODE 2: [row][k] with k contiguous
+  // (8 consecutive k of one row form one 16-byte fragment), hi and lo planes.
+  constexpr int SA = (MODE == 2) ? (BK + 8) : (AT ? (BM + 1) : (BK + 1));
+  constexpr int SB = (MODE == 2) ? (BK + 8) : (BT ? (BK + 1) : (BN + 1));
+  constexpr int NA = (MODE == 2) ? BM * SA : (AT ? BK * SA : BM * SA);
+  constexpr int NBs = (MODE == 2) ? BN * SB : (BT ? BN * SB : BK * SB);
+  typedef typename std::conditional<MODE == 2, __bf16, float>::type lt;
+  constexpr int PL = (MODE == 2) ? 2 : 1;            // planes: hi (and lo)
+  __shared__ __attribute__((aligned(16))) lt As[2][PL][NA];
+  __shared__ __attribute__((aligned(16))) lt Bs[2][PL][NBs];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int tile_m = blockIdx.x / g.tiles_n, tile_n = blockIdx.x % g.tiles_n;
+  const int64_t i0 = (int64_t)tile_m * BM, j0 = (int64_t)tile_n * BN;
+  if (g.lower && j0 >= i0 + g.diag_off + BM) return;
+  const int64_t z = blockIdx.z;
+  const double* A = g.A + z * g.sA;
+  const double* B = g.B + z * g.sB;
+  double* C = g.C + z * g.sC;
+  const int64_t M = g.M, N = g.N, K = g.K;
+  constexpr int RA = AT ? 256 / BM : 256 / BK;
+  constexpr int RB = BT ? 256 / BK : 256 / BN;
+  const int a_r = AT ? tid / BM : tid / BK, a_c = AT ? tid % BM : tid % BK;
+  const int b_r = BT ? tid / BK : tid / BN, b_c = BT ? tid % BK : tid % BN;
+  const double* pa = AT ? A + (int64_t)a_r * g.lda + i0 + a_c : A + (i0 + a_r) * g.lda + a_c;
+  const double* pb = BT ? B + (j0 + b_r) * g.ldb + b_c : B + (int64_t)b_r * g.ldb + j0 + b_c;
+  const int64_t lda = g.lda, ldb = g.ldb;
+
+  double ra[LA], rb[LB];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int p = 0; p < LA; ++p) {
+      if (AT) {
+        const int64_t gk = k0 + a_r + p * RA;
+        ra[p] = (i0 + a_c < M && gk < K) ? pa[(k0 + p * RA) * lda] : 0.0;
+      } else {
+        const int64_t gi = i0 + a_r + p * RA;
+        ra[p] = (gi < M && k0 + a_c < K) ? pa[(int64_t)p * RA * lda + k0] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < LB; ++p) {
+      if (BT) {
+        const int64_t gj = j0 + b_r + p * RB;
+        rb[p] = (gj < N && k0 + b_c < K) ? pb[(int64_t)p * RB * ldb + k0] : 0.0;
+      } else {
+        const int64_t gk = k0 + b_r + p * RB;
+        rb[p] = (j0 + b_c < N && gk < K) ? pb[(k0 + p * RB) * ldb] : 0.0;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < LA; ++p) {
+      const int r = a_r + p * RA;            // k-row (AT) or i-row
+      // element (i, k)
+      const int ii = AT ? a_c : r, kk = AT ? r : a_c;
+      const int idx = (MODE == 2) ? ii * SA + kk : (AT ? kk * SA + ii : ii * SA + kk);
+      if (MODE == 2) {
+        const __bf16 h = (__bf16)ra[p];
+        As[buf][0][idx] = h;
+        As[buf][PL - 1][idx] = (__bf16)(ra[p] - (double)(float)h);
+      } else {
+        As[buf][0][idx] = (lt)(float)ra[p];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < LB; ++p) {
+      const int r = b_r + p * RB;            // j-row (BT) or k-row
+      const int jj = BT ? r : b_c, kk = BT ? b_c : r;
+      const int idx = (MODE == 2) ? jj * SB + kk : (BT ? jj * SB + kk : kk * SB + jj);
+      if (MODE == 2) {
+        const __bf16 h = (__bf16)rb[p];
+        Bs[buf][0][idx] = h;
+        Bs[buf][PL - 1][idx] = (__bf16)(rb[p] - (double)(float)h);
+      } else {
+        Bs[buf][0][idx] = (lt)(float)rb[p];
+      }
+    }
+  };
+
+  flt4 acc[MI][NI];
+#pragma unroll
+  for (int a = 0; a < MI; ++a)
+#pragma unroll
+    for (int b = 0; b < NI; ++b) acc[a][b] = flt4{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t nk = (K + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int64_t t = 0; t < nk; ++t) {
+    const int cur = (int)(t & 1);
+    if (t + 1 < nk) load((t + 1) * BK);
+    if (MODE == 2) {
+      const int kb = 8 * (lane >> 4);
+      bf16x8 ah[MI], al[MI], bh[NI], bl[NI];
+#pragma unroll
+      for (int a = 0; a < MI; ++a) {
+        const int ii = wr * WM + a * 16 + (lane & 15);
+        ah[a] = *reinterpret_cast<const bf16x8*>(&As[cur][0][ii * SA + kb]);
+        al[a] = *reinterpret_cast<const bf16x8*>(&As[cur][PL - 1][ii * SA + kb]);
+      }
+#pragma unroll
+      for (int b = 0; b < NI; ++b) {
+        const int jj = wc * WN + b * 16 + (lane & 15);
+        bh[b] = *reinterpret_cast<const bf16x8*>(&Bs[cur][0][jj * SB + kb]);
+        bl[b] = *reinterpret_cast<const bf16x8*>(&Bs[cur][PL - 1][jj * SB + kb]);
+      }
+#pragma unroll
+      for (int a = 0; a < MI; ++a)
+#pragma unroll
+        for (int b = 0; b < NI; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+      for (int kq = 0; kq < BK / 4; ++kq) {
+        const int kr = kq * 4 + (lane >> 4);
+        float av[MI], bv[NI];
+#pragma unroll
+        for (int a = 0; a < MI; ++a) {
+          const int ii = wr * WM + a * 16 + (lane & 15);
+          av[a] = As[cur][0][AT ? kr * SA + ii : ii * SA + kr];
+        }
+#pragma unroll
+        for (int b = 0; b < NI; ++b) {
+          const int jj = wc * WN + b * 16 + (lane & 15);
+          bv[b] = Bs[cur][0][BT ? jj * SB + kr : kr * SB + jj];
+        }
+#pragma unroll
+        for (int a = 0; a < MI; ++a)
+#pragma unroll
+          for (int b = 0; b < NI; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+    }
+    if (t + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  const double alpha = g.alpha, beta = g.beta;
+#pragma unroll
+  for (int a = 0; a < MI; ++a) {
+#pragma unroll
+    for (int b = 0; b < NI; ++b) {
+      const int64_t col = j0 + wc * WN + b * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = i0 + wr * WM + a * 16 + 4 * (lane >> 4) + r;
+        if (row < M && col < N) {
+          double v = alpha * (double)acc[a][b][r];
+          double* p = C + row * g.ldc + col;
+          if (beta != 0.0) v = fma(beta, *p, v);
+          *p = v;
+        }
+      }
+    }
+  }
+}
+
+template <int BM, int BN, bool AT, bool BT>
+__global__ __launch_bounds__(256, 2) void k_gemm_lp1(GemmArgs g);
+template <int BM, int BN, bool AT, bool BT>
+__global__ __launch_bounds__(256, 2) void k_gemm_lp2(GemmArgs g);
 template <int BM, int BN>
 hipError_t launch_tile(const GemmDesc& d, hipStream_t s) {
   GemmArgs g;
@@ -168,12 +352,26 @@ hipError_t launch_tile(const GemmDesc& d, hipStream_t s) {
   const int64_t tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
   g.tiles_n = (int)tn;
   dim3 grid((unsigned)(tm * tn), 1, d.batch > 0 ? d.batch : 1), block(256);
-  if (d.at && d.bt) hipLaunchKernelGGL((k_gemm<BM, BN, true, true>), grid, block, 0, s, g);
-  else if (d.at) hipLaunchKernelGGL((k_gemm<BM, BN, true, false>), grid, block, 0, s, g);
-  else if (d.bt) hipLaunchKernelGGL((k_gemm<BM, BN, false, true>), grid, block, 0, s, g);
-  else hipLaunchKernelGGL((k_gemm<BM, BN, false, false>), grid, block, 0, s, g);
+#define CF_GEMM_MODE(KER)                                                              \
+  if (d.at && d.bt) hipLaunchKernelGGL((KER<BM, BN, true, true>), grid, block, 0, s, g);   \
+  else if (d.at) hipLaunchKernelGGL((KER<BM, BN, true, false>), grid, block, 0, s, g);     \
+  else if (d.bt) hipLaunchKernelGGL((KER<BM, BN, false, true>), grid, block, 0, s, g);     \
+  else hipLaunchKernelGGL((KER<BM, BN, false, false>), grid, block, 0, s, g);
+  if (d.mode == 1) {
+    CF_GEMM_MODE(k_gemm_lp1)
+  } else if (d.mode == 2) {
+    CF_GEMM_MODE(k_gemm_lp2)
+  } else {
+    CF_GEMM_MODE(k_gemm)
+  }
+#undef CF_GEMM_MODE
   return hipGetLastError();
 }
+
+template <int BM, int BN, bool AT, bool BT>
+__global__ __launch_bounds__(256, 2) void k_gemm_lp1(GemmArgs g) { k_gemm_lp_body<BM, BN, AT, BT, 1>(g); }
+template <int BM, int BN, bool AT, bool BT>
+__global__ __launch_bounds__(256, 2) void k_gemm_lp2(GemmArgs g) { k_gemm_lp_body<BM, BN, AT, BT, 2>(g); }
 
 }  // namespace
 

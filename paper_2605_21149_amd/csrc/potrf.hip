@@ -16,29 +16,31 @@ constexpr int NB = kNB;          // 64
 constexpr int OUTER = 256;       // outer panel width
 
 // Factor the b x b (b <= 64) diagonal block at (c, c) and invert the factor in the same sweep.
-// 256 threads on a 16 x 16 grid; thread (ty, tx) keeps the 4 x 4 sub-block (rows 4ty.., columns
-// 4tx..) of the matrix A and of X = L^-1 in registers.  Step j publishes, behind one barrier,
-// column j of A (unscaled) and row j of X (already scaled by 1/L_jj); then
-//   A: a_rq -= a_rj a_qj / a_jj      (q > j, right-looking Cholesky with the unscaled column)
-//   X: x_r. -= (a_rj / L_jj) x_j.    (r > j, right-looking forward substitution on the identity)
-// Both updates only need column j, final at step j, so factorisation and inversion share their
-// 64 barriers.  Reciprocals use the hardware estimate refined by two Newton steps.  Rows and
-// columns beyond b are padded with the identity.  Outputs: L11 (lower) in place, L11^-1 as a full
-// 64 x 64 block, the block's sum of ln L_jj and the first non-positive pivot.
-__device__ __forceinline__ double rcp_nr(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  r = fma(r, fma(-d, r, 1.0), r);
-  return fma(r, fma(-d, r, 1.0), r);
+// 256 threads on a 16 x 16 grid; thread (ty, tx) keeps the 4 x 4 sub-blocks (rows 4ty.., columns
+// 4tx..) of the matrix and of X = L^-1 in registers.  The sweep runs over 4-column groups J:
+//   A  thread (J, J) factors its 4 x 4 diagonal block and inverts it (register-local);
+//   B  the threads of column group J form L_RJ = A_RJ L_JJ^-T for the rows below, the threads of
+//      row group J form the finished rows X_J = L_JJ^-1 X_J; both are published through LDS;
+//   C  every thread below applies the rank-4 updates A_RQ -= L_RJ L_QJ^T and X_R -= L_RJ X_J.
+// Two barriers per 4 columns.  Reciprocal square roots use the hardware estimate refined by
+// Newton steps.  Rows and columns beyond b are padded with the identity.  Outputs: L11 (lower)
+// in place, L11^-1 as a full 64 x 64 block, the block's sum of ln L_jj and the first
+// non-positive pivot.
+__device__ __forceinline__ double rsq_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  return y * fma(-0.5 * d * y, y, 1.5);
 }
 
 __global__ __launch_bounds__(256) void k_potrf_diag(double* A_base, int64_t lda, int64_t sA, int64_t c,
                                                     int b, double* Li_base, int64_t sLi,
                                                     double* ldpart_base, int64_t sL, int blk,
                                                     int* fail) {
-  __shared__ double colb[2][NB];
-  __shared__ double rowb[2][NB];
-  __shared__ double piv[NB];
-  __shared__ double lg[NB];
+  __shared__ double Ljji[2][16];          // L_JJ^-1 (4 x 4, row-major)
+  __shared__ double colblk[2][NB][4];     // L_RJ, all rows
+  __shared__ double rowblk[2][4][NB];     // X_J, all columns
+  __shared__ double prodp[16];
+  __shared__ int badp[16];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   double* A = A_base + blockIdx.z * sA + c * lda + c;
   double a[4][4], x[4][4];
@@ -50,57 +52,149 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A_base, int64_t lda,
       a[i][j] = (r < b && q < b) ? (q <= r ? A[r * lda + q] : 0.0) : (r == q ? 1.0 : 0.0);
       x[i][j] = (r == q) ? 1.0 : 0.0;
     }
-  for (int j4 = 0; j4 < NB; j4 += 4) {
+  for (int J = 0; J < 16; ++J) {
+    const int buf = J & 1;
+    // ---- A: the 4 x 4 diagonal block
+    if (tx == J && ty == J) {
+      double l[4][4], y[4];
+      double prod = 1.0;
+      int bad = INT_MAX;
 #pragma unroll
-    for (int jj0 = 0; jj0 < 4; ++jj0) {
-      const int j = j4 + jj0, buf = j & 1;
-      const bool own_col = (tx == (j4 >> 2)), own_row = (ty == (j4 >> 2));
-      if (own_col) {
+      for (int cc = 0; cc < 4; ++cc) {
+        double d = a[cc][cc];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) colb[buf][4 * ty + i] = a[i][jj0];
+        for (int k = 0; k < cc; ++k) d = fma(-l[cc][k], l[cc][k], d);
+        if (bad == INT_MAX && (!(d > 0.0) || !isfinite(d)) && 4 * J + cc < b) bad = (int)c + 4 * J + cc;
+        prod *= d;
+        y[cc] = rsq_nr(d);
+        l[cc][cc] = d * y[cc];
+#pragma unroll
+        for (int r = cc + 1; r < 4; ++r) {
+          double t = a[r][cc];
+#pragma unroll
+          for (int k = 0; k < cc; ++k) t = fma(-l[r][k], l[cc][k], t);
+          l[r][cc] = t * y[cc];
+        }
+#pragma unroll
+        for (int r = 0; r < cc; ++r) l[r][cc] = 0.0;
       }
-      if (own_row) {   // row j of X: complete except for its scaling by 1/L_jj
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) rowb[buf][4 * tx + jj] = x[jj0][jj];
-      }
-      __syncthreads();
-      const double d = colb[buf][j];
-      const double inv = rcp_nr(d);
-      const double rs = rcp_nr(sqrt(d));                 // 1 / L_jj
-      if (tid == 0) piv[j] = d;
-      if (own_row) {
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) x[jj0][jj] *= rs;
-      }
-      double cr[4], cq[4], xr[4];
+      // inverse of the 4 x 4 lower factor
+      double li[4][4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        cr[i] = (4 * ty + i > j) ? colb[buf][4 * ty + i] : 0.0;   // a_rj, rows below j
-        cq[i] = (4 * tx + i > j) ? colb[buf][4 * tx + i] : 0.0;   // a_qj, columns right of j
-        xr[i] = rowb[buf][4 * tx + i] * rs;                       // row j of X
-      }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const double f = cr[i] * inv, l = cr[i] * rs;
+        for (int j = 0; j < 4; ++j) li[i][j] = 0.0;
+        li[i][i] = y[i];
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          a[i][jj] = fma(-f, cq[jj], a[i][jj]);
-          x[i][jj] = fma(-l, xr[jj], x[i][jj]);
+        for (int j = 0; j < i; ++j) {
+          double t = 0.0;
+#pragma unroll
+          for (int k = j; k < i; ++k) t = fma(l[i][k], li[k][j], t);
+          li[i][j] = -t * y[i];
         }
       }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          a[i][j] = l[i][j];
+          Ljji[buf][i * 4 + j] = li[i][j];
+        }
+      prodp[J] = prod;                       // logarithms are taken after the sweep
+      badp[J] = bad;
+    }
+    __syncthreads();
+    // ---- B: column group J below the diagonal, row group J of X
+    double li[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) li[i][j] = Ljji[buf][i * 4 + j];
+    if (tx == J && ty > J) {
+      double l[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          double t = 0.0;
+#pragma unroll
+          for (int k = 0; k <= cc; ++k) t = fma(a[i][k], li[cc][k], t);   // (A L^-T)[i][cc]
+          l[i][cc] = t;
+        }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          a[i][cc] = l[i][cc];
+          colblk[buf][4 * ty + i][cc] = l[i][cc];
+        }
+    }
+    if (ty == J) {
+      double xn[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          double t = 0.0;
+#pragma unroll
+          for (int k = 0; k <= i; ++k) t = fma(li[i][k], x[k][jj], t);
+          xn[i][jj] = t;
+        }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          x[i][jj] = xn[i][jj];
+          rowblk[buf][i][4 * tx + jj] = xn[i][jj];
+        }
+    }
+    __syncthreads();
+    // ---- C: rank-4 updates below
+    if (ty > J) {
+      double lr[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) lr[i][cc] = colblk[buf][4 * ty + i][cc];
+      if (tx > J) {
+        double lq[4][4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) lq[jj][cc] = colblk[buf][4 * tx + jj][cc];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            double t = a[i][jj];
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) t = fma(-lr[i][cc], lq[jj][cc], t);
+            a[i][jj] = t;
+          }
+      }
+      double xj[4][4];
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) xj[cc][jj] = rowblk[buf][cc][4 * tx + jj];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          double t = x[i][jj];
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) t = fma(-lr[i][cc], xj[cc][jj], t);
+          x[i][jj] = t;
+        }
     }
   }
-  __syncthreads();
-  if (tid < NB) lg[tid] = (tid < b) ? 0.5 * log(piv[tid]) : 0.0;
-  // scale the stored columns: L_rq = a_rq / sqrt(a_qq) below the diagonal, sqrt(a_qq) on it
+  // ---- write L (lower), L^-1, log det part, first bad pivot
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
       const int r = 4 * ty + i, q = 4 * tx + jj;
-      const double sq = sqrt(piv[q]);
-      const double l = (q < r) ? a[i][jj] / sq : sq;
-      if (r < b && q < b && q <= r) A[r * lda + q] = l;
+      if (r < b && q < b && q <= r) A[r * lda + q] = a[i][jj];
     }
   double* Li = Li_base + blockIdx.z * sLi + (int64_t)blk * NB * NB;
 #pragma unroll
@@ -108,13 +202,14 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A_base, int64_t lda,
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) Li[(4 * ty + i) * NB + 4 * tx + jj] = x[i][jj];
   __syncthreads();
+  if (tid < 16) prodp[tid] = 0.5 * log(prodp[tid]);
+  __syncthreads();
   if (tid == 0) {
     double acc = 0.0;
     int bad = INT_MAX;
-    for (int j = 0; j < b; ++j) {
-      const double d = piv[j];
-      if (bad == INT_MAX && (!(d > 0.0) || !isfinite(d))) bad = (int)c + j;
-      acc += lg[j];
+    for (int J = 0; J < 16; ++J) {
+      acc += prodp[J];
+      if (bad == INT_MAX && badp[J] != INT_MAX) bad = badp[J];
     }
     ldpart_base[blockIdx.z * sL + blk] = acc;
     if (bad != INT_MAX) atomicMin(fail, bad);
@@ -183,6 +278,7 @@ GemmDesc upd(const Factor& F, int64_t r0, int64_t c0, int64_t M, int64_t N, int6
   g.C = F.L + r0 * F.ld + c0; g.ldc = F.ld;
   g.alpha = -1.0; g.beta = 1.0; g.lower = 1; g.diag_off = c0 - r0;
   g.batch = F.batch; g.sA = F.sL; g.sB = F.sL; g.sC = F.sL;
+  g.mode = F.mode;
   return g;
 }
 
@@ -263,6 +359,7 @@ hipError_t trsm_rec(const Factor& F, double* Y, int64_t ldy, int64_t sY, double*
     g.C = G + r0 * ldg; g.ldc = ldg;
     g.alpha = 1.0; g.beta = 0.0; g.lower = 0;
     g.batch = batch; g.sB = sY; g.sC = sG;
+    g.mode = F.mode;
     return gemm_f64(g, s);
   }
   int64_t mid;
@@ -285,6 +382,7 @@ hipError_t trsm_rec(const Factor& F, double* Y, int64_t ldy, int64_t sY, double*
   g.C = Y + mid * ldy; g.ldc = ldy;
   g.alpha = -1.0; g.beta = 1.0; g.lower = 0;
   g.batch = batch; g.sA = F.sL; g.sB = sG; g.sC = sY;
+  g.mode = F.mode;
   CF_HIP_TRY(gemm_f64(g, s));
   return trsm_rec(F, Y, ldy, sY, G, ldg, sG, ncol, mid, r1, s);
 }
@@ -295,6 +393,60 @@ hipError_t trsm_lower_f64(const Factor& F, double* Y, int64_t ldy, int64_t sY, d
   if (ncol <= 0 || F.n <= 0) return hipSuccess;
   const int64_t start = (r0 / NB) * NB;
   return trsm_rec(F, Y, ldy, sY, G, ldg, sG, ncol, start, F.n, s);
+}
+
+namespace {
+// X[r0:r1] = L[r0:r1, r0:r1]^-T B[r0:r1] (B consumed).  Bottom half first, then
+// B[r0:mid] -= L[mid:r1, r0:mid]^T X[mid:r1], then the top half; leaves use the transposed
+// inverted diagonal blocks.
+hipError_t trsmt_rec(const Factor& F, double* B, int64_t ldb, int64_t sB, double* X, int64_t ldx,
+                     int64_t sX, int64_t ncol, int64_t r0, int64_t r1, hipStream_t s) {
+  const int batch = F.batch > 0 ? F.batch : 1;
+  const bool leaf256 = F.Li256 && (r0 % 256) == 0 && r1 - r0 == 256;
+  if (r1 - r0 <= NB || leaf256) {
+    const int64_t m = r1 - r0;
+    GemmDesc g{};
+    g.M = m; g.N = ncol; g.K = m;
+    if (leaf256) { g.A = F.Li256 + (r0 / 256) * 256 * 256; g.lda = 256; g.sA = F.sLi256; }
+    else { g.A = F.Li64 + (r0 / NB) * NB * NB; g.lda = NB; g.sA = F.sLi64; }
+    g.at = 1;
+    g.B = B + r0 * ldb; g.ldb = ldb; g.bt = 0;
+    g.C = X + r0 * ldx; g.ldc = ldx;
+    g.alpha = 1.0; g.beta = 0.0;
+    g.batch = batch; g.sB = sB; g.sC = sX;
+    g.mode = F.mode;
+    return gemm_f64(g, s);
+  }
+  int64_t mid;
+  const int64_t up = ((r0 + 255) / 256) * 256;
+  if (F.Li256 && r0 % 256 != 0 && up < r1) {
+    mid = up;
+  } else if (F.Li256 && r0 % 256 == 0 && r1 - r0 > 256) {
+    const int64_t n256 = (r1 - r0 + 255) / 256;
+    mid = r0 + ((n256 + 1) / 2) * 256;
+    if (mid >= r1) mid = r0 + 256;
+  } else {
+    const int64_t nblk = (r1 - r0 + NB - 1) / NB;
+    mid = r0 + ((nblk + 1) / 2) * NB;
+  }
+  CF_HIP_TRY(trsmt_rec(F, B, ldb, sB, X, ldx, sX, ncol, mid, r1, s));
+  GemmDesc g{};
+  g.M = mid - r0; g.N = ncol; g.K = r1 - mid;
+  g.A = F.L + mid * F.ld + r0; g.lda = F.ld; g.at = 1;     // A(i,k) = L[mid+k][r0+i]
+  g.B = X + mid * ldx; g.ldb = ldx; g.bt = 0;
+  g.C = B + r0 * ldb; g.ldc = ldb;
+  g.alpha = -1.0; g.beta = 1.0;
+  g.batch = batch; g.sA = F.sL; g.sB = sX; g.sC = sB;
+  g.mode = F.mode;
+  CF_HIP_TRY(gemm_f64(g, s));
+  return trsmt_rec(F, B, ldb, sB, X, ldx, sX, ncol, r0, mid, s);
+}
+}  // namespace
+
+hipError_t trsm_lower_t_f64(const Factor& F, double* B, int64_t ldb, int64_t sB, double* X, int64_t ldx,
+                            int64_t sX, int64_t ncol, hipStream_t s) {
+  if (ncol <= 0 || F.n <= 0) return hipSuccess;
+  return trsmt_rec(F, B, ldb, sB, X, ldx, sX, ncol, 0, F.n, s);
 }
 
 }  // namespace cf

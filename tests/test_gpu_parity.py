@@ -177,3 +177,46 @@ def test_not_positive_definite_reports_pivot():
         cf.fisher(p, I.uniform_bins(2, 5, 1, ("TT",)), device=True)
     assert e.value.status == cf.CF_ENOTPD
     assert e.value.report["fail_index"] >= 0
+
+
+# ----------------------------------------------------------------------------------- mixed precision
+# Tolerances of the mixed paths (FP32 / split-BF16x3 MFMA with FP64 diagonal blocks, FP64
+# refinement of C^-1 d): Fisher relative Frobenius error, y after refinement, -2lnL absolute.
+MIXED_TOL = {cf.CF_MIXED_FP32: {"F": 2e-6, "y": 1e-9, "chi2": 1e-8, "logdet": 1e-3},
+             cf.CF_MIXED_BF16X3: {"F": 5e-4, "y": 1e-6, "chi2": 1e-6, "logdet": 1e-1}}
+
+
+@pytest.mark.parametrize("prec", [cf.CF_MIXED_FP32, cf.CF_MIXED_BF16X3])
+def test_mixed_qml_against_oracle(prec):
+    p = tiny_healpix("TQU", nside=4, lmax=9, cut=0.25, lowrank=2)
+    spectra = I.spectra_for_fields("TQU")
+    lo = np.array([2, 4, 6, 8]); hi = np.array([3, 5, 7, 9])
+    C = cv.total_covariance(p)
+    maps = _maps(p, C, 2, 31)
+    ref = qml.qml_harmonic(p, spectra, lo, hi, maps, C)
+    bins = I.Bins(lo.astype(np.int32), hi.astype(np.int32), tuple(spectra))
+    say("mixed qml", prec, p.n)
+    got = {k: to_np(v) for k, v in cf.qml(p, bins, maps, precision=prec, device=True).items()}
+    fro = np.linalg.norm(got["F"] - ref["F"]) / np.linalg.norm(ref["F"])
+    my = metric_vec_fisher(got["y"], ref["y"], ref["F"])
+    say("  relFro F", fro, " M_y", my)
+    assert fro < MIXED_TOL[prec]["F"]
+    assert my < MIXED_TOL[prec]["y"]
+
+
+@pytest.mark.parametrize("prec", [cf.CF_MIXED_FP32, cf.CF_MIXED_BF16X3])
+def test_mixed_loglike_against_oracle(prec):
+    p = tiny_healpix("QU", nside=4, lmax=9, cut=0.25, lowrank=2)
+    C = cv.total_covariance(p)
+    maps = _maps(p, C, 3, 41)
+    pts = I.scan_points(3, seed=5)
+    clp = I.scan_spectra(pts, p.cl)[:, None]
+    say("mixed loglike", prec, p.n)
+    got = cf.loglike_batch([p], clp, [maps], precision=prec, device=True)
+    x2 = to_np(got["chi2"])[:, 0]
+    ld = to_np(got["logdet"])[:, 0]
+    ref_m2, ref_ld = likelihood.scan(p, maps, clp[:, 0])
+    ref_x2 = ref_m2 - ref_ld[:, None]
+    say("  chi2 rel", np.max(np.abs(x2 - ref_x2) / ref_x2), " logdet abs", np.max(np.abs(ld - ref_ld)))
+    assert np.max(np.abs(x2 - ref_x2) / ref_x2) < MIXED_TOL[prec]["chi2"]
+    assert np.max(np.abs(ld - ref_ld)) < MIXED_TOL[prec]["logdet"]
