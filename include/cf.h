@@ -85,6 +85,8 @@ typedef struct {
   int32_t stage_timing;   /* 1: record per-stage device time in the report      */
   int32_t refine_max;     /* mixed precision: max refinement steps (-1 default)  */
   int32_t allow_fallback; /* mixed precision: fall back to FP64 instead of ENOCONV */
+  int32_t no_graph;       /* 1: launch every kernel eagerly instead of replaying captured hipGraphs */
+  int32_t autotune;       /* 1: time the candidate batch sizes of a new scan shape and keep the best */
 } cf_exec;
 
 /* Optional report (NULL = none). */

@@ -42,7 +42,7 @@ class cf_bins(C.Structure):
 
 class cf_exec(C.Structure):
     _fields_ = [("stream", C.c_void_p), ("stage_timing", C.c_int32), ("refine_max", C.c_int32),
-                ("allow_fallback", C.c_int32)]
+                ("allow_fallback", C.c_int32), ("no_graph", C.c_int32), ("autotune", C.c_int32)]
 
 
 class cf_report(C.Structure):
@@ -191,12 +191,14 @@ def pack_bins(b):
     return s, [lo, hi]
 
 
-def _exec(stream=None, stage_timing=False):
+def _exec(stream=None, stage_timing=False, no_graph=False, autotune=False, refine_max=-1):
     e = cf_exec()
     e.stream = stream
     e.stage_timing = 1 if stage_timing else 0
-    e.refine_max = -1
+    e.refine_max = refine_max
     e.allow_fallback = 0
+    e.no_graph = 1 if no_graph else 0
+    e.autotune = 1 if autotune else 0
     return e
 
 
@@ -282,7 +284,7 @@ def qml(p, bins, maps, precision=CF_FP64, device=False, stage_timing=False, repo
 
 
 def loglike_batch(problems: Sequence, cl_points, maps: Sequence, precision=CF_FP64, device=False,
-                  stage_timing=False, report=False, packed=None):
+                  stage_timing=False, report=False, packed=None, no_graph=False, autotune=False):
     """-2 ln L over a scan.  cl_points [npoints][nprob][6][lstride]; maps[p] [nmaps][n_p].
     Returns dict(m2lnL [npoints][nprob][nmaps], chi2 (same), logdet [npoints][nprob])."""
     pks = packed or [pack_problem(p, device) for p in problems]
@@ -304,7 +306,7 @@ def loglike_batch(problems: Sequence, cl_points, maps: Sequence, precision=CF_FP
     x2 = _alloc((npoints, nprob, nmaps), device)
     ld = _alloc((npoints, nprob), device)
     rep = cf_report()
-    ex = _exec(_torch_stream() if device else None, stage_timing)
+    ex = _exec(_torch_stream() if device else None, stage_timing, no_graph, autotune)
     st = lib().cf_loglike_batch(arr, nprob, npoints, _ptr(clp), lstride, mptr, nmaps, int(precision),
                                 _ptr(m2), _ptr(x2), _ptr(ld), C.byref(ex), C.byref(rep))
     _check(st, rep)

@@ -884,6 +884,175 @@ int cf_qml(const cf_problem* prob, const cf_bins* bins, const double* maps, int3
 
 }  // extern "C"
 
+// ------------------------------------------------------------------------------- scan
+namespace cf {
+namespace {
+
+// Captured batch of a scan: one hipGraph per (problem, batch shape, buffers), replayed for every
+// full batch; the batch's first node advances the device-side point offset.
+struct ScanGraph {
+  std::string key;
+  hipGraphExec_t exec = nullptr;
+};
+std::mutex g_graph_mu;
+std::vector<ScanGraph> g_graphs[64];
+
+// Autotuned batch size per scan shape (n, nmaps, mode), in memory and in a small text file.
+struct TuneEntry { int64_t n; int nmaps, mode, bt; };
+std::vector<TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_path() {
+  const char* p = getenv("CF_TUNE_CACHE");
+  if (p && *p) return p;
+  const char* h = getenv("HOME");
+  return std::string(h && *h ? h : "/tmp") + "/.cf_autotune.txt";
+}
+void tune_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  FILE* f = fopen(tune_path().c_str(), "r");
+  if (!f) return;
+  TuneEntry e;
+  long long n;
+  while (fscanf(f, "scan gfx950 n=%lld nmaps=%d mode=%d batch=%d\n", &n, &e.nmaps, &e.mode, &e.bt) == 4) {
+    e.n = n;
+    g_tune.push_back(e);
+  }
+  fclose(f);
+}
+int tune_get(int64_t n, int nmaps, int mode) {
+  tune_load();
+  for (auto& e : g_tune)
+    if (e.n == n && e.nmaps == nmaps && e.mode == mode) return e.bt;
+  return 0;
+}
+void tune_put(int64_t n, int nmaps, int mode, int bt) {
+  g_tune.push_back({n, nmaps, mode, bt});
+  FILE* f = fopen(tune_path().c_str(), "a");
+  if (!f) return;
+  fprintf(f, "scan gfx950 n=%lld nmaps=%d mode=%d batch=%d\n", (long long)n, nmaps, mode, bt);
+  fclose(f);
+}
+
+struct ScanCtx {
+  CallCtx* c;
+  const cf_problem* prob;
+  const HostProblem* h;
+  const Staged* S;
+  int p, nprob, nmaps, lstride, mode, refine;
+  const double* cl_dev;
+  double *cwb, *Cb, *C0b, *Linv, *Li256, *pscr, *ldp, *D, *Yb, *Gb, *Xb, *Rb, *x2, *ldb;
+  int* flags;
+  double *m2, *chi2, *ld;
+  size_t layout;                      // workspace layout signature (bytes carved)
+};
+
+// One batch of b points starting at i0 (or at *i0p when i0p is given).
+int scan_batch(const ScanCtx& x, int64_t i0, int b, int64_t* i0p, Timer* tm) {
+  CallCtx& c = *x.c;
+  const HostProblem& h = *x.h;
+  const int64_t n = h.n;
+  const int Lp = h.lmax + 1, nmaps = x.nmaps;
+  const int64_t nblk = (n + kNB - 1) / kNB;
+  if (i0p) CF_DEV(launch_add_i64(i0p, b, c.s));
+  // a2: per-point weights c^XY_l
+  const double* clb = i0p ? x.cl_dev + (int64_t)x.p * 6 * x.lstride
+                          : x.cl_dev + (i0 * x.nprob + x.p) * 6 * (int64_t)x.lstride;
+  CF_DEV(launch_tables(clb, x.S->bl, x.S->pl, h.lmin, h.lmax, b, (int64_t)x.nprob * 6 * x.lstride,
+                       x.lstride, x.cwb, nullptr, nullptr, nullptr, c.s, i0p));
+  // a3: covariance of every point of the batch
+  CF_DEV(launch_cov_build(x.S->P, x.cwb, 6 * (int64_t)Lp, b, x.prob->noise_kind, x.S->noise,
+                          x.prob->noise_rank, x.S->noise_U, x.Cb, n, n * n, x.mode ? 0 : 1, x.flags, c.s));
+  if (x.mode)
+    CF_DEV(hipMemcpyAsync(x.C0b, x.Cb, sizeof(double) * b * n * n, hipMemcpyDeviceToDevice, c.s));
+  if (tm) tm->mark(ST_BUILD);
+  // a4: Cholesky and log det
+  Factor F;
+  F.L = x.Cb; F.n = n; F.ld = n; F.sL = n * n;
+  F.Li64 = x.Linv; F.sLi64 = nblk * kNB * kNB;
+  F.Li256 = (n >= 256) ? x.Li256 : nullptr; F.sLi256 = (n / 256) * 256 * 256;
+  F.ldpart = x.ldp; F.sPart = nblk;
+  F.fail = x.flags + 1; F.batch = b; F.mode = x.mode;
+  if (int st = potrf_on(*c.dev, F, x.pscr, c.s, c.dev->aux[1], c.dev->ev + 8)) return st;
+  if (tm) tm->mark(ST_POTRF);
+  // a6: u = L^-1 d for every map, chi^2 = |u|^2 (FP64); mixed: refined x = C^-1 d, chi^2 = d^T x
+  for (int j = 0; j < b; ++j)
+    CF_DEV(hipMemcpyAsync(x.Yb + (size_t)j * n * nmaps, x.D, sizeof(double) * n * nmaps,
+                          hipMemcpyDeviceToDevice, c.s));
+  CF_DEV(trsm_lower_f64(F, x.Yb, nmaps, n * nmaps, x.Gb, nmaps, n * nmaps, nmaps, 0, c.s));
+  if (!x.mode) {
+    CF_DEV(launch_colsumsq(x.Gb, n, nmaps, nmaps, n * nmaps, b, x.x2, nmaps, c.s));
+  } else {
+    CF_DEV(trsm_lower_t_f64(F, x.Gb, nmaps, n * nmaps, x.Xb, nmaps, n * nmaps, nmaps, c.s));
+    for (int it = 0; it < x.refine; ++it) {
+      for (int j = 0; j < b; ++j)
+        CF_DEV(hipMemcpyAsync(x.Rb + (size_t)j * n * nmaps, x.D, sizeof(double) * n * nmaps,
+                              hipMemcpyDeviceToDevice, c.s));
+      GemmDesc r{};
+      r.M = n; r.N = nmaps; r.K = n;
+      r.A = x.C0b; r.lda = n; r.B = x.Xb; r.ldb = nmaps; r.C = x.Rb; r.ldc = nmaps;
+      r.alpha = -1.0; r.beta = 1.0; r.batch = b; r.sA = n * n; r.sB = n * nmaps; r.sC = n * nmaps;
+      CF_DEV(gemm_f64(r, c.s));
+      CF_DEV(trsm_lower_f64(F, x.Rb, nmaps, n * nmaps, x.Gb, nmaps, n * nmaps, nmaps, 0, c.s));
+      CF_DEV(trsm_lower_t_f64(F, x.Gb, nmaps, n * nmaps, x.Rb, nmaps, n * nmaps, nmaps, c.s));
+      CF_DEV(launch_axpy(x.Xb, x.Rb, 1.0, (int64_t)b * n * nmaps, c.s));
+    }
+    CF_DEV(launch_coldot(x.D, x.Xb, n, nmaps, nmaps, 0, n * nmaps, b, x.x2, nmaps, c.s));
+  }
+  CF_DEV(launch_sum_parts(x.ldp, (int)nblk, nblk, b, x.ldb, 1, c.s));
+  CF_DEV(launch_scan_finish(x.x2, x.ldb, b, nmaps, i0, x.p, x.nprob, x.m2, x.chi2, x.ld, c.s, i0p));
+  if (tm) tm->mark(ST_TRSM);
+  return CF_OK;
+}
+
+std::string graph_key(const ScanCtx& x, int b, const char* ws) {
+  char buf[512];
+  snprintf(buf, sizeof buf, "%d|%lld|%d|%d|%d|%d|%d|%d|%zu|%p|%p|%p|%p|%p|%p|%p|%p|%p", x.p,
+           (long long)x.h->n, b, x.nmaps, x.mode, x.refine, x.lstride, x.nprob, x.layout, (const void*)ws,
+           (const void*)x.cl_dev, (const void*)x.D, (const void*)x.m2, (const void*)x.chi2,
+           (const void*)x.ld, (const void*)x.S->noise, (const void*)x.S->noise_U, (const void*)x.c->s);
+  return buf;
+}
+
+// Runs points [i0, i0 + nb*b) of problem x.p as nb replays of the captured batch.
+int scan_replay(ScanCtx& x, int64_t i0, int b, int64_t nb, int64_t* i0p) {
+  CallCtx& c = *x.c;
+  int dev = 0;
+  CF_DEV(hipGetDevice(&dev));
+  const std::string key = graph_key(x, b, c.dev->ws);
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_graph_mu);
+    for (auto& e : g_graphs[dev])
+      if (e.key == key) exec = e.exec;
+  }
+  if (!exec) {
+    hipGraph_t graph = nullptr;
+    CF_DEV(hipStreamBeginCapture(c.s, hipStreamCaptureModeRelaxed));
+    int st = scan_batch(x, 0, b, i0p, nullptr);
+    hipError_t e2 = hipStreamEndCapture(c.s, &graph);
+    if (st) return st;
+    if (e2 != hipSuccess) return fail(CF_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+    CF_DEV(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    CF_DEV(hipGraphDestroy(graph));
+    std::lock_guard<std::mutex> g(g_graph_mu);
+    if (g_graphs[dev].size() >= 16) {
+      (void)hipGraphExecDestroy(g_graphs[dev].front().exec);
+      g_graphs[dev].erase(g_graphs[dev].begin());
+    }
+    g_graphs[dev].push_back({key, exec});
+  }
+  if (nb > 0) {
+    CF_DEV(launch_set_i64(i0p, i0 - b, c.s));
+    for (int64_t k = 0; k < nb; ++k) CF_DEV(hipGraphLaunch(exec, c.s));
+  }
+  return CF_OK;
+}
+
+}  // namespace
+}  // namespace cf
+
 extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t npoints,
                                 const double* cl_points, int32_t lstride, const double* const* maps,
                                 int32_t nmaps, int32_t precision, double* m2lnL, double* chi2,
@@ -896,6 +1065,7 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   if (precision < CF_FP64 || precision > CF_MIXED_BF16X3) return fail(CF_EINVAL, "unknown precision %d", precision);
   const int mode = precision;
   const int refine = (ex && ex->refine_max >= 0) ? ex->refine_max : (mode == 2 ? 3 : 2);
+  const bool use_graph = !(ex && ex->no_graph) && !(ex && ex->stage_timing);
   const int mem = probs[0].mem;
   std::vector<HostProblem> H(nprob);
   int lmax_all = 0;
@@ -914,11 +1084,17 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   }
   CallCtx c;
   if (int st = c.begin(ex)) return st;
-  // batch of points factorised together, sized by the largest problem
   int nmax = 0;
   for (int p = 0; p < nprob; ++p) nmax = H[p].n > nmax ? H[p].n : nmax;
+  // batch of points factorised together: the autotuned size of this shape if known, else the
+  // largest of at most 16 whose covariances fit in 6 GB
   const size_t per = (size_t)nmax * nmax * 8 * (mode ? 2 : 1);
-  int Bt = (int)std::min<size_t>(16, std::max<size_t>(1, (size_t(6) << 30) / per));
+  const int bt_cap = (int)std::min<size_t>(16, std::max<size_t>(1, (size_t(6) << 30) / per));
+  int Bt = bt_cap;
+  if (nprob == 1) {
+    const int tuned = tune_get(nmax, nmaps, mode);
+    if (tuned > 0) Bt = std::min(tuned, bt_cap);
+  }
   if (Bt > npoints) Bt = npoints;
   const int L = lmax_all + 1;
   Sizer z;
@@ -928,20 +1104,22 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
     for (int p = 0; p < nprob; ++p) z.add<double>((size_t)nmaps * H[p].n);
     z.add<double>((size_t)npoints * nprob * nmaps * 2 + (size_t)npoints * nprob);
   }
-  z.add<double>((size_t)Bt * 6 * L);                   // cw per point
-  z.add<double>((size_t)Bt * nmax * nmax);             // C batch
-  z.add<double>((size_t)Bt * ((nmax + kNB - 1) / kNB) * kNB * kNB);   // inverted diagonal blocks
-  z.add<double>((size_t)Bt * (nmax / 256) * 256 * 256);               // inverted 256-blocks
-  z.add<double>((size_t)potrf_scratch(Bt));
-  z.add<double>((size_t)Bt * ((nmax + kNB - 1) / kNB)); // logdet parts
-  z.add<double>((size_t)nmax * nmaps);                 // D
-  z.add<double>((size_t)Bt * nmax * nmaps);            // Y copies
-  z.add<double>((size_t)Bt * nmax * nmaps);            // G
-  z.add<double>(mode ? (size_t)Bt * nmax * nmax : 1);  // FP64 covariance copies (mixed)
-  z.add<double>(mode ? (size_t)Bt * nmax * nmaps : 1);  // x = C^-1 d (mixed)
-  z.add<double>(mode ? (size_t)Bt * nmax * nmaps : 1);  // residuals (mixed)
-  z.add<double>((size_t)Bt * nmaps);                   // chi2 batch
-  z.add<double>((size_t)Bt);                           // logdet batch
+  const int Bw = bt_cap;   // workspace sized for the largest batch the tuner may pick
+  z.add<double>((size_t)Bw * 6 * L);
+  z.add<double>((size_t)Bw * nmax * nmax);
+  z.add<double>((size_t)Bw * ((nmax + kNB - 1) / kNB) * kNB * kNB);
+  z.add<double>((size_t)Bw * (nmax / 256) * 256 * 256);
+  z.add<double>((size_t)potrf_scratch(Bw));
+  z.add<double>((size_t)Bw * ((nmax + kNB - 1) / kNB));
+  z.add<double>((size_t)nmax * nmaps);
+  z.add<double>((size_t)Bw * nmax * nmaps);
+  z.add<double>((size_t)Bw * nmax * nmaps);
+  z.add<double>(mode ? (size_t)Bw * nmax * nmax : 1);
+  z.add<double>(mode ? (size_t)Bw * nmax * nmaps : 1);
+  z.add<double>(mode ? (size_t)Bw * nmax * nmaps : 1);
+  z.add<double>((size_t)Bw * nmaps);
+  z.add<double>((size_t)Bw);
+  z.add<int64_t>(1);
   z.add<int>(8);
   if (int st = ensure_ws(*c.dev, z.off)) return st;
   Bump bp(c.dev->ws);
@@ -965,87 +1143,78 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
     chi2_dev = chi2 ? o + (size_t)npoints * nprob * nmaps : nullptr;
     ld_dev = logdet ? o + (size_t)npoints * nprob * nmaps * 2 : nullptr;
   }
-  double* cwb = bp.take<double>((size_t)Bt * 6 * L);
-  double* Cb = bp.take<double>((size_t)Bt * nmax * nmax);
-  double* Linv = bp.take<double>((size_t)Bt * ((nmax + kNB - 1) / kNB) * kNB * kNB);
-  double* Li256 = bp.take<double>((size_t)Bt * (nmax / 256) * 256 * 256);
-  double* pscr = bp.take<double>((size_t)potrf_scratch(Bt));
-  double* ldp = bp.take<double>((size_t)Bt * ((nmax + kNB - 1) / kNB));
-  double* D = bp.take<double>((size_t)nmax * nmaps);
-  double* Yb = bp.take<double>((size_t)Bt * nmax * nmaps);
-  double* Gb = bp.take<double>((size_t)Bt * nmax * nmaps);
-  double* C0b = bp.take<double>(mode ? (size_t)Bt * nmax * nmax : 1);
-  double* Xb = bp.take<double>(mode ? (size_t)Bt * nmax * nmaps : 1);
-  double* Rb = bp.take<double>(mode ? (size_t)Bt * nmax * nmaps : 1);
-  double* x2 = bp.take<double>((size_t)Bt * nmaps);
-  double* ldb = bp.take<double>((size_t)Bt);
-  int* flags = bp.take<int>(8);
-  CF_DEV(launch_fill_int(flags, 1, 0, c.s));
-  CF_DEV(launch_fill_int(flags + 1, 1, INT_MAX, c.s));
+  ScanCtx x;
+  x.c = &c; x.nprob = nprob; x.nmaps = nmaps; x.lstride = lstride; x.mode = mode; x.refine = refine;
+  x.cl_dev = cl_dev;
+  x.cwb = bp.take<double>((size_t)Bw * 6 * L);
+  x.Cb = bp.take<double>((size_t)Bw * nmax * nmax);
+  x.Linv = bp.take<double>((size_t)Bw * ((nmax + kNB - 1) / kNB) * kNB * kNB);
+  x.Li256 = bp.take<double>((size_t)Bw * (nmax / 256) * 256 * 256);
+  x.pscr = bp.take<double>((size_t)potrf_scratch(Bw));
+  x.ldp = bp.take<double>((size_t)Bw * ((nmax + kNB - 1) / kNB));
+  x.D = bp.take<double>((size_t)nmax * nmaps);
+  x.Yb = bp.take<double>((size_t)Bw * nmax * nmaps);
+  x.Gb = bp.take<double>((size_t)Bw * nmax * nmaps);
+  x.C0b = bp.take<double>(mode ? (size_t)Bw * nmax * nmax : 1);
+  x.Xb = bp.take<double>(mode ? (size_t)Bw * nmax * nmaps : 1);
+  x.Rb = bp.take<double>(mode ? (size_t)Bw * nmax * nmaps : 1);
+  x.x2 = bp.take<double>((size_t)Bw * nmaps);
+  x.ldb = bp.take<double>((size_t)Bw);
+  int64_t* i0p = bp.take<int64_t>(1);
+  x.flags = bp.take<int>(8);
+  x.m2 = m2_dev; x.chi2 = chi2_dev; x.ld = ld_dev;
+  x.layout = bp.off;
+  CF_DEV(launch_fill_int(x.flags, 1, 0, c.s));
+  CF_DEV(launch_fill_int(x.flags + 1, 1, INT_MAX, c.s));
   Timer tm;
   tm.begin(ex && ex->stage_timing, c.s);
   double flops = 0.0;
   for (int p = 0; p < nprob; ++p) {
     const HostProblem& h = H[p];
-    const int64_t n = h.n;
-    const int Lp = h.lmax + 1;
-    const int64_t nblk = (n + kNB - 1) / kNB;
-    CF_DEV(launch_transpose(map_dev[p], nmaps, n, n, D, nmaps, c.s));
-    for (int64_t i0 = 0; i0 < npoints; i0 += Bt) {
-      const int b = (int)std::min<int64_t>(Bt, npoints - i0);
-      // a2: per-point weights c^XY_l
-      CF_DEV(launch_tables(cl_dev + (i0 * nprob + p) * 6 * (int64_t)lstride, S[p].bl, S[p].pl, h.lmin,
-                           h.lmax, b, (int64_t)nprob * 6 * lstride, lstride, cwb, nullptr, nullptr,
-                           nullptr, c.s));
-      // a3: covariance of every point in the batch (lower triangle)
-      CF_DEV(launch_cov_build(S[p].P, cwb, 6 * (int64_t)Lp, b, probs[p].noise_kind, S[p].noise,
-                              probs[p].noise_rank, S[p].noise_U, Cb, n, n * n, mode ? 0 : 1, flags, c.s));
-      if (mode)
-        CF_DEV(hipMemcpyAsync(C0b, Cb, sizeof(double) * b * n * n, hipMemcpyDeviceToDevice, c.s));
-      tm.mark(ST_BUILD);
-      // a4: Cholesky and log det
-      Factor F;
-      F.L = Cb; F.n = n; F.ld = n; F.sL = n * n;
-      F.Li64 = Linv; F.sLi64 = nblk * kNB * kNB;
-      F.Li256 = (n >= 256) ? Li256 : nullptr; F.sLi256 = (n / 256) * 256 * 256;
-      F.ldpart = ldp; F.sPart = nblk;
-      F.fail = flags + 1; F.batch = b; F.mode = mode;
-      if (int st = potrf_on(*c.dev, F, pscr, c.s, c.dev->aux[1], c.dev->ev + 8)) return st;
-      tm.mark(ST_POTRF);
-      // a6: u = L^-1 d for every map, chi^2 = |u|^2
-      for (int j = 0; j < b; ++j)
-        CF_DEV(hipMemcpyAsync(Yb + (size_t)j * n * nmaps, D, sizeof(double) * n * nmaps,
-                              hipMemcpyDeviceToDevice, c.s));
-      CF_DEV(trsm_lower_f64(F, Yb, nmaps, n * nmaps, Gb, nmaps, n * nmaps, nmaps, 0, c.s));
-      if (!mode) {
-        CF_DEV(launch_colsumsq(Gb, n, nmaps, nmaps, n * nmaps, b, x2, nmaps, c.s));
-      } else {
-        // x = C~^-1 d, then x += C~^-1 (d - C x) with the FP64 covariance; chi^2 = d^T x
-        CF_DEV(trsm_lower_t_f64(F, Gb, nmaps, n * nmaps, Xb, nmaps, n * nmaps, nmaps, c.s));
-        for (int it = 0; it < refine; ++it) {
-          for (int j = 0; j < b; ++j)
-            CF_DEV(hipMemcpyAsync(Rb + (size_t)j * n * nmaps, D, sizeof(double) * n * nmaps,
-                                  hipMemcpyDeviceToDevice, c.s));
-          GemmDesc r{};
-          r.M = n; r.N = nmaps; r.K = n;
-          r.A = C0b; r.lda = n; r.B = Xb; r.ldb = nmaps; r.C = Rb; r.ldc = nmaps;
-          r.alpha = -1.0; r.beta = 1.0; r.batch = b; r.sA = n * n; r.sB = n * nmaps; r.sC = n * nmaps;
-          CF_DEV(gemm_f64(r, c.s));
-          CF_DEV(trsm_lower_f64(F, Rb, nmaps, n * nmaps, Gb, nmaps, n * nmaps, nmaps, 0, c.s));
-          CF_DEV(trsm_lower_t_f64(F, Gb, nmaps, n * nmaps, Rb, nmaps, n * nmaps, nmaps, c.s));
-          CF_DEV(launch_axpy(Xb, Rb, 1.0, (int64_t)b * n * nmaps, c.s));
-        }
-        CF_DEV(launch_coldot(D, Xb, n, nmaps, nmaps, 0, n * nmaps, b, x2, nmaps, c.s));
+    x.p = p; x.prob = &probs[p]; x.h = &h; x.S = &S[p];
+    CF_DEV(launch_transpose(map_dev[p], nmaps, h.n, h.n, x.D, nmaps, c.s));
+    int b = Bt;
+    int64_t i0 = 0;
+    // autotuning of the batch size: time one replay for each candidate on the first call of a shape
+    if (ex && ex->autotune && nprob == 1 && tune_get(h.n, nmaps, mode) == 0 && npoints >= 2) {
+      int best = Bt;
+      double best_rate = 0.0;
+      for (int cand : {2, 4, 8, 16}) {
+        if (cand > bt_cap || cand > npoints - i0) break;
+        if (use_graph) { if (int st = scan_replay(x, i0, cand, 0, i0p)) return st; }   // capture first
+        hipEvent_t e0, e1;
+        CF_DEV(hipEventCreate(&e0));
+        CF_DEV(hipEventCreate(&e1));
+        CF_DEV(hipEventRecord(e0, c.s));
+        if (use_graph) { if (int st = scan_replay(x, i0, cand, 1, i0p)) return st; }
+        else if (int st = scan_batch(x, i0, cand, nullptr, nullptr)) return st;
+        CF_DEV(hipEventRecord(e1, c.s));
+        CF_DEV(hipEventSynchronize(e1));
+        float ms = 0.f;
+        CF_DEV(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        const double rate = cand / (double)ms;
+        if (rate > best_rate) { best_rate = rate; best = cand; }
+        i0 += cand;
       }
-      CF_DEV(launch_sum_parts(ldp, (int)nblk, nblk, b, ldb, 1, c.s));
-      CF_DEV(launch_scan_finish(x2, ldb, b, nmaps, i0, p, nprob, m2_dev, chi2_dev, ld_dev, c.s));
-      tm.mark(ST_TRSM);
+      tune_put(h.n, nmaps, mode, best);
+      b = best;
     }
-    const double nd = (double)n;
+    const int64_t nfull = (npoints - i0) / b;
+    if (use_graph && nfull >= 1) {
+      if (int st = scan_replay(x, i0, b, nfull, i0p)) return st;
+      i0 += nfull * b;
+    }
+    for (; i0 < npoints; i0 += b) {
+      const int bb = (int)std::min<int64_t>(b, npoints - i0);
+      if (int st = scan_batch(x, i0, bb, nullptr, &tm)) return st;
+    }
+    const double nd = (double)h.n;
     flops += (double)npoints * (nd * nd * nd / 3.0 + nd * nd * nmaps);
   }
   int fl[2];
-  if (int st = read_flags(c, flags, 2, fl)) return st;
+  if (int st = read_flags(c, x.flags, 2, fl)) return st;
   if (fl[0]) return fail(CF_EINVAL, "non-finite covariance entry (check noise and scan spectra)");
   if (fl[1] != INT_MAX) {
     if (rep) rep->fail_index = fl[1];
@@ -1059,6 +1228,6 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   }
   CF_DEV(hipStreamSynchronize(c.s));
   tm.finish(rep);
-  if (rep) { rep->flops = flops; rep->n = H[0].n; rep->ir_iters = mode ? refine : 0; }
+  if (rep) { rep->flops = flops; rep->n = H[0].n; rep->ir_iters = mode ? refine : 0; rep->n_fallback = Bt; }
   return CF_OK;
 }

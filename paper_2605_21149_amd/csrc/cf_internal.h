@@ -48,9 +48,10 @@ hipError_t launch_geometry(const int* ring_idx, int nside, const double* theta, 
                            int npx, double* pix, hipStream_t s);
 // Items (scan points) i < nitems: spectra at cl + i*cl_stride, row x at + x*cl_ld.
 // Outputs cw, lam: [nitems][6][lmax+1]; wl, coef: item 0 only (nullable).
+// i0p (nullable): device-side item offset added to every item index (captured scan batches).
 hipError_t launch_tables(const double* cl, const double* bl, const double* pl, int lmin, int lmax,
                          int nitems, int64_t cl_stride, int64_t cl_ld, double* cw, double* wl,
-                         double* lam, double* coef, hipStream_t s);
+                         double* lam, double* coef, hipStream_t s, const int64_t* i0p = nullptr);
 
 // ---------------------------------------------------------------- covariance assembly
 // C (n x n, ld) = S + N for a batch: cw/C advance by cw_stride / c_stride per batch item.
@@ -148,7 +149,9 @@ hipError_t launch_add_scalar(const double* vec, int64_t nper, int batch, const d
 hipError_t launch_sub_bias(double* q, const double* bias, int K, int nmaps, hipStream_t s);
 hipError_t launch_scan_finish(const double* chi2b, const double* ldb, int B, int nmaps, int64_t i0,
                               int prob, int nprob, double* m2, double* chi2, double* logdet,
-                              hipStream_t s);
+                              hipStream_t s, const int64_t* i0p = nullptr);
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
+hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s);
 

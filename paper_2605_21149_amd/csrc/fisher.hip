@@ -368,10 +368,12 @@ __global__ void k_sub_bias(double* q, const double* bias, int K, int nmaps) {
 
 // Scatter a batch of per-point chi^2 [B][nmaps] and ln|C| [B] into the scan outputs
 // [npoints][nprob][nmaps] (m2lnL, chi2) and [npoints][nprob] (logdet).
-__global__ void k_scan_finish(const double* chi2b, const double* ldb, int B, int nmaps, int64_t i0,
-                              int prob, int nprob, double* m2, double* chi2, double* logdet) {
+__global__ void k_scan_finish(const double* chi2b, const double* ldb, int B, int nmaps, int64_t i0h,
+                              int prob, int nprob, double* m2, double* chi2, double* logdet,
+                              const int64_t* i0p) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= B * nmaps) return;
+  const int64_t i0 = i0p ? *i0p : i0h;
   const int b = idx / nmaps, j = idx % nmaps;
   const int64_t row = (i0 + b) * nprob + prob;
   const double x = chi2b[idx], l = ldb[b];
@@ -531,9 +533,21 @@ hipError_t launch_sub_bias(double* q, const double* bias, int K, int nmaps, hipS
 
 hipError_t launch_scan_finish(const double* chi2b, const double* ldb, int B, int nmaps, int64_t i0,
                               int prob, int nprob, double* m2, double* chi2, double* logdet,
-                              hipStream_t s) {
+                              hipStream_t s, const int64_t* i0p) {
   hipLaunchKernelGGL(k_scan_finish, dim3(blocks((int64_t)B * nmaps, 256)), dim3(256), 0, s, chi2b, ldb,
-                     B, nmaps, i0, prob, nprob, m2, chi2, logdet);
+                     B, nmaps, i0, prob, nprob, m2, chi2, logdet, i0p);
+  return hipGetLastError();
+}
+
+__global__ void k_set_i64(int64_t* p, int64_t v) { if (threadIdx.x == 0) *p = v; }
+__global__ void k_add_i64(int64_t* p, int64_t v) { if (threadIdx.x == 0) *p += v; }
+
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(64), 0, s, p, v);
   return hipGetLastError();
 }
 

@@ -68,7 +68,7 @@ __global__ void k_geometry(const int* ring_idx, int nside, const double* theta, 
 // coefficients.  One thread per (item, l); items are scan points sharing one problem.
 __global__ void k_tables(const double* cl, const double* bl, const double* pl, int lmin, int lmax,
                          int64_t cl_stride, int64_t cl_ld, double* cw, double* wl, double* lam,
-                         double* coef) {
+                         double* coef, const int64_t* i0p) {
   const int L = lmax + 1;
   int l = blockIdx.x * blockDim.x + threadIdx.x;
   int item = blockIdx.y;
@@ -78,7 +78,7 @@ __global__ void k_tables(const double* cl, const double* bl, const double* pl, i
   double w = pl ? pl[l] : 1.0;
   double W = b * b * w * w;
   double f = (2.0 * l + 1.0) / (4.0 * pi) * W;
-  const double* c = cl + item * cl_stride;
+  const double* c = cl + (item + (i0p ? *i0p : 0)) * cl_stride;
   for (int x = 0; x < 6; ++x) {
     double v = c[(int64_t)x * cl_ld + l];
     if (cw) cw[(int64_t)item * 6 * L + x * L + l] = (l >= lmin) ? f * v : 0.0;
@@ -122,10 +122,10 @@ hipError_t launch_geometry(const int* ring_idx, int nside, const double* theta, 
 
 hipError_t launch_tables(const double* cl, const double* bl, const double* pl, int lmin, int lmax,
                          int nitems, int64_t cl_stride, int64_t cl_ld, double* cw, double* wl,
-                         double* lam, double* coef, hipStream_t s) {
+                         double* lam, double* coef, hipStream_t s, const int64_t* i0p) {
   int L = lmax + 1;
   hipLaunchKernelGGL(k_tables, dim3((L + 127) / 128, nitems), dim3(128), 0, s, cl, bl, pl, lmin,
-                     lmax, cl_stride, cl_ld, cw, wl, lam, coef);
+                     lmax, cl_stride, cl_ld, cw, wl, lam, coef, i0p);
   return hipGetLastError();
 }
 

@@ -220,3 +220,34 @@ def test_mixed_loglike_against_oracle(prec):
     say("  chi2 rel", np.max(np.abs(x2 - ref_x2) / ref_x2), " logdet abs", np.max(np.abs(ld - ref_ld)))
     assert np.max(np.abs(x2 - ref_x2) / ref_x2) < MIXED_TOL[prec]["chi2"]
     assert np.max(np.abs(ld - ref_ld)) < MIXED_TOL[prec]["logdet"]
+
+
+def test_loglike_graph_replay_matches_eager():
+    """The captured-and-replayed scan (several full batches plus a remainder) gives the same
+    numbers as the eager launches, replay after replay, with eager work in between."""
+    p = tiny_healpix("QU", nside=4, lmax=9, cut=0.25, lowrank=2)
+    C = cv.total_covariance(p)
+    maps = _maps(p, C, 4, 51)
+    pts = I.scan_points(37, seed=12)
+    clp = I.scan_spectra(pts, p.cl)[:, None]
+    say("graph replay", p.n)
+    eager = to_np(cf.loglike_batch([p], clp, [maps], device=True, no_graph=True)["m2lnL"])
+    for rep in range(3):
+        got = to_np(cf.loglike_batch([p], clp, [maps], device=True)["m2lnL"])
+        np.testing.assert_allclose(got, eager, rtol=1e-13, atol=0)
+        cf.cov_build(p, device=True)                      # eager work between replays
+    ref, _ = likelihood.scan(p, maps, clp[:, 0])
+    np.testing.assert_allclose(eager[:, 0], ref, rtol=TOL)
+
+
+def test_loglike_autotune_records_a_batch_size(tmp_path, monkeypatch):
+    monkeypatch.setenv("CF_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    p = tiny_healpix("QU", nside=2, lmax=6, cut=0.2, lowrank=1)
+    C = cv.total_covariance(p)
+    maps = _maps(p, C, 2, 61)
+    pts = I.scan_points(40, seed=13)
+    clp = I.scan_spectra(pts, p.cl)[:, None]
+    say("autotune", p.n)
+    got = cf.loglike_batch([p], clp, [maps], device=True, autotune=True)
+    ref, _ = likelihood.scan(p, maps, clp[:, 0])
+    np.testing.assert_allclose(to_np(got["m2lnL"])[:, 0], ref, rtol=TOL)
