@@ -362,3 +362,49 @@ def test_monte_carlo_unbiasedness_and_fisher_variance():
     assert np.all(np.abs(mean - truth) < 4 * sig / np.sqrt(nsim))
     var = H["chat"].var(axis=0)
     assert np.all(np.abs(var / sig ** 2 - 1) < 5 * np.sqrt(2 / nsim))
+
+
+# --------------------------------------------------------------------------- emulator MLP
+def test_mlp_gradient_matches_central_differences():
+    from oracle import mlp
+    rng = np.random.default_rng(3)
+    params = mlp.init_params([7, 16, 16, 1], rng)
+    x = rng.uniform(0.5, 1.5, (32, 7))
+    y = rng.standard_normal(32)
+    loss, grads = mlp.loss_and_grads(params, x, y)
+    h = 1e-6
+    for l in range(3):
+        for which in (0, 1):
+            P = params[l][which]
+            idx = tuple(rng.integers(0, s) for s in P.shape)
+            P0 = P[idx]
+            P[idx] = P0 + h
+            lp, _ = mlp.loss_and_grads(params, x, y)
+            P[idx] = P0 - h
+            lm, _ = mlp.loss_and_grads(params, x, y)
+            P[idx] = P0
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - grads[l][which][idx]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_mlp_adam_first_step_is_signed_lr():
+    """With zero moments, the first Adam step moves every parameter by lr * g / (|g| + eps)."""
+    from oracle import mlp
+    rng = np.random.default_rng(4)
+    params = mlp.init_params([3, 4, 1], rng)
+    grads = [(rng.standard_normal(W.shape), rng.standard_normal(b.shape)) for W, b in params]
+    zeros = [(np.zeros_like(W), np.zeros_like(b)) for W, b in params]
+    newp, _, _ = mlp.adam_step(params, grads, zeros, zeros, 1, 1e-3)
+    for (W, b), (gW, gb), (W1, b1) in zip(params, grads, newp):
+        np.testing.assert_allclose(W - W1, 1e-3 * gW / (np.abs(gW) + 1e-8), rtol=1e-9)
+        np.testing.assert_allclose(b - b1, 1e-3 * gb / (np.abs(gb) + 1e-8), rtol=1e-9)
+
+
+def test_bf16_rounding_matches_definition():
+    from oracle import mlp
+    x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 2.0 ** -9, 1.0 + 3 * 2.0 ** -9, -3.140625, 1e-3])
+    r = mlp.round_bf16(x)
+    # 8 significant bits: 1 + 2^-8 is not representable -> ties to even (1); 1 + 3*2^-9 -> 1 + 2^-7
+    np.testing.assert_array_equal(r[:4], [1.0, 1.0, 1.0, 1.0 + 2.0 ** -7])
+    assert r[4] == -3.140625
+    assert abs(r[5] - 1e-3) / 1e-3 < 2.0 ** -8
