@@ -143,6 +143,95 @@ int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t npoints,
                      int32_t nmaps, int32_t precision, double* m2lnL, double* chi2,
                      double* logdet, const cf_exec* ex, cf_report* rep);
 
+/* ---------------------------------------------------------------------------------------------
+ * Likelihood emulator.  Not part of the paper's method: a surrogate of the -2 ln L of
+ * cf_loglike_batch over a box of model parameters, whose uncertain or out-of-box queries are
+ * sent back to the exact likelihood.
+ *
+ * Network: in_dim -> width -> ... -> width -> 1 (depth hidden layers, SiLU after each hidden
+ * layer, linear output).  Hidden-to-hidden products run on bfloat16 operands with FP32
+ * accumulation; the input and output layers, biases, master weights and Adam moments are FP32.
+ * Parameters of one member, flat (cf_emu_param_count floats): for each layer l in order,
+ * W_l [out][in] row-major then b_l [out].
+ * Inputs are normalised to [-1, 1] on the per-parameter [min, max] box of the training inputs
+ * (the hull); targets are standardised with the training mean and standard deviation.
+ * The ensemble's prediction is the mean of its members; its spread is their sample standard
+ * deviation (both in units of -2 ln L).
+ * ------------------------------------------------------------------------------------------- */
+typedef struct cf_emu cf_emu;
+
+/* Spectra linear in the parameters: cl(x) = base + sum_k x_k basis_k, each [6][lstride]
+ * (host memory).  The exact -2 ln L of a query x is cf_loglike_batch at cl(x). */
+typedef struct {
+  int32_t nparam;          /* = emulator in_dim                   */
+  int32_t lstride;         /* >= lmax+1 of the exact problem      */
+  const double* base;      /* [6][lstride]                        */
+  const double* basis;     /* [nparam][6][lstride]                */
+} cf_linear_spectra;
+
+/* Training controls (NULL = defaults in brackets). */
+typedef struct {
+  int32_t epochs;          /* passes over the training split [200]                          */
+  int32_t batch;           /* minibatch rows, 1..65536 [1024]                               */
+  double lr;               /* Adam step size at the first step, cosine-decayed to 0 [1e-3]  */
+  double beta1, beta2;     /* Adam moment decay [0.9, 0.999]                                */
+  double eps;              /* Adam denominator guard [1e-8]                                 */
+  double val_frac;         /* held-out fraction, 0 <= val_frac < 1 [0.1]                    */
+} cf_emu_opts;
+
+/* Create an ensemble of `ensemble` (1..16) networks with in_dim 1..8 inputs, width 64, 128 or
+ * 256 and depth 1..8 hidden layers on the current device.  Weights are drawn uniformly in
+ * +-1/sqrt(fan_in) from a splitmix64 stream seeded with seed + member; Adam moments are zero. */
+int cf_emu_create(int32_t in_dim, int32_t width, int32_t depth, int32_t ensemble, uint64_t seed,
+                  cf_emu** out);
+void cf_emu_destroy(cf_emu* emu);
+int64_t cf_emu_param_count(const cf_emu* emu);   /* floats per member, or -1 */
+/* Shape of an ensemble (any output pointer may be NULL). */
+int cf_emu_shape(const cf_emu* emu, int32_t* in_dim, int32_t* width, int32_t* depth, int32_t* ensemble);
+
+/* Train every member on (x [N][in_dim], y [N]) in memory space `mem` with MSE loss and Adam.
+ * A seeded random split keeps val_frac of the rows out of training.  The first call fixes the
+ * hull and target scaling; later calls continue from the current weights and moments.
+ * Report: ms_total device time, flops algorithmic, est_err = {final training loss (standardised
+ * MSE, member mean), held-out RMS error, held-out max |error|, held-out mean spread} (-2 ln L units;
+ * zero when nothing is held out), ir_iters = optimiser steps of this call. */
+int cf_emu_train(cf_emu* emu, const double* x, const double* y, int64_t N, int32_t mem,
+                 const cf_emu_opts* opts, const cf_exec* ex, cf_report* rep);
+
+/* Predict -2 ln L for N queries x [N][in_dim] (memory space `mem`, as are y_out, spread_out and
+ * used_fallback).  A query needs the exact likelihood when it lies outside the hull or its spread
+ * exceeds spread_max.  With exact_prob, exact_map ([n] in exact_prob->mem space) and model given,
+ * those queries are evaluated by cf_loglike_batch (FP64) at cl(x) and flagged in used_fallback;
+ * with exact_prob NULL the ensemble mean is returned for every query and used_fallback marks the
+ * queries that would need the exact likelihood.  spread_out, used_fallback nullable.
+ * Report: ms_total wall time of the call, n_fallback, est_err[0] ms of the ensemble inference,
+ * est_err[1] ms of the exact evaluations. */
+int cf_emu_predict(cf_emu* emu, const double* x, int64_t N, int32_t mem, double spread_max,
+                   const cf_problem* exact_prob, const cf_linear_spectra* model,
+                   const double* exact_map, double* y_out, double* spread_out,
+                   uint8_t* used_fallback, const cf_exec* ex, cf_report* rep);
+
+/* Inspection and checking of the networks (host memory, raw network units: inputs already
+ * normalised, outputs and targets standardised).
+ *   cf_emu_get_params / set_params: FP32 master parameters of one member (set refreshes the
+ *     bfloat16 copies; moments are kept).
+ *   cf_emu_forward: out [ensemble][N] member outputs.
+ *   cf_emu_gradient: grad [ensemble][P] gradient of mean((f(x) - y)^2) over the N rows, loss
+ *     [ensemble] (nullable) its value; the weights are not changed.
+ *   cf_emu_adam: one Adam step of every member with the given gradient [ensemble][P] and step
+ *     size lr (moment decays of the last cf_emu_train options, else the defaults). */
+int cf_emu_get_params(const cf_emu* emu, int32_t member, float* out);
+int cf_emu_set_params(cf_emu* emu, int32_t member, const float* in);
+int cf_emu_forward(cf_emu* emu, const double* x, int64_t N, float* out);
+int cf_emu_gradient(cf_emu* emu, const double* x, const double* y, int64_t N, float* grad,
+                    double* loss);
+int cf_emu_adam(cf_emu* emu, const float* grad, double lr);
+
+/* Write / read the whole emulator state (shape, weights, moments, step count, hull, scaling,
+ * optimiser constants) as a little-endian binary file. cf_emu_load creates on the current device. */
+int cf_emu_save(const cf_emu* emu, const char* path);
+int cf_emu_load(const char* path, cf_emu** out);
+
 /* Thread-local description of the last error on this thread. */
 const char* cf_last_error(void);
 

@@ -4,9 +4,10 @@ mean-squared-error gradient and one Adam step.
 Oracle code: test infrastructure only (see oracle/__init__.py).
 
 Parameters are a list [(W1, b1), ..., (WL, bL)] with W_l of shape [out][in] (y = x W^T + b).
-``round_bf16`` reproduces the rounding the GPU applies to the operands of its matrix products
-(weights and layer inputs rounded to bfloat16, round-to-nearest-even), so that the GPU forward and
-backward passes can be compared with this one on equal inputs.
+With ``bf16=True`` the operands of the hidden-to-hidden products (layers 2..L-1: their weights and
+their input activations) are rounded to bfloat16 (round-to-nearest-even), the precision in which
+the GPU feeds those products to its matrix cores; the input and output layers stay unrounded.
+This lets the GPU passes be compared with this one on equal operands.
 """
 import numpy as np
 
@@ -29,6 +30,11 @@ def silu_grad(z):
     return s * (1.0 + z * (1.0 - s))
 
 
+def _hidden(l, nlayers):
+    """Layer l (0-based) maps hidden to hidden: neither the first nor the last layer."""
+    return 0 < l < nlayers - 1
+
+
 def init_params(sizes, rng):
     """Uniform(-1/sqrt(in), 1/sqrt(in)) weights and biases (any fixed rule works for the checks)."""
     params = []
@@ -43,8 +49,9 @@ def forward(params, x, bf16=False):
     h = np.asarray(x, dtype=np.float64)
     cache = []
     for l, (W, b) in enumerate(params):
-        hin = round_bf16(h) if bf16 else h
-        Wq = round_bf16(W) if bf16 else W
+        q = bf16 and _hidden(l, len(params))
+        hin = round_bf16(h) if q else h
+        Wq = round_bf16(W) if q else W
         z = hin @ Wq.T + b
         cache.append((hin, z))
         h = silu(z) if l < len(params) - 1 else z
@@ -62,7 +69,7 @@ def loss_and_grads(params, x, y, bf16=False):
     for l in range(len(params) - 1, -1, -1):
         hin, z = cache[l]
         W = params[l][0]
-        Wq = round_bf16(W) if bf16 else W
+        Wq = round_bf16(W) if bf16 and _hidden(l, len(params)) else W
         grads[l] = (d.T @ hin, d.sum(axis=0))
         if l > 0:
             dh = d @ Wq

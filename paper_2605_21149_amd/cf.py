@@ -62,7 +62,20 @@ STAGES = ("build", "potrf", "ybuild", "trsm", "syrk", "reduce", "qml", "other")
 
 # Every symbol include/cf.h declares.
 EXPORTS = ("cf_problem_dim", "cf_problem_nmodes", "cf_cov_build", "cf_fisher", "cf_qml",
-           "cf_loglike_batch", "cf_last_error", "cf_version")
+           "cf_loglike_batch", "cf_emu_create", "cf_emu_destroy", "cf_emu_param_count", "cf_emu_shape",
+           "cf_emu_train", "cf_emu_predict", "cf_emu_get_params", "cf_emu_set_params",
+           "cf_emu_forward", "cf_emu_gradient", "cf_emu_adam", "cf_emu_save", "cf_emu_load",
+           "cf_last_error", "cf_version")
+
+
+class cf_linear_spectra(C.Structure):
+    _fields_ = [("nparam", C.c_int32), ("lstride", C.c_int32), ("base", _dp), ("basis", _dp)]
+
+
+class cf_emu_opts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("val_frac", C.c_double)]
 
 
 class CFError(RuntimeError):
@@ -97,7 +110,32 @@ def lib():
         L.cf_loglike_batch.argtypes = [C.POINTER(cf_problem), C.c_int32, C.c_int32, _dp, C.c_int32,
                                        C.POINTER(_dp), C.c_int32, C.c_int32, _dp, _dp, _dp,
                                        C.POINTER(cf_exec), C.POINTER(cf_report)]
-        for name in ("cf_cov_build", "cf_fisher", "cf_qml", "cf_loglike_batch"):
+        _fp = C.POINTER(C.c_float)
+        L.cf_emu_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
+                                    C.POINTER(C.c_void_p)]
+        L.cf_emu_destroy.argtypes = [C.c_void_p]
+        L.cf_emu_destroy.restype = None
+        L.cf_emu_param_count.argtypes = [C.c_void_p]
+        L.cf_emu_param_count.restype = C.c_int64
+        _ip = C.POINTER(C.c_int32)
+        L.cf_emu_shape.argtypes = [C.c_void_p, _ip, _ip, _ip, _ip]
+        L.cf_emu_train.argtypes = [C.c_void_p, _dp, _dp, C.c_int64, C.c_int32,
+                                   C.POINTER(cf_emu_opts), C.POINTER(cf_exec), C.POINTER(cf_report)]
+        L.cf_emu_predict.argtypes = [C.c_void_p, _dp, C.c_int64, C.c_int32, C.c_double,
+                                     C.POINTER(cf_problem), C.POINTER(cf_linear_spectra), _dp, _dp,
+                                     _dp, C.POINTER(C.c_uint8), C.POINTER(cf_exec),
+                                     C.POINTER(cf_report)]
+        L.cf_emu_get_params.argtypes = [C.c_void_p, C.c_int32, _fp]
+        L.cf_emu_set_params.argtypes = [C.c_void_p, C.c_int32, _fp]
+        L.cf_emu_forward.argtypes = [C.c_void_p, _dp, C.c_int64, _fp]
+        L.cf_emu_gradient.argtypes = [C.c_void_p, _dp, _dp, C.c_int64, _fp, _dp]
+        L.cf_emu_adam.argtypes = [C.c_void_p, _fp, C.c_double]
+        L.cf_emu_save.argtypes = [C.c_void_p, C.c_char_p]
+        L.cf_emu_load.argtypes = [C.c_char_p, C.POINTER(C.c_void_p)]
+        for name in ("cf_cov_build", "cf_fisher", "cf_qml", "cf_loglike_batch", "cf_emu_create",
+                     "cf_emu_train", "cf_emu_predict", "cf_emu_get_params", "cf_emu_set_params",
+                     "cf_emu_forward", "cf_emu_gradient", "cf_emu_adam", "cf_emu_save",
+                     "cf_emu_load"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -312,3 +350,125 @@ def loglike_batch(problems: Sequence, cl_points, maps: Sequence, precision=CF_FP
     _check(st, rep)
     out = {"m2lnL": m2, "chi2": x2, "logdet": ld}
     return (out, rep.as_dict()) if report else out
+
+
+# ------------------------------------------------------------------------------ emulator
+class Emulator:
+    """Handle of a cf_emu ensemble (see include/cf.h); every method is one library call."""
+
+    def __init__(self, in_dim=7, width=256, depth=3, ensemble=4, seed=501, _handle=None):
+        self._h = C.c_void_p()
+        if _handle is not None:
+            self._h = _handle
+        else:
+            _check(lib().cf_emu_create(in_dim, width, depth, ensemble, seed, C.byref(self._h)))
+        v = [C.c_int32() for _ in range(4)]
+        _check(lib().cf_emu_shape(self._h, *[C.byref(a) for a in v]))
+        self.in_dim, self.width, self.depth, self.ensemble = (a.value for a in v)
+        self.P = int(lib().cf_emu_param_count(self._h))
+
+    @classmethod
+    def load(cls, path):
+        h = C.c_void_p()
+        _check(lib().cf_emu_load(str(path).encode(), C.byref(h)))
+        return cls(_handle=h)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.cf_emu_destroy(h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def save(self, path):
+        _check(lib().cf_emu_save(self._h, str(path).encode()))
+
+    def train(self, x, y, epochs=200, batch=1024, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+              val_frac=0.1, device=False, report=False):
+        xs, ys = self._arr(x, device), self._arr(y, device)
+        o = cf_emu_opts(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps),
+                        float(val_frac))
+        rep = cf_report()
+        ex = _exec(_torch_stream() if device else None)
+        st = lib().cf_emu_train(self._h, _ptr(xs), _ptr(ys), xs.shape[0],
+                                CF_MEM_DEVICE if device else CF_MEM_HOST, C.byref(o), C.byref(ex),
+                                C.byref(rep))
+        _check(st, rep)
+        return rep.as_dict() if report else None
+
+    def predict(self, x, spread_max=0.1, exact=None, device=False, report=False):
+        """exact = (problem, base [6][L], basis [in][6][L], map [n]) enables the exact fallback.
+        Returns dict(y, spread, fallback)."""
+        xs = self._arr(x, device)
+        N = xs.shape[0]
+        keep = []
+        pp = ms = mp = None
+        if exact is not None:
+            prob, base, basis, emap = exact
+            pk = pack_problem(prob, device)
+            keep.append(pk)
+            pp = C.byref(pk.struct)
+            base, basis = _host(base), _host(basis)
+            keep += [base, basis]
+            ms = cf_linear_spectra(basis.shape[0], base.shape[-1], _ptr(base), _ptr(basis))
+            ms = C.byref(ms)
+            em = self._arr(emap, device)
+            keep.append(em)
+            mp = _ptr(em)
+        y = _alloc((N,), device)
+        sp = _alloc((N,), device)
+        if device:
+            import torch
+            fb = torch.empty((N,), dtype=torch.uint8, device="cuda")
+        else:
+            fb = np.empty((N,), dtype=np.uint8)
+        rep = cf_report()
+        ex = _exec(_torch_stream() if device else None)
+        st = lib().cf_emu_predict(self._h, _ptr(xs), N, CF_MEM_DEVICE if device else CF_MEM_HOST,
+                                  float(spread_max), pp, ms, mp, _ptr(y), _ptr(sp),
+                                  _ptr(fb, C.c_uint8), C.byref(ex), C.byref(rep))
+        _check(st, rep)
+        out = {"y": y, "spread": sp, "fallback": fb}
+        return (out, rep.as_dict()) if report else out
+
+    def get_params(self, member=0):
+        out = np.empty(self.P, np.float32)
+        _check(lib().cf_emu_get_params(self._h, member, _ptr(out, C.c_float)))
+        return out
+
+    def set_params(self, member, p):
+        p = _host(p, np.float32)
+        assert p.shape == (self.P,)
+        _check(lib().cf_emu_set_params(self._h, member, _ptr(p, C.c_float)))
+
+    def forward(self, xn):
+        xn = _host(xn)
+        N = xn.shape[0]
+        out = np.empty((self.ensemble, N), np.float32)
+        _check(lib().cf_emu_forward(self._h, _ptr(xn), N, _ptr(out, C.c_float)))
+        return out
+
+    def gradient(self, xn, yn):
+        xn, yn = _host(xn), _host(yn)
+        N = xn.shape[0]
+        g = np.empty((self.ensemble, self.P), np.float32)
+        loss = np.empty(self.ensemble, np.float64)
+        _check(lib().cf_emu_gradient(self._h, _ptr(xn), _ptr(yn), N, _ptr(g, C.c_float), _ptr(loss)))
+        return g, loss
+
+    def adam(self, grad, lr):
+        g = _host(grad, np.float32)
+        _check(lib().cf_emu_adam(self._h, _ptr(g, C.c_float), float(lr)))
+
+    @staticmethod
+    def _arr(a, device):
+        if device:
+            import torch
+            t = a if _is_torch(a) else torch.as_tensor(np.ascontiguousarray(a, np.float64))
+            return t.to("cuda", torch.float64).contiguous()
+        return _host(a)

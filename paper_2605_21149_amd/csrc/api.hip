@@ -688,6 +688,17 @@ double fisher_flops(const HostProblem& H) {
 }
 
 }  // namespace
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
 }  // namespace cf
 
 using namespace cf;

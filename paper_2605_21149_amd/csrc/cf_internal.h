@@ -155,4 +155,62 @@ hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s);
 
+// ---------------------------------------------------------------- likelihood emulator
+// Error text for cf_last_error() from code outside the API translation unit.
+int set_error(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+struct EmuNet {                 // device state of an ensemble
+  int in, W, D, E;              // inputs (<= 8), width (64/128/256), hidden layers, members
+  int64_t P;                    // FP32 parameters per member
+  float* master;                // [E][P]
+  float* m;                     // [E][P] Adam first moments
+  float* v;                     // [E][P] Adam second moments
+  __bf16* wq;                   // [E][D-1][2][W][W]: W_l and W_l^T (l = 1..D-1) in bfloat16
+};
+struct EmuTrain {               // one minibatch
+  int64_t n;                    // valid rows
+  int64_t rows;                 // rows rounded up to a multiple of 64
+  const float* xn;              // [*][8] normalised inputs
+  const float* yn;              // [*] standardised targets
+  const int* idx;               // [E][idx_stride] source rows of this batch, NULL = identity
+  int64_t idx_stride;
+  float scale;                  // 2 / n
+  __bf16* hq;                   // [E][D-1][rows][W] hidden activations h_0..h_{D-2}
+  float* z;                     // [E][D-1][rows][W] pre-activations z_1..z_{D-2}
+  float* hD;                    // [E][rows][W] h_{D-1}
+  float* d;                     // [E][D][rows][W] deltas of the hidden layers
+  float* dout;                  // [E][rows] output deltas
+  float* sq;                    // [E][rows] squared residuals
+  float* xb;                    // [E][rows][8] gathered inputs
+};
+struct EmuAdam {
+  float lr, b1, b2, eps, c1, c2;   // c1 = 1/(1-b1^t), c2 = 1/(1-b2^t)
+  int do_adam;                     // apply the update (else only write grad)
+  float* grad;                     // [E][P] gradient output, nullable
+  float* loss;                     // [E] mean squared residual, nullable
+  float inv_n;
+};
+struct EmuInfer {
+  const double* x;              // [n][in]
+  int64_t n;
+  int raw;                      // 1: x already normalised, no routing outputs
+  double lo[8], hi[8];          // hull
+  double ymu, ysig, spread_max;
+  double* y;                    // [n] ensemble mean (-2 ln L units)
+  double* spread;               // [n] ensemble sample standard deviation, nullable
+  uint8_t* flag;                // [n] 1 = outside the hull or spread > spread_max
+  float* raw_out;               // [E][n] member outputs, nullable
+};
+struct EmuScale { double lo[8], hi[8], ymu, ysig; };
+
+int64_t emu_param_count(int in, int W, int D);
+int64_t emu_off_w(int l, int in, int W, int D);
+hipError_t launch_emu_train_step(const EmuNet& net, const EmuTrain& tr, const EmuAdam& A, hipStream_t s);
+hipError_t launch_emu_infer(const EmuNet& net, const EmuInfer& q, hipStream_t s);
+hipError_t launch_emu_adam(const EmuNet& net, const float* grad, const EmuAdam& A, hipStream_t s);
+hipError_t launch_emu_refresh(const EmuNet& net, hipStream_t s);
+hipError_t launch_emu_prep(const double* x, const double* y, const int* rows, int64_t n, int in,
+                           const EmuScale& sc, float* xn, float* yn, hipStream_t s);
+hipError_t launch_emu_scatter(const double* val, const int* idx, int64_t n, double* y, hipStream_t s);
+
 }  // namespace cf

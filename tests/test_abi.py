@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _header_symbols():
     src = open(os.path.join(ROOT, "include", "cf.h")).read()
-    return sorted(set(re.findall(r"^(?:const char\*|int64_t|int)\s+(cf_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^(?:const char\*|int64_t|int|void)\s+(cf_\w+)\s*\(", src, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -68,3 +68,19 @@ def test_argument_validation():
     assert "noise" in _expect(cf.CF_EINVAL, lambda: cf.cov_build(r))
     # unsupported precision in this build is rejected, not silently run in FP64
     _expect(cf.CF_EINVAL, lambda: cf.fisher(p, bins, precision=7))
+
+
+def test_emulator_argument_validation():
+    """Shape checks of cf_emu_create run before any device call."""
+    import ctypes as C
+    L = cf.lib()
+    h = C.c_void_p()
+    for args in ((0, 256, 3, 4), (9, 256, 3, 4), (7, 96, 3, 4), (7, 256, 0, 4), (7, 256, 9, 4),
+                 (7, 256, 3, 0), (7, 256, 3, 17)):
+        assert L.cf_emu_create(*args, 1, C.byref(h)) == cf.CF_EINVAL
+        assert not h.value
+    assert L.cf_emu_param_count(None) == -1
+    assert L.cf_emu_shape(None, None, None, None, None) == cf.CF_EINVAL
+    assert L.cf_emu_train(None, None, None, 0, 0, None, None, None) == cf.CF_EINVAL
+    assert L.cf_emu_load(b"/nonexistent/emu.bin", C.byref(h)) == cf.CF_EINVAL
+    L.cf_emu_destroy(None)

@@ -408,3 +408,20 @@ def test_bf16_rounding_matches_definition():
     np.testing.assert_array_equal(r[:4], [1.0, 1.0, 1.0, 1.0 + 2.0 ** -7])
     assert r[4] == -3.140625
     assert abs(r[5] - 1e-3) / 1e-3 < 2.0 ** -8
+
+
+def test_mlp_bf16_mode_rounds_only_hidden_products():
+    """A network without hidden-to-hidden layers is unaffected by the bf16 mode; with one, the
+    bf16 output equals an FP64 pass whose middle weights and middle inputs were pre-rounded."""
+    from oracle import mlp
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-1, 1, (9, 3))
+    p2 = mlp.init_params([3, 8, 1], rng)
+    np.testing.assert_array_equal(mlp.forward(p2, x, bf16=True)[0], mlp.forward(p2, x)[0])
+    p3 = mlp.init_params([3, 8, 8, 1], rng)
+    out = mlp.forward(p3, x, bf16=True)[0]
+    W0, b0 = p3[0]
+    h0 = mlp.silu(x @ W0.T + b0)
+    h1 = mlp.silu(mlp.round_bf16(h0) @ mlp.round_bf16(p3[1][0]).T + p3[1][1])
+    ref = h1 @ p3[2][0].T + p3[2][1]
+    np.testing.assert_allclose(out, ref[:, 0], rtol=1e-15, atol=1e-15)
