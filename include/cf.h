@@ -154,7 +154,9 @@ int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t npoints,
  * Parameters of one member, flat (cf_emu_param_count floats): for each layer l in order,
  * W_l [out][in] row-major then b_l [out].
  * Inputs are normalised to [-1, 1] on the per-parameter [min, max] box of the training inputs
- * (the hull); targets are standardised with the training mean and standard deviation.
+ * (the hull).  The networks learn the residual of the targets about a least-squares polynomial
+ * baseline in the normalised inputs (degree cf_emu_opts.baseline), standardised with the
+ * residual's training mean and standard deviation; predictions add the baseline back.
  * The ensemble's prediction is the mean of its members; its spread is their sample standard
  * deviation (both in units of -2 ln L).
  * ------------------------------------------------------------------------------------------- */
@@ -177,6 +179,8 @@ typedef struct {
   double beta1, beta2;     /* Adam moment decay [0.9, 0.999]                                */
   double eps;              /* Adam denominator guard [1e-8]                                 */
   double val_frac;         /* held-out fraction, 0 <= val_frac < 1 [0.1]                    */
+  int32_t baseline;        /* degree 0, 1 or 2 of the polynomial fitted to the targets by    */
+                           /* least squares before the networks learn the residual [2]       */
 } cf_emu_opts;
 
 /* Create an ensemble of `ensemble` (1..16) networks with in_dim 1..8 inputs, width 64, 128 or
@@ -191,7 +195,8 @@ int cf_emu_shape(const cf_emu* emu, int32_t* in_dim, int32_t* width, int32_t* de
 
 /* Train every member on (x [N][in_dim], y [N]) in memory space `mem` with MSE loss and Adam.
  * A seeded random split keeps val_frac of the rows out of training.  The first call fixes the
- * hull and target scaling; later calls continue from the current weights and moments.
+ * hull, the baseline and the target scaling; later calls continue from the current weights and
+ * moments.
  * Report: ms_total device time, flops algorithmic, est_err = {final training loss (standardised
  * MSE, member mean), held-out RMS error, held-out max |error|, held-out mean spread} (-2 ln L units;
  * zero when nothing is held out), ir_iters = optimiser steps of this call. */

@@ -75,7 +75,7 @@ class cf_linear_spectra(C.Structure):
 class cf_emu_opts(C.Structure):
     _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
                 ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
-                ("val_frac", C.c_double)]
+                ("val_frac", C.c_double), ("baseline", C.c_int32)]
 
 
 class CFError(RuntimeError):
@@ -389,10 +389,10 @@ class Emulator:
         _check(lib().cf_emu_save(self._h, str(path).encode()))
 
     def train(self, x, y, epochs=200, batch=1024, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
-              val_frac=0.1, device=False, report=False):
+              val_frac=0.1, baseline=2, device=False, report=False):
         xs, ys = self._arr(x, device), self._arr(y, device)
         o = cf_emu_opts(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps),
-                        float(val_frac))
+                        float(val_frac), int(baseline))
         rep = cf_report()
         ex = _exec(_torch_stream() if device else None)
         st = lib().cf_emu_train(self._h, _ptr(xs), _ptr(ys), xs.shape[0],

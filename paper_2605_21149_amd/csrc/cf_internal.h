@@ -190,18 +190,39 @@ struct EmuAdam {
   float* loss;                     // [E] mean squared residual, nullable
   float inv_n;
 };
+// Input box and target model: u = (2x - lo - hi) / (hi - lo); the networks learn
+// (y - q(u) - ymu) / ysig with q a polynomial baseline of degree qdeg (0, 1 or 2) whose
+// coefficients qc are ordered 1, u_k (k < in), u_i u_j (i <= j, row by row).
+constexpr int kEmuQ = 45;
+struct EmuScale {
+  double lo[8], hi[8], ymu, ysig;
+  int qdeg;
+  double qc[kEmuQ];
+};
+__host__ __device__ inline int emu_nfeat(int in, int qdeg) {
+  return qdeg <= 0 ? 0 : (qdeg == 1 ? 1 + in : 1 + in + in * (in + 1) / 2);
+}
+__host__ __device__ inline double emu_baseline(const EmuScale& sc, const double* u, int in) {
+  if (sc.qdeg <= 0) return 0.0;
+  double s = sc.qc[0];
+  int o = 1;
+  for (int k = 0; k < in; ++k) s += sc.qc[o++] * u[k];
+  if (sc.qdeg >= 2)
+    for (int i = 0; i < in; ++i)
+      for (int j = i; j < in; ++j) s += sc.qc[o++] * u[i] * u[j];
+  return s;
+}
 struct EmuInfer {
   const double* x;              // [n][in]
   int64_t n;
   int raw;                      // 1: x already normalised, no routing outputs
-  double lo[8], hi[8];          // hull
-  double ymu, ysig, spread_max;
+  EmuScale sc;
+  double spread_max;
   double* y;                    // [n] ensemble mean (-2 ln L units)
   double* spread;               // [n] ensemble sample standard deviation, nullable
   uint8_t* flag;                // [n] 1 = outside the hull or spread > spread_max
   float* raw_out;               // [E][n] member outputs, nullable
 };
-struct EmuScale { double lo[8], hi[8], ymu, ysig; };
 
 int64_t emu_param_count(int in, int W, int D);
 int64_t emu_off_w(int l, int in, int W, int D);

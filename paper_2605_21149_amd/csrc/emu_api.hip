@@ -152,6 +152,54 @@ double train_flops_per_row(const EmuNet& n) {
   return fwd + 2.0 * H + fwd;
 }
 
+// Least-squares polynomial baseline of degree sc.qdeg through (u(x_r), y_r) over the training
+// rows: normal equations (features 1, u_k, u_i u_j on [-1, 1]) solved by Cholesky in FP64.
+int fit_baseline(const double* x, const double* y, const int* rows, int64_t nt, int in, EmuScale& sc) {
+  for (double& c : sc.qc) c = 0.0;
+  const int nf = emu_nfeat(in, sc.qdeg);
+  if (nf == 0) return CF_OK;
+  if (nt < 4 * nf) return set_error(CF_EINVAL, "%lld training rows are too few for a degree-%d baseline", (long long)nt, sc.qdeg);
+  std::vector<double> A((size_t)nf * nf, 0.0), b((size_t)nf, 0.0), f((size_t)nf), u(8);
+  for (int64_t i = 0; i < nt; ++i) {
+    const int64_t r = rows[i];
+    for (int k = 0; k < in; ++k) u[k] = (2.0 * x[r * in + k] - sc.lo[k] - sc.hi[k]) / (sc.hi[k] - sc.lo[k]);
+    int o = 0;
+    f[o++] = 1.0;
+    for (int k = 0; k < in; ++k) f[o++] = u[k];
+    if (sc.qdeg >= 2)
+      for (int p = 0; p < in; ++p)
+        for (int q = p; q < in; ++q) f[o++] = u[p] * u[q];
+    for (int p = 0; p < nf; ++p) {
+      b[p] += f[p] * y[r];
+      for (int q = 0; q <= p; ++q) A[(size_t)p * nf + q] += f[p] * f[q];
+    }
+  }
+  for (int p = 0; p < nf; ++p) {                 // Cholesky A = L L^T (lower, in place)
+    for (int q = 0; q <= p; ++q) {
+      double s = A[(size_t)p * nf + q];
+      for (int k = 0; k < q; ++k) s -= A[(size_t)p * nf + k] * A[(size_t)q * nf + k];
+      if (p == q) {
+        if (!(s > 0.0)) return set_error(CF_EINVAL, "training inputs do not determine the baseline");
+        A[(size_t)p * nf + p] = std::sqrt(s);
+      } else {
+        A[(size_t)p * nf + q] = s / A[(size_t)q * nf + q];
+      }
+    }
+  }
+  for (int p = 0; p < nf; ++p) {                 // L z = b, then L^T c = z
+    double s = b[p];
+    for (int k = 0; k < p; ++k) s -= A[(size_t)p * nf + k] * b[k];
+    b[p] = s / A[(size_t)p * nf + p];
+  }
+  for (int p = nf - 1; p >= 0; --p) {
+    double s = b[p];
+    for (int k = p + 1; k < nf; ++k) s -= A[(size_t)k * nf + p] * b[k];
+    b[p] = s / A[(size_t)p * nf + p];
+  }
+  for (int p = 0; p < nf; ++p) sc.qc[p] = b[p];
+  return CF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -234,7 +282,7 @@ int cf_emu_train(cf_emu* m, const double* x, const double* y, int64_t N, int32_t
   if (!x || !y) return set_error(CF_EINVAL, "x or y is NULL");
   if (N < 2 || N > (int64_t)1 << 30) return set_error(CF_EINVAL, "N = %lld outside 2..2^30", (long long)N);
   if (mem != CF_MEM_HOST && mem != CF_MEM_DEVICE) return set_error(CF_EINVAL, "unknown mem %d", mem);
-  cf_emu_opts o{200, 1024, 1e-3, 0.9, 0.999, 1e-8, 0.1};
+  cf_emu_opts o{200, 1024, 1e-3, 0.9, 0.999, 1e-8, 0.1, 2};
   if (opts) o = *opts;
   if (o.epochs < 1) return set_error(CF_EINVAL, "epochs %d < 1", o.epochs);
   if (o.batch < 1 || o.batch > 65536) return set_error(CF_EINVAL, "batch %d outside 1..65536", o.batch);
@@ -243,6 +291,7 @@ int cf_emu_train(cf_emu* m, const double* x, const double* y, int64_t N, int32_t
     return set_error(CF_EINVAL, "Adam betas must lie in [0, 1)");
   if (!(o.eps > 0.0)) return set_error(CF_EINVAL, "eps must be positive");
   if (!(o.val_frac >= 0.0 && o.val_frac < 1.0)) return set_error(CF_EINVAL, "val_frac outside [0, 1)");
+  if (o.baseline < 0 || o.baseline > 2) return set_error(CF_EINVAL, "baseline degree %d outside 0..2", o.baseline);
   std::lock_guard<std::mutex> lk(m->mu);
   if (int st = check_device(m)) return st;
   const EmuNet& n = m->net;
@@ -283,13 +332,22 @@ int cf_emu_train(cf_emu* m, const double* x, const double* y, int64_t N, int32_t
       sc.lo[k] = lo;
       sc.hi[k] = hi;
     }
+    sc.qdeg = o.baseline;
+    if (int st = fit_baseline(xh, yh, perm.data() + nval, nt, in, sc)) return st;
     double mu = 0.0;
-    for (int64_t i = nval; i < N; ++i) mu += yh[perm[i]];
+    std::vector<double> res((size_t)nt);
+    std::vector<double> u(8);
+    for (int64_t i = 0; i < nt; ++i) {
+      const int64_t r = perm[nval + i];
+      for (int k = 0; k < in; ++k) u[k] = (2.0 * xh[r * in + k] - sc.lo[k] - sc.hi[k]) / (sc.hi[k] - sc.lo[k]);
+      res[i] = yh[r] - emu_baseline(sc, u.data(), in);
+      mu += res[i];
+    }
     mu /= (double)nt;
     double var = 0.0;
-    for (int64_t i = nval; i < N; ++i) var += (yh[perm[i]] - mu) * (yh[perm[i]] - mu);
+    for (double r : res) var += (r - mu) * (r - mu);
     const double sig = std::sqrt(var / (double)nt);
-    if (!(sig > 0.0)) return set_error(CF_EINVAL, "training targets are constant");
+    if (!(sig > 0.0)) return set_error(CF_EINVAL, "training targets are exactly fitted by the baseline");
     sc.ymu = mu;
     sc.ysig = sig;
     m->sc = sc;
@@ -393,9 +451,8 @@ int cf_emu_train(cf_emu* m, const double* x, const double* y, int64_t N, int32_t
     EMU_DEV(hipMemcpyAsync(xvd, xv.data(), xv.size() * 8, hipMemcpyHostToDevice, s));
     EmuInfer q{};
     q.x = xvd; q.n = nval; q.raw = 0;
-    std::memcpy(q.lo, m->sc.lo, sizeof q.lo);
-    std::memcpy(q.hi, m->sc.hi, sizeof q.hi);
-    q.ymu = m->sc.ymu; q.ysig = m->sc.ysig; q.spread_max = INFINITY;
+    q.sc = m->sc;
+    q.spread_max = INFINITY;
     q.y = yv; q.spread = sv; q.flag = fv;
     EMU_DEV(launch_emu_infer(n, q, s));
     std::vector<double> hyv((size_t)nval), hsv((size_t)nval);
@@ -468,9 +525,8 @@ int cf_emu_predict(cf_emu* m, const double* x, int64_t N, int32_t mem, double sp
   EMU_DEV(hipEventCreate(&e1));
   EmuInfer q{};
   q.x = xd; q.n = N; q.raw = 0;
-  std::memcpy(q.lo, m->sc.lo, sizeof q.lo);
-  std::memcpy(q.hi, m->sc.hi, sizeof q.hi);
-  q.ymu = m->sc.ymu; q.ysig = m->sc.ysig; q.spread_max = spread_max;
+  q.sc = m->sc;
+  q.spread_max = spread_max;
   q.y = yd; q.spread = sd; q.flag = fd;
   EMU_DEV(hipEventRecord(e0, s));
   EMU_DEV(launch_emu_infer(n, q, s));
@@ -588,7 +644,8 @@ int cf_emu_forward(cf_emu* m, const double* x, int64_t N, float* out) {
   EMU_DEV(hipMemcpyAsync(xd, x, (size_t)N * n.in * 8, hipMemcpyHostToDevice, m->s));
   EmuInfer q{};
   q.x = xd; q.n = N; q.raw = 1; q.raw_out = od;
-  q.ysig = 1.0; q.spread_max = INFINITY;
+  q.sc.ysig = 1.0;
+  q.spread_max = INFINITY;
   EMU_DEV(launch_emu_infer(n, q, m->s));
   EMU_DEV(hipMemcpyAsync(out, od, (size_t)N * n.E * 4, hipMemcpyDeviceToHost, m->s));
   EMU_DEV(hipStreamSynchronize(m->s));
@@ -654,8 +711,8 @@ int cf_emu_adam(cf_emu* m, const float* grad, double lr) {
   return CF_OK;
 }
 
-// State file: "CFEMU001", int32 in, W, D, E, scaled; int64 P, step, calls; uint64 seed;
-// double lo[8], hi[8], ymu, ysig, b1, b2, eps; float master[E][P], m[E][P], v[E][P].
+// State file: "CFEMU002", int32 in, W, D, E, scaled, qdeg; int64 P, step, calls; uint64 seed;
+// double lo[8], hi[8], ymu, ysig, b1, b2, eps, qc[45]; float master[E][P], m[E][P], v[E][P].
 int cf_emu_save(const cf_emu* m, const char* path) {
   if (!m || !path) return set_error(CF_EINVAL, "NULL argument");
   if (int st = check_device(m)) return st;
@@ -668,15 +725,16 @@ int cf_emu_save(const cf_emu* m, const char* path) {
   EMU_DEV(hipMemcpy(c.data(), n.v, np * 4, hipMemcpyDeviceToHost));
   FILE* f = std::fopen(path, "wb");
   if (!f) return set_error(CF_EINVAL, "cannot open %s for writing", path);
-  const int32_t hi[5] = {n.in, n.W, n.D, n.E, m->scaled};
+  const int32_t hi[6] = {n.in, n.W, n.D, n.E, m->scaled, m->sc.qdeg};
   const int64_t hl[3] = {n.P, m->step, m->calls};
   const double hd[21] = {m->sc.lo[0], m->sc.lo[1], m->sc.lo[2], m->sc.lo[3], m->sc.lo[4], m->sc.lo[5],
                          m->sc.lo[6], m->sc.lo[7], m->sc.hi[0], m->sc.hi[1], m->sc.hi[2], m->sc.hi[3],
                          m->sc.hi[4], m->sc.hi[5], m->sc.hi[6], m->sc.hi[7], m->sc.ymu, m->sc.ysig,
                          m->b1, m->b2, m->eps};
-  bool ok = std::fwrite("CFEMU001", 1, 8, f) == 8 && std::fwrite(hi, 4, 5, f) == 5 &&
+  bool ok = std::fwrite("CFEMU002", 1, 8, f) == 8 && std::fwrite(hi, 4, 6, f) == 6 &&
             std::fwrite(hl, 8, 3, f) == 3 && std::fwrite(&m->seed, 8, 1, f) == 1 &&
-            std::fwrite(hd, 8, 21, f) == 21 && std::fwrite(a.data(), 4, np, f) == np &&
+            std::fwrite(hd, 8, 21, f) == 21 && std::fwrite(m->sc.qc, 8, kEmuQ, f) == (size_t)kEmuQ &&
+            std::fwrite(a.data(), 4, np, f) == np &&
             std::fwrite(b.data(), 4, np, f) == np && std::fwrite(c.data(), 4, np, f) == np;
   ok = (std::fclose(f) == 0) && ok;
   if (!ok) return set_error(CF_EINVAL, "write to %s failed", path);
@@ -689,13 +747,14 @@ int cf_emu_load(const char* path, cf_emu** out) {
   FILE* f = std::fopen(path, "rb");
   if (!f) return set_error(CF_EINVAL, "cannot open %s", path);
   char magic[8];
-  int32_t hi[5];
+  int32_t hi[6];
   int64_t hl[3];
   uint64_t seed;
-  double hd[21];
-  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "CFEMU001", 8) == 0 &&
-            std::fread(hi, 4, 5, f) == 5 && std::fread(hl, 8, 3, f) == 3 &&
-            std::fread(&seed, 8, 1, f) == 1 && std::fread(hd, 8, 21, f) == 21;
+  double hd[21], qc[kEmuQ];
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "CFEMU002", 8) == 0 &&
+            std::fread(hi, 4, 6, f) == 6 && std::fread(hl, 8, 3, f) == 3 &&
+            std::fread(&seed, 8, 1, f) == 1 && std::fread(hd, 8, 21, f) == 21 &&
+            std::fread(qc, 8, kEmuQ, f) == (size_t)kEmuQ;
   if (!ok) { std::fclose(f); return set_error(CF_EINVAL, "%s is not an emulator state file", path); }
   cf_emu* m = nullptr;
   if (int st = cf_emu_create(hi[0], hi[1], hi[2], hi[3], seed, &m)) { std::fclose(f); return st; }
@@ -715,6 +774,8 @@ int cf_emu_load(const char* path, cf_emu** out) {
   m->calls = hl[2];
   for (int k = 0; k < 8; ++k) { m->sc.lo[k] = hd[k]; m->sc.hi[k] = hd[8 + k]; }
   m->sc.ymu = hd[16]; m->sc.ysig = hd[17];
+  m->sc.qdeg = hi[5];
+  std::memcpy(m->sc.qc, qc, sizeof qc);
   m->b1 = hd[18]; m->b2 = hd[19]; m->eps = hd[20];
   if (hipMemcpy(m->net.master, a.data(), np * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(m->net.m, b.data(), np * 4, hipMemcpyHostToDevice) != hipSuccess ||

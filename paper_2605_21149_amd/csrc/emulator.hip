@@ -475,8 +475,8 @@ __global__ __launch_bounds__(256) void k_emu_infer(EmuNet net, EmuInfer q) {
       if (q.raw) {
         v = (float)x;
       } else {
-        v = (float)((2.0 * x - q.lo[k] - q.hi[k]) / (q.hi[k] - q.lo[k]));
-        if (!(x >= q.lo[k] && x <= q.hi[k])) inside[r] = 0;
+        v = (float)((2.0 * x - q.sc.lo[k] - q.sc.hi[k]) / (q.sc.hi[k] - q.sc.lo[k]));
+        if (!(x >= q.sc.lo[k] && x <= q.sc.hi[k])) inside[r] = 0;
       }
     }
     xs[t] = v;
@@ -506,8 +506,10 @@ __global__ __launch_bounds__(256) void k_emu_infer(EmuNet net, EmuInfer q) {
       const double dv = outs[e * kTM + tid] - mean;
       var += dv * dv;
     }
-    const double spread = net.E > 1 ? q.ysig * sqrt(var / (net.E - 1)) : 0.0;
-    q.y[row] = q.ymu + q.ysig * mean;
+    const double spread = net.E > 1 ? q.sc.ysig * sqrt(var / (net.E - 1)) : 0.0;
+    double u[kXin];
+    for (int k = 0; k < in; ++k) u[k] = (2.0 * q.x[row * in + k] - q.sc.lo[k] - q.sc.hi[k]) / (q.sc.hi[k] - q.sc.lo[k]);
+    q.y[row] = emu_baseline(q.sc, u, in) + q.sc.ymu + q.sc.ysig * mean;
     if (q.spread) q.spread[row] = spread;
     q.flag[row] = (!inside[tid] || !(spread <= q.spread_max)) ? 1 : 0;
   }
@@ -540,9 +542,12 @@ __global__ void k_emu_prep(const double* x, const double* y, const int* rows, in
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const int64_t r = rows ? rows[t] : t;
-  for (int k = 0; k < kXin; ++k)
-    xn[t * kXin + k] = k < in ? (float)((2.0 * x[r * in + k] - sc.lo[k] - sc.hi[k]) / (sc.hi[k] - sc.lo[k])) : 0.0f;
-  yn[t] = (float)((y[r] - sc.ymu) / sc.ysig);
+  double u[kXin];
+  for (int k = 0; k < kXin; ++k) {
+    u[k] = k < in ? (2.0 * x[r * in + k] - sc.lo[k] - sc.hi[k]) / (sc.hi[k] - sc.lo[k]) : 0.0;
+    xn[t * kXin + k] = (float)u[k];
+  }
+  yn[t] = (float)((y[r] - emu_baseline(sc, u, in) - sc.ymu) / sc.ysig);
 }
 
 __global__ void k_emu_scatter(const double* val, const int* idx, int64_t n, double* y) {

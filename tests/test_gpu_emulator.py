@@ -114,7 +114,7 @@ def test_train_step_equals_gradient_then_adam():
     a = cf.Emulator(in_dim, W, D, 1, seed=42)
     b = cf.Emulator(in_dim, W, D, 1, seed=42)
     lr = 1e-3
-    a.train(x, y, epochs=1, batch=N, lr=lr, val_frac=0.0)
+    a.train(x, y, epochs=1, batch=N, lr=lr, val_frac=0.0, baseline=0)
     lo, hi = x.min(axis=0), x.max(axis=0)
     xn = (2 * x - lo - hi) / (hi - lo)
     yn = (y - y.mean()) / y.std()
@@ -210,3 +210,23 @@ def test_prediction_falls_back_to_the_exact_likelihood():
     r2 = emu.predict(q, spread_max=0.5)
     np.testing.assert_array_equal(r2["fallback"], r["fallback"])
     np.testing.assert_array_equal(r2["y"][~fb], r["y"][~fb])
+
+
+def test_quadratic_baseline_carries_a_quadratic_target():
+    """With the degree-2 baseline a (nearly) quadratic target is reproduced by the least-squares
+    fit alone; the networks only see the tiny residual."""
+    cf = _cf()
+    rng = np.random.default_rng(71)
+    x = rng.uniform(0.5, 1.5, (4096, 7))
+    B = rng.standard_normal((7, 7))
+    c = rng.standard_normal(7)
+
+    def f(t):
+        return 500.0 + t @ c * 30.0 + 10.0 * np.einsum("ni,ij,nj->n", t, B, t) + 1e-6 * np.sin(5 * t[:, 0])
+
+    emu = cf.Emulator(7, 64, 2, 2, seed=72)
+    emu.train(x, f(x), epochs=2, batch=512, baseline=2)
+    q = rng.uniform(0.5, 1.5, (500, 7))
+    err = np.max(np.abs(emu.predict(q, spread_max=1e9)["y"] - f(q)))
+    print(f"quadratic target: max |err| {err:.2e} (sigma {f(x).std():.1f})", flush=True)
+    assert err <= 1e-4 * f(x).std()
