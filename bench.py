@@ -27,6 +27,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 / BF16x3 comparison")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run one device-to-device copy of MIB MiB (HBM counter calibration)")
     ap.add_argument("--emulator", action="store_true",
                     help="also train and measure the likelihood emulator on the QU N_side 16 scan problem")
     ap.add_argument("--emu-train", type=int, default=200000, help="exact training points")
@@ -187,6 +190,15 @@ def main():
               f"(multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 17                     # doubles
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 8 * n}), flush=True)
+        return
     from paper_2605_21149_amd import cf
     from paper_2605_21149_amd import inputs as I
 
@@ -240,7 +252,8 @@ def main():
     scan_stage = np.asarray(cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True,
                                              stage_timing=True, report=True,
                                              packed=[packed])[1]["ms_stage"])
-    mixed = mixed_precision(cf, I, problem, bins, packed, d_maps_qml, d_cl, d_maps_scan)
+    mixed = None if args.no_mixed else mixed_precision(cf, I, problem, bins, packed, d_maps_qml, d_cl,
+                                                          d_maps_scan)
     # dominant kernel: the FP64 MFMA GEMM forming Z = G^T G (two launches: all columns over the
     # Q,U rows, then the T x T block over the T rows); algorithmic flops count only the Z blocks
     # that are not identically zero, each symmetric pair once.

@@ -94,6 +94,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2605_21149_amd/build.py")
+        # torch ships its own HIP runtime; loading it first makes libcf bind to that same runtime
+        # (one runtime per process), whichever of the two the caller touches first.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         L.cf_last_error.restype = C.c_char_p
         L.cf_version.restype = C.c_char_p

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -356,6 +357,8 @@ enum { ST_BUILD = 0, ST_POTRF, ST_YBUILD, ST_TRSM, ST_SYRK, ST_REDUCE, ST_QML, S
 void make_cholesky_streams(Device& d, int id) {
   hipDeviceProp_t prop;
   d.crit = d.bulk = nullptr;
+  const char* env = getenv("CF_CU_MASK");   // "0": plain streams (e.g. for counter collection)
+  if (env && env[0] == '0') return;
   if (hipGetDeviceProperties(&prop, id) != hipSuccess) return;
   const int ncu = prop.multiProcessorCount;
   if (ncu < 64 || ncu % 8 || ncu > 1024) return;
@@ -379,7 +382,11 @@ void make_cholesky_streams(Device& d, int id) {
 int potrf_on(Device& d, Factor& F, double* scratch, hipStream_t s, hipStream_t side, hipEvent_t* ev) {
   // A batch of factorisations is bound by its bulk updates, not by the chain of diagonal blocks:
   // it keeps every CU for the bulk work.
-  if (!d.crit || F.batch > 1) {
+  // The reserved-CU streams are never used while s is being captured into a graph (a captured
+  // scan with CU-masked streams taking part crashed the runtime).
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  CF_DEV(hipStreamIsCapturing(s, &cap));
+  if (!d.crit || F.batch > 1 || cap != hipStreamCaptureStatusNone) {
     Streams st{s, d.aux[0], side, ev[0], ev[1], ev[2]};
     CF_DEV(potrf_f64(F, scratch, st));
     return CF_OK;

@@ -25,8 +25,68 @@ struct GemmArgs {
   int lower;
   int64_t diag_off;
   int64_t sA, sB, sC;
-  int tiles_n;
+  int tiles_m, tiles_n;
+  int remap;          // 0: row-major tiles; 1: XCD chunks, grouped rows; 2: as 1, lower triangle of a square grid
 };
+
+// Tile schedule.  Workgroups go to the 8 XCDs round-robin in launch order and every XCD has its
+// own L2.  With remap, XCD x takes the contiguous range [x*per, (x+1)*per) of the (batch item,
+// tile) sequence, and the tiles of one batch item are ordered in bands of 8 tile rows swept column
+// by column, so that the tiles resident on one XCD at a time form compact blocks that share their
+// A and B panels.  remap 2 enumerates only the lower triangle (diagonal included) of a square tile
+// grid, so no workgroup is launched for a skipped tile.
+__host__ __device__ inline bool tile_map(int remap, int tiles_m, int tiles_n, int64_t nx, int64_t nz,
+                                         int64_t bx, int64_t bz, int64_t& z, int& tm, int& tn) {
+  if (!remap) {
+    tm = (int)(bx / tiles_n);
+    tn = (int)(bx % tiles_n);
+    z = bz;
+    return true;
+  }
+  const int64_t gid = bz * nx + bx;
+  const int64_t total = nx * nz;
+  const int64_t base = total / 8, rem = total % 8, x = gid % 8;   // XCD x owns base (+1 if x < rem) items
+  const int64_t tg = x * base + (x < rem ? x : rem) + gid / 8;
+  if (tg >= total) return false;
+  z = tg / nx;
+  const int64_t t = tg % nx;
+  constexpr int G = 8;
+  if (remap == 2) {
+    auto S = [](int64_t q) { const int64_t r = q * G; return r * (r + 1) / 2; };   // tiles in rows < qG
+    int64_t q = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5) / G;
+    while (q > 0 && S(q) > t) --q;
+    while (S(q + 1) <= t) ++q;
+    const int64_t r0 = q * G;
+    const int rows = (int)(tiles_m - r0 < G ? tiles_m - r0 : G);
+    int64_t u = t - S(q);
+    if (u < rows * r0) {
+      tn = (int)(u / rows);
+      tm = (int)(r0 + u % rows);
+    } else {
+      u -= rows * r0;
+      int c = 0;
+      while (u >= rows - c) {
+        u -= rows - c;
+        ++c;
+      }
+      tn = (int)(r0 + c);
+      tm = (int)(r0 + c + u);
+    }
+  } else {
+    const int64_t span = (int64_t)G * tiles_n;
+    const int64_t q = t / span;
+    const int64_t r0 = q * G;
+    const int rows = (int)(tiles_m - r0 < G ? tiles_m - r0 : G);
+    const int64_t u = t - q * span;
+    tn = (int)(u / rows);
+    tm = (int)(r0 + u % rows);
+  }
+  return true;
+}
+
+__device__ __forceinline__ bool tile_of(const GemmArgs& g, int64_t& z, int& tm, int& tn) {
+  return tile_map(g.remap, g.tiles_m, g.tiles_n, gridDim.x, gridDim.z, blockIdx.x, blockIdx.z, z, tm, tn);
+}
 
 template <int BM, int BN, bool AT, bool BT>
 __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
@@ -45,10 +105,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int tile_m = blockIdx.x / g.tiles_n, tile_n = blockIdx.x % g.tiles_n;
+  int64_t z;
+  int tile_m, tile_n;
+  if (!tile_of(g, z, tile_m, tile_n)) return;
   const int64_t i0 = (int64_t)tile_m * BM, j0 = (int64_t)tile_n * BN;
   if (g.lower && j0 >= i0 + g.diag_off + BM) return;   // tile strictly above the diagonal
-  const int64_t z = blockIdx.z;
   const double* A = g.A + z * g.sA;
   const double* B = g.B + z * g.sB;
   double* C = g.C + z * g.sC;
@@ -187,10 +248,11 @@ __device__ __forceinline__ void k_gemm_lp_body(GemmArgs g) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int tile_m = blockIdx.x / g.tiles_n, tile_n = blockIdx.x % g.tiles_n;
+  int64_t z;
+  int tile_m, tile_n;
+  if (!tile_of(g, z, tile_m, tile_n)) return;
   const int64_t i0 = (int64_t)tile_m * BM, j0 = (int64_t)tile_n * BN;
   if (g.lower && j0 >= i0 + g.diag_off + BM) return;
-  const int64_t z = blockIdx.z;
   const double* A = g.A + z * g.sA;
   const double* B = g.B + z * g.sB;
   double* C = g.C + z * g.sC;
@@ -350,8 +412,17 @@ hipError_t launch_tile(const GemmDesc& d, hipStream_t s) {
   g.alpha = d.alpha; g.beta = d.beta; g.lower = d.lower; g.diag_off = d.diag_off;
   g.sA = d.sA; g.sB = d.sB; g.sC = d.sC;
   const int64_t tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
+  g.tiles_m = (int)tm;
   g.tiles_n = (int)tn;
-  dim3 grid((unsigned)(tm * tn), 1, d.batch > 0 ? d.batch : 1), block(256);
+  int64_t nx = tm * tn;
+  g.remap = 0;
+  if (d.lower && d.diag_off == 0 && tm == tn && BM == BN && d.M == d.N) {
+    g.remap = 2;
+    nx = tm * (tm + 1) / 2;
+  } else if (!d.lower) {
+    g.remap = 1;
+  }
+  dim3 grid((unsigned)nx, 1, d.batch > 0 ? d.batch : 1), block(256);
 #define CF_GEMM_MODE(KER)                                                              \
   if (d.at && d.bt) hipLaunchKernelGGL((KER<BM, BN, true, true>), grid, block, 0, s, g);   \
   else if (d.at) hipLaunchKernelGGL((KER<BM, BN, true, false>), grid, block, 0, s, g);     \

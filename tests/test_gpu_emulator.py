@@ -15,6 +15,13 @@ from paper_2605_21149_amd import inputs as I  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    _cf().lib()
+    assert torch.cuda.is_available(), "GPU tests selected but torch sees no GPU"
+
+
 def _cf():
     from paper_2605_21149_amd import cf
     return cf

@@ -22,10 +22,10 @@ TOL = 1e-10
 
 @pytest.fixture(scope="module", autouse=True)
 def _gpu():
-    torch = pytest.importorskip("torch")
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
+    import torch
     cf.lib()
+    # these tests only run where a GPU is expected: a missing device is a failure, not a skip
+    assert torch.cuda.is_available(), "GPU tests selected but torch sees no GPU"
 
 
 def _maps(p, C, nmaps, seed):
@@ -148,6 +148,19 @@ def test_loglike_batch_small():
     say("  max rel", np.max(np.abs(m2 - ref_m2) / np.abs(ref_m2)))
     np.testing.assert_allclose(m2, ref_m2, rtol=TOL)
     np.testing.assert_allclose(ld, ref_ld, rtol=TOL)
+
+
+def test_loglike_single_point_captured():
+    """One point per batch: the captured batch factorises a single matrix (the reserved-CU
+    streams of single factorisations stay out of graph capture)."""
+    p = tiny_healpix("QU", nside=4, lmax=9, cut=0.25, lowrank=2)
+    maps = _maps(p, cv.total_covariance(p), 2, 23)
+    clp = I.scan_spectra(I.scan_points(1, seed=24), p.cl)[:, None]
+    say("loglike single point (graph)", p.n)
+    got = [to_np(cf.loglike_batch([p], clp, [maps], device=True)["m2lnL"])[:, 0] for _ in range(2)]
+    ref, _ = likelihood.scan(p, maps, clp[:, 0])
+    for g in got:
+        np.testing.assert_allclose(g, ref, rtol=TOL)
 
 
 def test_loglike_two_uneven_problems():
