@@ -46,7 +46,7 @@ struct Device {
   // Cholesky streams: the critical path (diagonal blocks, panels, lookahead columns) runs on a
   // small reserved set of CUs so that the bulk trailing update, which owns the rest, never delays
   // it.  Both are plain streams when CU masks are unavailable.
-  hipStream_t crit = nullptr, bulk = nullptr;
+  hipStream_t crit = nullptr, bulk = nullptr, bulk2 = nullptr;   // bulk2: same CUs as bulk
   hipEvent_t ev[kEvents] = {};               // ordering events between the streams
   char* ws = nullptr;
   size_t cap = 0;
@@ -368,14 +368,20 @@ void make_cholesky_streams(Device& d, int id) {
     const bool c = (i % 8) == ((i / per) % 8);
     (c ? mc : mb)[i / 32] |= 1u << (i % 32);
   }
-  hipStream_t a = nullptr, b = nullptr;
+  hipStream_t a = nullptr, b = nullptr, b2 = nullptr;
   if (hipExtStreamCreateWithCUMask(&a, (uint32_t)mc.size(), mc.data()) != hipSuccess) return;
   if (hipExtStreamCreateWithCUMask(&b, (uint32_t)mb.size(), mb.data()) != hipSuccess) {
     (void)hipStreamDestroy(a);
     return;
   }
+  if (hipExtStreamCreateWithCUMask(&b2, (uint32_t)mb.size(), mb.data()) != hipSuccess) {
+    (void)hipStreamDestroy(a);
+    (void)hipStreamDestroy(b);
+    return;
+  }
   d.crit = a;
   d.bulk = b;
+  d.bulk2 = b2;
 }
 
 // Factorisation on the reserved-CU streams, ordered after and joined back into s.
@@ -394,7 +400,8 @@ int potrf_on(Device& d, Factor& F, double* scratch, hipStream_t s, hipStream_t s
   CF_DEV(hipEventRecord(ev[3], s));
   CF_DEV(hipStreamWaitEvent(d.crit, ev[3], 0));
   CF_DEV(hipStreamWaitEvent(d.bulk, ev[3], 0));
-  Streams st{d.crit, d.bulk, side, ev[0], ev[1], ev[2]};
+  CF_DEV(hipStreamWaitEvent(d.bulk2, ev[3], 0));
+  Streams st{d.crit, d.bulk, d.bulk2, ev[0], ev[1], ev[2]};
   CF_DEV(potrf_f64(F, scratch, st));
   CF_DEV(hipEventRecord(ev[4], d.crit));
   CF_DEV(hipStreamWaitEvent(s, ev[4], 0));
@@ -445,17 +452,33 @@ struct FisherBufs {
   int* flags;   // [0] non-finite covariance, [1] first failing pivot, [2] F pivot failure
 };
 
-size_t fisher_ws(const HostProblem& H, const HostBins& B, Sizer& z, int mode) {
+// Buffers of the Fisher path.  FP64 factorises [C; D^T; Y^T] (n + nm + k rows, ld n) in one
+// pass, so that u^T = (L^-1 d)^T and G^T = (L^-1 Y)^T come out of the factorisation as the rows
+// below C.  Mixed: C, Y and G apart, plus an FP64 copy of C for the refinement residuals.
+struct FisherSizes { size_t C, C0, Y, G, Li256; };
+FisherSizes fisher_sizes(const HostProblem& H, int mode, int nm) {
+  const size_t n = H.n, k = H.k;
+  FisherSizes q;
+  q.C = mode ? n * n : (n + nm + k) * n;
+  q.C0 = mode ? n * n : 1;
+  q.Y = n * k;
+  q.G = mode ? n * k : 1;
+  q.Li256 = mode ? (n / 256) * 256 * 256 : 1;
+  return q;
+}
+
+size_t fisher_ws(const HostProblem& H, const HostBins& B, Sizer& z, int mode, int nm) {
   const int nl = H.lmax - H.lmin + 1;
   const int np = H.nfm * H.nfm, nq = np * (np + 1) / 2;
   const int K = B.ns * B.nb;
-  z.add<double>((size_t)H.n * H.n);
-  z.add<double>(mode ? (size_t)H.n * H.n : 1);
-  z.add<double>((size_t)H.n * H.k);
-  z.add<double>((size_t)H.n * H.k);
+  const FisherSizes q = fisher_sizes(H, mode, nm);
+  z.add<double>(q.C);
+  z.add<double>(q.C0);
+  z.add<double>(q.Y);
+  z.add<double>(q.G);
   z.add<double>((size_t)H.k * H.k);
   z.add<double>((size_t)((H.n + kNB - 1) / kNB) * kNB * kNB);
-  z.add<double>((size_t)(H.n / 256) * 256 * 256);
+  z.add<double>(q.Li256);
   z.add<double>((size_t)potrf_scratch(1));
   z.add<double>((H.n + kNB - 1) / kNB);
   z.add<double>((size_t)nl * (nl + 1) / 2 * nq);
@@ -467,17 +490,18 @@ size_t fisher_ws(const HostProblem& H, const HostBins& B, Sizer& z, int mode) {
   return z.off;
 }
 
-void fisher_take(Bump& bp, const HostProblem& H, const HostBins& B, FisherBufs& f, int mode) {
+void fisher_take(Bump& bp, const HostProblem& H, const HostBins& B, FisherBufs& f, int mode, int nm) {
   const int nl = H.lmax - H.lmin + 1;
   const int np = H.nfm * H.nfm, nq = np * (np + 1) / 2;
   const int K = B.ns * B.nb;
-  f.C = bp.take<double>((size_t)H.n * H.n);
-  f.C0 = bp.take<double>(mode ? (size_t)H.n * H.n : 1);
-  f.Y = bp.take<double>((size_t)H.n * H.k);
-  f.G = bp.take<double>((size_t)H.n * H.k);
+  const FisherSizes q = fisher_sizes(H, mode, nm);
+  f.C = bp.take<double>(q.C);
+  f.C0 = bp.take<double>(q.C0);
+  f.Y = bp.take<double>(q.Y);
+  f.G = bp.take<double>(q.G);
   f.Z = bp.take<double>((size_t)H.k * H.k);
   f.Linv = bp.take<double>((size_t)((H.n + kNB - 1) / kNB) * kNB * kNB);
-  f.Li256 = bp.take<double>((size_t)(H.n / 256) * 256 * 256);
+  f.Li256 = bp.take<double>(q.Li256);
   f.scratch = bp.take<double>((size_t)potrf_scratch(1));
   f.ldpart = bp.take<double>((H.n + kNB - 1) / kNB);
   f.gram = bp.take<double>((size_t)nl * (nl + 1) / 2 * nq);
@@ -492,7 +516,7 @@ Factor make_factor(const FisherBufs& f, int64_t n, int mode) {
   Factor F;
   F.L = f.C; F.n = n; F.ld = n; F.sL = 0;
   F.Li64 = f.Linv; F.sLi64 = 0;
-  F.Li256 = (n >= 256) ? f.Li256 : nullptr; F.sLi256 = 0;
+  F.Li256 = (n >= 256 && mode) ? f.Li256 : nullptr; F.sLi256 = 0;
   F.ldpart = f.ldpart; F.sPart = 0;
   F.fail = f.flags + 1;
   F.batch = 1;
@@ -522,12 +546,95 @@ hipError_t weighted_maps(const double* A, int64_t lda, int64_t M, int64_t K, con
   return gemm_f64(w, s);
 }
 
+// FP64: one factorisation of [C; D^T; Y^T] gives L, u^T = (L^-1 d)^T and G^T = (L^-1 Y)^T (the
+// rows below C trail the factorisation on its side stream); Z = G^T G and w = G^T u are products
+// of those rows.  Y is built on aux[0] while s builds C.  For T+QU problems the E,B rows of Y^T
+// vanish on the T pixels: they are placed last, stay out of the panels that end before the first
+// Q pixel, and their Z products start at that pixel.
+int fisher_core_fp64(const cf_problem* prob, const HostProblem& H, const Staged& S, FisherBufs& f,
+                     QmlBufs* qb, CallCtx& cc, Timer& tm) {
+  const DevProblem& P = S.P;
+  const int64_t n = H.n, k = H.k;
+  const int nm = qb ? qb->nmaps : 0;
+  hipStream_t s = cc.s, s1 = cc.dev->aux[0], s2 = cc.dev->aux[1];
+  hipEvent_t* ev = cc.dev->ev;
+  enum { E_START = 0, E_Y, E_L, E_S1 };
+  double* Dt = f.C + n * n;                 // nm rows: d^T, then u^T
+  double* Gt = Dt + (int64_t)nm * n;        // k rows: Y^T, then G^T
+  CF_DEV(hipEventRecord(ev[E_START], s));
+  CF_DEV(hipStreamWaitEvent(s1, ev[E_START], 0));
+  hipEvent_t ty = tm.open(s1);
+  CF_DEV(launch_ybuild(P, f.Y, k, s1));
+  CF_DEV(launch_transpose(f.Y, n, k, k, Gt, n, s1));
+  tm.close(ST_YBUILD, ty, s1);
+  CF_DEV(hipEventRecord(ev[E_Y], s1));
+  CF_DEV(launch_fill_int(f.flags, 1, 0, s));
+  CF_DEV(launch_fill_int(f.flags + 1, 2, INT_MAX, s));
+  CF_DEV(launch_cov_build(P, S.cw, 0, 1, prob->noise_kind, S.noise, prob->noise_rank, S.noise_U, f.C, n,
+                          0, 1, f.flags, s));
+  if (nm) CF_DEV(hipMemcpyAsync(Dt, qb->maps, sizeof(double) * nm * n, hipMemcpyDeviceToDevice, s));
+  tm.mark(ST_BUILD);
+  CF_DEV(hipStreamWaitEvent(s, ev[E_Y], 0));
+  const bool split = H.has_t && H.has_p;
+  const int64_t kT = H.has_t ? H.kf : 0, kP = k - kT;
+  const int64_t p0 = split ? (H.npx / kNB) * kNB : 0;
+  Factor F = make_factor(f, n, 0);
+  F.rows = n + nm + k;
+  if (split) { F.rows_early = n + nm + kT; F.p_early = H.npx; }
+  if (int st = potrf_on(*cc.dev, F, f.scratch, s, s2, ev + 8)) return st;
+  tm.mark(ST_POTRF);
+  hipEvent_t tz = tm.open(s);
+  if (split) {
+    // Z rows of E,B against all columns (lower part), over columns >= p0 (aux[0])
+    CF_DEV(hipEventRecord(ev[E_L], s));
+    CF_DEV(hipStreamWaitEvent(s1, ev[E_L], 0));
+    GemmDesc h{};
+    h.M = kP; h.N = k; h.K = n - p0;
+    h.A = Gt + kT * n + p0; h.lda = n; h.at = 0;
+    h.B = Gt + p0; h.ldb = n; h.bt = 1;
+    h.C = f.Z + kT * k; h.ldc = k; h.alpha = 1.0; h.beta = 0.0; h.lower = 1; h.diag_off = kT;
+    h.batch = 1;
+    CF_DEV(gemm_f64(h, s1));
+    CF_DEV(hipEventRecord(ev[E_S1], s1));
+    // Z_TT over all columns (s)
+    GemmDesc g{};
+    g.M = kT; g.N = kT; g.K = n;
+    g.A = Gt; g.lda = n; g.at = 0;
+    g.B = Gt; g.ldb = n; g.bt = 1;
+    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1;
+    CF_DEV(gemm_f64(g, s));
+    CF_DEV(hipStreamWaitEvent(s, ev[E_S1], 0));
+  } else {
+    GemmDesc g{};
+    g.M = k; g.N = k; g.K = n;
+    g.A = Gt; g.lda = n; g.at = 0;
+    g.B = Gt; g.ldb = n; g.bt = 1;
+    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1;
+    CF_DEV(gemm_f64(g, s));
+  }
+  tm.close(ST_SYRK, tz, s);
+  if (qb) {   // w = G^T u  (k x nm)
+    GemmDesc w{};
+    w.M = k; w.N = nm; w.K = n;
+    w.A = Gt; w.lda = n; w.at = 0;
+    w.B = Dt; w.ldb = n; w.bt = 1;
+    w.C = qb->W; w.ldc = nm; w.alpha = 1.0; w.beta = 0.0; w.batch = 1;
+    CF_DEV(gemm_f64(w, s));
+  }
+  tm.mark(ST_OTHER);
+  CF_DEV(launch_symmetrize(f.Z, k, k, s));
+  CF_DEV(launch_gram(P, f.Z, k, f.gram, f.ztr, s));
+  tm.mark(ST_REDUCE);
+  return CF_OK;
+}
+
 // Covariance, factor, Y, G = L^-1 Y, Z = G^T G (+ u = L^-1 d, w = G^T u), Gram of Z blocks.
 // Three streams: the caller's stream s carries the covariance, the factorisation and the T part;
 // aux[0] builds Y (concurrently with the factorisation) and then carries the E,B part; aux[1]
 // solves the maps.  Events order the hand-offs; everything is joined back into s.
 int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, FisherBufs& f,
                 QmlBufs* qb, CallCtx& cc, Timer& tm, int mode) {
+  if (mode == 0) return fisher_core_fp64(prob, H, S, f, qb, cc, tm);
   const DevProblem& P = S.P;
   const int64_t n = H.n, k = H.k;
   hipStream_t s = cc.s, s1 = cc.dev->aux[0], s2 = cc.dev->aux[1];
@@ -780,13 +887,13 @@ int cf_fisher(const cf_problem* prob, const cf_bins* bins, int32_t precision, do
   if (int st = c.begin(ex)) return st;
   Sizer z;
   size_staging(z, prob, H);
-  fisher_ws(H, B, z, mode);
+  fisher_ws(H, B, z, mode, 0);
   if (int st = ensure_ws(*c.dev, z.off)) return st;
   Bump bp(c.dev->ws);
   Staged S;
   if (int st = stage(bp, prob, H, nullptr, c.s, S)) return st;
   FisherBufs f;
-  fisher_take(bp, H, B, f, mode);
+  fisher_take(bp, H, B, f, mode, 0);
   CF_DEV(hipMemcpyAsync(f.lo, B.lo.data(), sizeof(int) * B.nb, hipMemcpyHostToDevice, c.s));
   CF_DEV(hipMemcpyAsync(f.hi, B.hi.data(), sizeof(int) * B.nb, hipMemcpyHostToDevice, c.s));
   Timer tm;
@@ -826,7 +933,7 @@ int cf_qml(const cf_problem* prob, const cf_bins* bins, const double* maps, int3
   const int K = B.ns * B.nb;
   Sizer z;
   size_staging(z, prob, H);
-  fisher_ws(H, B, z, mode);
+  fisher_ws(H, B, z, mode, nmaps);
   z.add<double>((size_t)nmaps * H.n);        // maps copy (host inputs)
   z.add<double>((size_t)H.n * nmaps * 3);    // mixed: d, x, residual
   z.add<double>((size_t)H.n * nmaps);        // D = maps^T
@@ -843,7 +950,7 @@ int cf_qml(const cf_problem* prob, const cf_bins* bins, const double* maps, int3
   Staged S;
   if (int st = stage(bp, prob, H, nullptr, c.s, S)) return st;
   FisherBufs f;
-  fisher_take(bp, H, B, f, mode);
+  fisher_take(bp, H, B, f, mode, nmaps);
   double* mcopy = bp.take<double>((size_t)nmaps * H.n);
   double* mix = bp.take<double>((size_t)H.n * nmaps * 3);
   double* D = bp.take<double>((size_t)H.n * nmaps);
@@ -979,21 +1086,34 @@ int scan_batch(const ScanCtx& x, int64_t i0, int b, int64_t* i0p, Timer* tm) {
                           : x.cl_dev + (i0 * x.nprob + x.p) * 6 * (int64_t)x.lstride;
   CF_DEV(launch_tables(clb, x.S->bl, x.S->pl, h.lmin, h.lmax, b, (int64_t)x.nprob * 6 * x.lstride,
                        x.lstride, x.cwb, nullptr, nullptr, nullptr, c.s, i0p));
-  // a3: covariance of every point of the batch
+  // a3: covariance of every point of the batch.  FP64: slot = [C; d^T] (n + nmaps rows), so that
+  // the factorisation also yields u^T = (L^-1 d)^T; mixed: slot = C (solved and refined apart).
+  const int64_t slot = x.mode ? n * n : (n + nmaps) * n;
   CF_DEV(launch_cov_build(x.S->P, x.cwb, 6 * (int64_t)Lp, b, x.prob->noise_kind, x.S->noise,
-                          x.prob->noise_rank, x.S->noise_U, x.Cb, n, n * n, x.mode ? 0 : 1, x.flags, c.s));
+                          x.prob->noise_rank, x.S->noise_U, x.Cb, n, slot, x.mode ? 0 : 1, x.flags, c.s));
   if (x.mode)
     CF_DEV(hipMemcpyAsync(x.C0b, x.Cb, sizeof(double) * b * n * n, hipMemcpyDeviceToDevice, c.s));
+  else
+    for (int j = 0; j < b; ++j)
+      CF_DEV(hipMemcpyAsync(x.Cb + j * slot + n * n, x.D, sizeof(double) * n * nmaps, hipMemcpyDeviceToDevice, c.s));
   if (tm) tm->mark(ST_BUILD);
   // a4: Cholesky and log det
   Factor F;
-  F.L = x.Cb; F.n = n; F.ld = n; F.sL = n * n;
+  F.L = x.Cb; F.n = n; F.ld = n; F.sL = slot;
   F.Li64 = x.Linv; F.sLi64 = nblk * kNB * kNB;
-  F.Li256 = (n >= 256) ? x.Li256 : nullptr; F.sLi256 = (n / 256) * 256 * 256;
+  F.Li256 = (n >= 256 && x.mode) ? x.Li256 : nullptr; F.sLi256 = (n / 256) * 256 * 256;
   F.ldpart = x.ldp; F.sPart = nblk;
   F.fail = x.flags + 1; F.batch = b; F.mode = x.mode;
+  if (!x.mode) F.rows = n + nmaps;
   if (int st = potrf_on(*c.dev, F, x.pscr, c.s, c.dev->aux[1], c.dev->ev + 8)) return st;
   if (tm) tm->mark(ST_POTRF);
+  if (!x.mode) {   // chi^2_j = |u_j|^2 from the rows below C
+    CF_DEV(launch_rowsumsq(x.Cb + n * n, nmaps, n, n, slot, b, x.x2, nmaps, c.s));
+    CF_DEV(launch_sum_parts(x.ldp, (int)nblk, nblk, b, x.ldb, 1, c.s));
+    CF_DEV(launch_scan_finish(x.x2, x.ldb, b, nmaps, i0, x.p, x.nprob, x.m2, x.chi2, x.ld, c.s, i0p));
+    if (tm) tm->mark(ST_TRSM);
+    return CF_OK;
+  }
   // a6: u = L^-1 d for every map, chi^2 = |u|^2 (FP64); mixed: refined x = C^-1 d, chi^2 = d^T x
   for (int j = 0; j < b; ++j)
     CF_DEV(hipMemcpyAsync(x.Yb + (size_t)j * n * nmaps, x.D, sizeof(double) * n * nmaps,
@@ -1124,7 +1244,7 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   }
   const int Bw = bt_cap;   // workspace sized for the largest batch the tuner may pick
   z.add<double>((size_t)Bw * 6 * L);
-  z.add<double>((size_t)Bw * nmax * nmax);
+  z.add<double>((size_t)Bw * (nmax + (mode ? 0 : nmaps)) * nmax);
   z.add<double>((size_t)Bw * ((nmax + kNB - 1) / kNB) * kNB * kNB);
   z.add<double>((size_t)Bw * (nmax / 256) * 256 * 256);
   z.add<double>((size_t)potrf_scratch(Bw));
@@ -1165,7 +1285,7 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   x.c = &c; x.nprob = nprob; x.nmaps = nmaps; x.lstride = lstride; x.mode = mode; x.refine = refine;
   x.cl_dev = cl_dev;
   x.cwb = bp.take<double>((size_t)Bw * 6 * L);
-  x.Cb = bp.take<double>((size_t)Bw * nmax * nmax);
+  x.Cb = bp.take<double>((size_t)Bw * (nmax + (mode ? 0 : nmaps)) * nmax);
   x.Linv = bp.take<double>((size_t)Bw * ((nmax + kNB - 1) / kNB) * kNB * kNB);
   x.Li256 = bp.take<double>((size_t)Bw * (nmax / 256) * 256 * 256);
   x.pscr = bp.take<double>((size_t)potrf_scratch(Bw));
@@ -1190,7 +1310,10 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   for (int p = 0; p < nprob; ++p) {
     const HostProblem& h = H[p];
     x.p = p; x.prob = &probs[p]; x.h = &h; x.S = &S[p];
-    CF_DEV(launch_transpose(map_dev[p], nmaps, h.n, h.n, x.D, nmaps, c.s));
+    if (mode)   // mixed: D = maps^T (n x nmaps) for the separate solves; FP64: maps as rows
+      CF_DEV(launch_transpose(map_dev[p], nmaps, h.n, h.n, x.D, nmaps, c.s));
+    else
+      CF_DEV(hipMemcpyAsync(x.D, map_dev[p], sizeof(double) * nmaps * h.n, hipMemcpyDeviceToDevice, c.s));
     int b = Bt;
     int64_t i0 = 0;
     // autotuning of the batch size: time one replay for each candidate on the first call of a shape

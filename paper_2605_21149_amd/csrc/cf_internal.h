@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <vector>
 
 namespace cf {
 
@@ -78,6 +79,12 @@ hipError_t gemm_f64(const GemmDesc& g, hipStream_t s);
 // A (batched) Cholesky factor with the inverses of its diagonal blocks.
 struct Factor {
   double* L = nullptr; int64_t n = 0, ld = 0, sL = 0;   // row-major, lower; batch stride sL
+  // Extra rows below the n x n matrix (rows n .. rows-1, same ld) are carried through the
+  // factorisation like rows of a larger matrix: on return they hold B L^-T for their input B,
+  // i.e. the transposed forward solve (L^-1 B^T)^T.  Panels ending at or before column p_early
+  // only touch rows below rows_early (callers put rows that vanish on those columns last).
+  int64_t rows = 0;                                    // 0: n
+  int64_t rows_early = 0, p_early = 0;
   double* Li64 = nullptr; int64_t sLi64 = 0;           // [ceil(n/64)][64][64] inverted 64-blocks
   double* Li256 = nullptr; int64_t sLi256 = 0;         // [n/256][256][256] inverted full 256-blocks (nullable)
   double* ldpart = nullptr; int64_t sPart = 0;         // [ceil(n/64)] per-block sums of ln L_ii
@@ -112,7 +119,9 @@ hipError_t gemv_tn(const double* A, int64_t lda, int64_t M, int64_t K, const dou
                    double* W, int64_t ldw, double* part, hipStream_t s);
 
 // ---------------------------------------------------------------- harmonic basis
-hipError_t launch_ybuild(const DevProblem& P, double* Y, int64_t ldy, hipStream_t s);
+// Y (npix x k, ld ldy); the E,B columns start pgap columns after the T columns (room for
+// other columns solved together with Y).
+hipError_t launch_ybuild(const DevProblem& P, double* Y, int64_t ldy, hipStream_t s, int64_t pgap = 0);
 
 // ---------------------------------------------------------------- Fisher / QML reductions
 hipError_t launch_symmetrize(double* Z, int64_t k, int64_t ldz, hipStream_t s);
@@ -139,6 +148,9 @@ hipError_t launch_transpose(const double* A, int64_t rows, int64_t cols, int64_t
                             int64_t ldb, hipStream_t s);
 hipError_t launch_colsumsq(const double* U, int64_t rows, int64_t cols, int64_t ldu, int64_t sU,
                            int batch, double* out, int64_t sOut, hipStream_t s);
+// out[b][r] = sum_c X[b][r][c]^2 for a batch of row-major (rows x cols, ld ldx) matrices.
+hipError_t launch_rowsumsq(const double* X, int64_t rows, int64_t cols, int64_t ldx, int64_t sX, int batch,
+                           double* out, int64_t sOut, hipStream_t s);
 hipError_t launch_coldot(const double* U, const double* V, int64_t rows, int64_t cols, int64_t ld,
                          int64_t sU, int64_t sV, int batch, double* out, int64_t sOut, hipStream_t s);
 hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s);

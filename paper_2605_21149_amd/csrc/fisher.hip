@@ -307,12 +307,12 @@ __global__ void k_transpose(const double* A, int64_t rows, int64_t cols, int64_t
     if (c0 + r < cols && r0 + tx < rows) B[(c0 + r) * ldb + r0 + tx] = t[tx][r];
 }
 
-// out[b][j] = sum_i U[b][i][j]^2: one workgroup per (column, batch item), fixed-order tree sum.
+// out[b][j] = sum_i U[b][i*ldu + j*cs]^2: one workgroup per (column, batch item), fixed-order tree sum.
 __global__ __launch_bounds__(256) void k_colsumsq(const double* U, int64_t rows, int64_t cols, int64_t ldu,
-                                                  int64_t sU, double* out, int64_t sOut) {
+                                                  int64_t cs, int64_t sU, double* out, int64_t sOut) {
   __shared__ double red[256];
   const int64_t j = blockIdx.x;
-  const double* u = U + blockIdx.z * sU + j;
+  const double* u = U + blockIdx.z * sU + j * cs;
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < rows; i += 256) { const double v = u[i * ldu]; s = fma(v, v, s); }
   red[threadIdx.x] = s;
@@ -498,7 +498,14 @@ hipError_t launch_transpose(const double* A, int64_t rows, int64_t cols, int64_t
 hipError_t launch_colsumsq(const double* U, int64_t rows, int64_t cols, int64_t ldu, int64_t sU,
                            int batch, double* out, int64_t sOut, hipStream_t s) {
   hipLaunchKernelGGL(k_colsumsq, dim3((unsigned)cols, 1, batch), dim3(256), 0, s, U, rows, cols, ldu,
-                     sU, out, sOut);
+                     (int64_t)1, sU, out, sOut);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowsumsq(const double* X, int64_t rows, int64_t cols, int64_t ldx, int64_t sX, int batch,
+                           double* out, int64_t sOut, hipStream_t s) {
+  hipLaunchKernelGGL(k_colsumsq, dim3((unsigned)rows, 1, batch), dim3(256), 0, s, X, cols, rows, (int64_t)1,
+                     ldx, sX, out, sOut);
   return hipGetLastError();
 }
 

@@ -1,4 +1,5 @@
 // Blocked Cholesky C = L L^T, ln|C| from its diagonal, and forward substitution L^-1 Y.
+// Rows appended below C ride along the factorisation and come out as their forward solves.
 //
 // Right-looking, two-level blocking: 256-column outer panels whose 64-column diagonal blocks are
 // factorised and inverted by one workgroup; the column panel below each block is then a GEMM
@@ -283,6 +284,21 @@ GemmDesc upd(const Factor& F, int64_t r0, int64_t c0, int64_t M, int64_t N, int6
   return g;
 }
 
+// X[:, c0..c1) -= X[:, k0..k1) L[c0..c1, k0..k1)^T for the rx extra rows X (ld F.ld).
+GemmDesc xupd(const Factor& F, double* X, int64_t rx, int64_t k0, int64_t k1, int64_t c0, int64_t c1) {
+  GemmDesc u{};
+  u.M = rx; u.N = c1 - c0; u.K = k1 - k0;
+  u.A = X + k0; u.lda = F.ld; u.at = 0;
+  u.B = F.L + c0 * F.ld + k0; u.ldb = F.ld; u.bt = 1;
+  u.C = X + c0; u.ldc = F.ld;
+  u.alpha = -1.0; u.beta = 1.0;
+  u.batch = F.batch; u.sA = F.sL; u.sB = F.sL; u.sC = F.sL;
+  u.mode = F.mode;
+  return u;
+}
+
+constexpr int64_t kDefer = 256;    // measured: deferring to rank-1024 products did not pay off
+
 }  // namespace
 
 hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
@@ -291,13 +307,17 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
   const unsigned nb = F.batch > 0 ? F.batch : 1;
   hipStream_t s = st.s;
   bool pending_b = false, pending_i = false;
+  int64_t px = 0;                            // first panel column whose extra-row update is pending
   // Outer panel width: a single factorisation is bound by its chain of diagonal blocks and keeps
   // 256-column panels; a batch is bound by its trailing updates, which run markedly faster as
   // rank-512 products (the C tile is read and written half as often per flop).
   const int64_t W = nb > 1 ? 512 : 256;
+  const int64_t rows = F.rows > n ? F.rows : n;
+  auto rows_for = [&](int64_t pe) { return (F.rows_early > 0 && pe <= F.p_early) ? F.rows_early : rows; };
+  double* X = F.L + n * lda;                 // extra rows
   for (int64_t c = 0; c < n; c += W) {
     const int64_t pe = (c + W < n) ? c + W : n;
-    // ---- critical path: the diagonal blocks and panels of this outer panel
+    // ---- critical path: the diagonal blocks and panels of this outer panel (rows of C only)
     for (int64_t q = c; q < pe; q += NB) {
       const int b = (int)((n - q) < NB ? (n - q) : NB);
       const int blk = (int)(q / NB);
@@ -325,8 +345,37 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
       for (int64_t q = c; q + OUTER <= pe; q += OUTER) CF_HIP_TRY(tri256(F, (int)(q / OUTER), scratch, st.s2));
       pending_i = true;
     }
-    if (pe >= n) break;
+    // ---- extra rows (side stream): solve against this panel, then pass the contributions of the
+    //      pending panels [px, pe) on to the next panel's columns, and to all later columns once
+    //      they span kDefer columns.  Extra rows never feed back into C, so they trail the
+    //      factorisation.
+    const int64_t rx = rows_for(pe) - n;
     const int64_t pn = (pe + W < n) ? pe + W : n;    // end of the next panel
+    if (rx > 0) {
+      CF_HIP_TRY(hipStreamWaitEvent(st.s2, st.eL, 0));
+      for (int64_t q = c; q < pe; q += NB) {
+        const int b = (int)((n - q) < NB ? (n - q) : NB);
+        GemmDesc g{};                                          // X_q <- X_q L_qq^-T (in place)
+        g.M = rx; g.N = b; g.K = b;
+        g.A = X + q; g.lda = lda; g.at = 0;
+        g.B = F.Li64 + (q / NB) * NB * NB; g.ldb = NB; g.bt = 1;
+        g.C = X + q; g.ldc = lda;
+        g.alpha = 1.0; g.beta = 0.0;
+        g.batch = nb; g.sA = F.sL; g.sB = F.sLi64; g.sC = F.sL;
+        CF_HIP_TRY(gemm_f64(g, st.s2));
+        if (q + b < pe) CF_HIP_TRY(gemm_f64(xupd(F, X, rx, q, q + b, q + b, pe), st.s2));
+      }
+      if (pe < n) {
+        if (pe - px >= kDefer || pn >= n) {        // all pending panels into all later columns
+          CF_HIP_TRY(gemm_f64(xupd(F, X, rx, px, pe, pe, n), st.s2));
+          px = pe;
+        } else {                                   // only into the next panel's columns
+          CF_HIP_TRY(gemm_f64(xupd(F, X, rx, px, pe, pe, pn), st.s2));
+        }
+      }
+      pending_i = true;
+    }
+    if (pe >= n) break;
     // ---- lookahead: the next panel's columns on the critical path, after the previous bulk update
     if (pending_b) CF_HIP_TRY(hipStreamWaitEvent(s, st.eB, 0));
     CF_HIP_TRY(gemm_f64(upd(F, pe, pe, n - pe, pn - pe, c, pe - c), s));

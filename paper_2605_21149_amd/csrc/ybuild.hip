@@ -45,7 +45,8 @@ __device__ void rec_step(Rec& r, double mu) {
   r.l += 1;
 }
 
-__global__ __launch_bounds__(128) void k_ybuild(DevProblem P, double* __restrict__ Y, int64_t ldy) {
+__global__ __launch_bounds__(128) void k_ybuild(DevProblem P, double* __restrict__ Y, int64_t ldy,
+                                                int64_t pgap) {
   const int p = blockIdx.x;
   const double* rec = P.pix + (int64_t)p * kPixRec;
   const double z = rec[8], phi = rec[9];
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(128) void k_ybuild(DevProblem P, double* __restrict
     double* yt = Y + rowT * ldy;
     double* yq = Y + rowQ * ldy;
     double* yu = Y + rowU * ldy;
-    for (int64_t q = threadIdx.x; q < 2 * (int64_t)kf; q += blockDim.x) yt[kf + q] = 0.0;
+    for (int64_t q = threadIdx.x; q < 2 * (int64_t)kf; q += blockDim.x) yt[kf + pgap + q] = 0.0;
     for (int64_t q = threadIdx.x; q < kf; q += blockDim.x) { yq[q] = 0.0; yu[q] = 0.0; }
   }
 
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(128) void k_ybuild(DevProblem P, double* __restrict
           const double Fp = -0.5 * nrm * (dm + dp);
           const double Fm = 0.5 * nrm * (dm - dp);
           const int64_t base = l * l - lm2 + cs0;
-          const int64_t ce = (int64_t)fE * kf + base, cb = (int64_t)fB * kf + base;
+          const int64_t ce = (int64_t)fE * kf + pgap + base, cb = (int64_t)fB * kf + pgap + base;
           if (m == 0) {
             // E_l0 = Fp (real), B_l0 = 0
             yq[ce] = Fp; yq[cb] = 0.0;
@@ -125,9 +126,9 @@ __global__ __launch_bounds__(128) void k_ybuild(DevProblem P, double* __restrict
 
 }  // namespace
 
-hipError_t launch_ybuild(const DevProblem& P, double* Y, int64_t ldy, hipStream_t s) {
+hipError_t launch_ybuild(const DevProblem& P, double* Y, int64_t ldy, hipStream_t s, int64_t pgap) {
   if (P.npx <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ybuild, dim3(P.npx), dim3(128), 0, s, P, Y, ldy);
+  hipLaunchKernelGGL(k_ybuild, dim3(P.npx), dim3(128), 0, s, P, Y, ldy, pgap);
   return hipGetLastError();
 }
 
