@@ -583,20 +583,27 @@ int fisher_core_fp64(const cf_problem* prob, const HostProblem& H, const Staged&
   if (split) { F.rows_early = n + nm + kT; F.p_early = H.npx; }
   if (int st = potrf_on(*cc.dev, F, f.scratch, s, s2, ev + 8)) return st;
   tm.mark(ST_POTRF);
-  hipEvent_t tz = tm.open(s);
+  // Z = G^T G, lower blocks.  The symmetric product of the largest field block is the separately
+  // named kernel instance (tag 1) whose launch the stage timer brackets on its own stream.
   if (split) {
-    // Z rows of E,B against all columns (lower part), over columns >= p0 (aux[0])
+    // E,B rows (columns >= p0 only; aux[0]): against the T columns, then the E,B block
     CF_DEV(hipEventRecord(ev[E_L], s));
     CF_DEV(hipStreamWaitEvent(s1, ev[E_L], 0));
     GemmDesc h{};
-    h.M = kP; h.N = k; h.K = n - p0;
+    h.M = kP; h.N = kT; h.K = n - p0;
     h.A = Gt + kT * n + p0; h.lda = n; h.at = 0;
     h.B = Gt + p0; h.ldb = n; h.bt = 1;
-    h.C = f.Z + kT * k; h.ldc = k; h.alpha = 1.0; h.beta = 0.0; h.lower = 1; h.diag_off = kT;
-    h.batch = 1;
+    h.C = f.Z + kT * k; h.ldc = k; h.alpha = 1.0; h.beta = 0.0; h.batch = 1;
     CF_DEV(gemm_f64(h, s1));
+    GemmDesc e = h;
+    e.N = kP;
+    e.B = Gt + kT * n + p0;
+    e.C = f.Z + kT * k + kT; e.lower = 1; e.tag = 1;
+    hipEvent_t tz = tm.open(s1);
+    CF_DEV(gemm_f64(e, s1));
+    tm.close(ST_SYRK, tz, s1);
     CF_DEV(hipEventRecord(ev[E_S1], s1));
-    // Z_TT over all columns (s)
+    // T block over all columns (s)
     GemmDesc g{};
     g.M = kT; g.N = kT; g.K = n;
     g.A = Gt; g.lda = n; g.at = 0;
@@ -609,10 +616,11 @@ int fisher_core_fp64(const cf_problem* prob, const HostProblem& H, const Staged&
     g.M = k; g.N = k; g.K = n;
     g.A = Gt; g.lda = n; g.at = 0;
     g.B = Gt; g.ldb = n; g.bt = 1;
-    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1;
+    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1; g.tag = 1;
+    hipEvent_t tz = tm.open(s);
     CF_DEV(gemm_f64(g, s));
+    tm.close(ST_SYRK, tz, s);
   }
-  tm.close(ST_SYRK, tz, s);
   if (qb) {   // w = G^T u  (k x nm)
     GemmDesc w{};
     w.M = k; w.N = nm; w.K = n;

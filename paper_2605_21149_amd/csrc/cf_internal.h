@@ -73,6 +73,7 @@ struct GemmDesc {
   int64_t diag_off;                       // with lower: the diagonal is col = row + diag_off
   int batch; int64_t sA, sB, sC;          // batch count and element strides
   int mode;                               // 0 FP64 MFMA, 1 FP32 MFMA, 2 split-BF16 x3 MFMA
+  int tag;                                // 1: Z = G^T G (a separately named kernel instance)
 };
 hipError_t gemm_f64(const GemmDesc& g, hipStream_t s);
 

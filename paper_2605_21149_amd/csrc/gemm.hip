@@ -88,7 +88,8 @@ __device__ __forceinline__ bool tile_of(const GemmArgs& g, int64_t& z, int& tm, 
   return tile_map(g.remap, g.tiles_m, g.tiles_n, gridDim.x, gridDim.z, blockIdx.x, blockIdx.z, z, tm, tn);
 }
 
-template <int BM, int BN, bool AT, bool BT>
+// TAG only names a separate instance (profiles can then tell the Z = G^T G launches apart).
+template <int BM, int BN, bool AT, bool BT, int TAG = 0>
 __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2, MI = WM / 16, NI = WN / 16;
@@ -428,7 +429,9 @@ hipError_t launch_tile(const GemmDesc& d, hipStream_t s) {
   else if (d.at) hipLaunchKernelGGL((KER<BM, BN, true, false>), grid, block, 0, s, g);     \
   else if (d.bt) hipLaunchKernelGGL((KER<BM, BN, false, true>), grid, block, 0, s, g);     \
   else hipLaunchKernelGGL((KER<BM, BN, false, false>), grid, block, 0, s, g);
-  if (d.mode == 1) {
+  if (d.tag == 1 && d.mode == 0 && !d.at && d.bt) {
+    hipLaunchKernelGGL((k_gemm<BM, BN, false, true, 1>), grid, block, 0, s, g);
+  } else if (d.mode == 1) {
     CF_GEMM_MODE(k_gemm_lp1)
   } else if (d.mode == 2) {
     CF_GEMM_MODE(k_gemm_lp2)
