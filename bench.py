@@ -82,7 +82,12 @@ def emulator_bench(cf, I, n_train, epochs, n_query, spread_max=0.1, seed_map=403
     torch.cuda.synchronize()
     xt = I.scan_points(n_train, seed=501)
     t0 = time.perf_counter()
-    yt = torch.cat([exact(xt[i:i + 16384]) for i in range(0, n_train, 16384)])
+    parts = []
+    for i in range(0, n_train, 16384):
+        parts.append(exact(xt[i:i + 16384]))
+        torch.cuda.synchronize()
+        _log(f"emulator: exact points {min(i + 16384, n_train)} / {n_train}")
+    yt = torch.cat(parts)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     exact_rate = n_train / t_gen
@@ -115,6 +120,7 @@ def emulator_bench(cf, I, n_train, epochs, n_query, spread_max=0.1, seed_map=403
     _log(f"emulator: {fb.mean():.3f} fallback, predict {t_fb:.2f} s")
     return {
         "problem": f"QU N_side 16 scan (n={n}), 7 parameters, map 0",
+        "target_std": float(yt.std().item()),
         "network": "7-256-256-256-1 SiLU, 4 members, BF16 MFMA hidden products / FP32 accumulate",
         "train_points": n_train, "epochs": epochs, "train_steps": tr["ir_iters"],
         "exact_gen_s": t_gen, "exact_points_per_s": exact_rate,
