@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A_base, int64_t lda,
           colblk[buf][4 * ty + i][cc] = l[i][cc];
         }
     }
-    if (ty == J) {
+    if (ty == J && tx <= J) {          // X_J vanishes right of column group J
       double xn[4][4];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -151,42 +151,30 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A_base, int64_t lda,
         }
     }
     __syncthreads();
-    // ---- C: rank-4 updates below
-    if (ty > J) {
+    // ---- C: rank-4 updates below.  Lanes right of the column group update the factor (only on or
+    //      below the diagonal: J < tx <= ty), lanes left of it the inverse (X_J vanishes right of J:
+    //      tx <= J); one shared FMA path with per-lane operands.
+    if (ty > J && tx <= ty) {
+      const bool inv = tx <= J;
       double lr[4][4];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) lr[i][cc] = colblk[buf][4 * ty + i][cc];
-      if (tx > J) {
-        double lq[4][4];
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj)
-#pragma unroll
-          for (int cc = 0; cc < 4; ++cc) lq[jj][cc] = colblk[buf][4 * tx + jj][cc];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj) {
-            double t = a[i][jj];
-#pragma unroll
-            for (int cc = 0; cc < 4; ++cc) t = fma(-lr[i][cc], lq[jj][cc], t);
-            a[i][jj] = t;
-          }
-      }
-      double xj[4][4];
+      double w[4][4];                  // w[cc][jj]: X_J[cc][4tx+jj] or L_QJ[4tx+jj][cc]
 #pragma unroll
       for (int cc = 0; cc < 4; ++cc)
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) xj[cc][jj] = rowblk[buf][cc][4 * tx + jj];
+        for (int jj = 0; jj < 4; ++jj)
+          w[cc][jj] = inv ? rowblk[buf][cc][4 * tx + jj] : colblk[buf][4 * tx + jj][cc];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
-          double t = x[i][jj];
+          double t = inv ? x[i][jj] : a[i][jj];
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc) t = fma(-lr[i][cc], xj[cc][jj], t);
-          x[i][jj] = t;
+          for (int cc = 0; cc < 4; ++cc) t = fma(-lr[i][cc], w[cc][jj], t);
+          if (inv) x[i][jj] = t; else a[i][jj] = t;
         }
     }
   }
