@@ -142,6 +142,7 @@ __global__ void k_fisher_assemble(GramView G, int ns, int s0, int s1, int s2, in
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= K * K) return;
   const int A = idx / K, B = idx % K;
+  if (A < B) return;                   // one evaluation per symmetric pair, mirrored below
   const int specs[6] = {s0, s1, s2, s3, s4, s5};
   const int sa = specs[A / nb], ba = A % nb, sb = specs[B / nb], bb = B % nb;
   int xa, ya, xb, yb;
@@ -164,6 +165,7 @@ __global__ void k_fisher_assemble(GramView G, int ns, int s0, int s1, int s2, in
     }
   }
   F[idx] = 0.5 * sum;
+  F[(int64_t)B * K + A] = 0.5 * sum;
 }
 
 // One workgroup per parameter A: the (l, sigma, l', f, g) terms are spread over the threads and
