@@ -1033,10 +1033,12 @@ struct ScanGraph {
 std::mutex g_graph_mu;
 std::vector<ScanGraph> g_graphs[64];
 
-// Autotuned batch size per scan shape (n, nmaps, mode), in memory and in a small text file.
-struct TuneEntry { int64_t n; int nmaps, mode, bt; };
+// Autotuned launch shape of the scan per (n, nmaps, mode): points per batch, outer panel width
+// of the batched factorisation and GEMM tile of its updates; in memory and in a small text file
+// (one line per shape: "scan gfx950 n=.. nmaps=.. mode=.. batch=.. panel=.. tile=..").
+struct TuneEntry { int64_t n; int nmaps, mode, bt, panel, tile; };
 std::vector<TuneEntry> g_tune;
-bool g_tune_loaded = false;
+std::string g_tune_loaded;            // path the table was read from
 
 std::string tune_path() {
   const char* p = getenv("CF_TUNE_CACHE");
@@ -1045,29 +1047,37 @@ std::string tune_path() {
   return std::string(h && *h ? h : "/tmp") + "/.cf_autotune.txt";
 }
 void tune_load() {
-  if (g_tune_loaded) return;
-  g_tune_loaded = true;
-  FILE* f = fopen(tune_path().c_str(), "r");
+  const std::string path = tune_path();
+  if (g_tune_loaded == path) return;
+  g_tune_loaded = path;
+  g_tune.clear();
+  FILE* f = fopen(path.c_str(), "r");
   if (!f) return;
-  TuneEntry e;
-  long long n;
-  while (fscanf(f, "scan gfx950 n=%lld nmaps=%d mode=%d batch=%d\n", &n, &e.nmaps, &e.mode, &e.bt) == 4) {
+  char line[256];
+  while (fgets(line, sizeof line, f)) {
+    TuneEntry e{};
+    long long n;
+    const int got = sscanf(line, "scan gfx950 n=%lld nmaps=%d mode=%d batch=%d panel=%d tile=%d", &n, &e.nmaps,
+                           &e.mode, &e.bt, &e.panel, &e.tile);
+    if (got < 4) continue;
+    if (got < 6) e.panel = e.tile = 0;
     e.n = n;
     g_tune.push_back(e);
   }
   fclose(f);
 }
-int tune_get(int64_t n, int nmaps, int mode) {
+const TuneEntry* tune_get(int64_t n, int nmaps, int mode) {
   tune_load();
   for (auto& e : g_tune)
-    if (e.n == n && e.nmaps == nmaps && e.mode == mode) return e.bt;
-  return 0;
+    if (e.n == n && e.nmaps == nmaps && e.mode == mode) return &e;
+  return nullptr;
 }
-void tune_put(int64_t n, int nmaps, int mode, int bt) {
-  g_tune.push_back({n, nmaps, mode, bt});
+void tune_put(const TuneEntry& e) {
+  g_tune.push_back(e);
   FILE* f = fopen(tune_path().c_str(), "a");
   if (!f) return;
-  fprintf(f, "scan gfx950 n=%lld nmaps=%d mode=%d batch=%d\n", (long long)n, nmaps, mode, bt);
+  fprintf(f, "scan gfx950 n=%lld nmaps=%d mode=%d batch=%d panel=%d tile=%d\n", (long long)e.n, e.nmaps, e.mode,
+          e.bt, e.panel, e.tile);
   fclose(f);
 }
 
@@ -1077,6 +1087,7 @@ struct ScanCtx {
   const HostProblem* h;
   const Staged* S;
   int p, nprob, nmaps, lstride, mode, refine;
+  int panel = 0, tile = 0;            // launch shape of the batched factorisation (0: defaults)
   const double* cl_dev;
   double *cwb, *Cb, *C0b, *Linv, *Li256, *pscr, *ldp, *D, *Yb, *Gb, *Xb, *Rb, *x2, *ldb;
   int* flags;
@@ -1115,6 +1126,7 @@ int scan_batch(const ScanCtx& x, int64_t i0, int b, int64_t* i0p, Timer* tm) {
   F.Li256 = (n >= 256 && x.mode) ? x.Li256 : nullptr; F.sLi256 = (n / 256) * 256 * 256;
   F.ldpart = x.ldp; F.sPart = nblk;
   F.fail = x.flags + 1; F.batch = b; F.mode = x.mode;
+  F.panel = x.panel; F.tile = x.tile;
   if (!x.mode) F.rows = n + nmaps;
   if (int st = potrf_on(*c.dev, F, x.pscr, c.s, c.dev->aux[1], c.dev->ev + 8)) return st;
   if (tm) tm->mark(ST_POTRF);
@@ -1157,8 +1169,9 @@ int scan_batch(const ScanCtx& x, int64_t i0, int b, int64_t* i0p, Timer* tm) {
 
 std::string graph_key(const ScanCtx& x, int b, const char* ws) {
   char buf[512];
-  snprintf(buf, sizeof buf, "%d|%lld|%d|%d|%d|%d|%d|%d|%zu|%p|%p|%p|%p|%p|%p|%p|%p|%p", x.p,
-           (long long)x.h->n, b, x.nmaps, x.mode, x.refine, x.lstride, x.nprob, x.layout, (const void*)ws,
+  snprintf(buf, sizeof buf, "%d|%lld|%d|%d|%d|%d|%d|%d|%d|%d|%zu|%p|%p|%p|%p|%p|%p|%p|%p|%p", x.p,
+           (long long)x.h->n, b, x.nmaps, x.mode, x.refine, x.lstride, x.nprob, x.panel, x.tile, x.layout,
+           (const void*)ws,
            (const void*)x.cl_dev, (const void*)x.D, (const void*)x.m2, (const void*)x.chi2,
            (const void*)x.ld, (const void*)x.S->noise, (const void*)x.S->noise_U, (const void*)x.c->s);
   return buf;
@@ -1244,10 +1257,11 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   const size_t per = (size_t)nmax * nmax * 8 * (mode ? 2 : 1);
   const int bt_cap = (int)std::min<size_t>(16, std::max<size_t>(1, (size_t(6) << 30) / per));
   int Bt = bt_cap;
-  if (nprob == 1) {
-    const int tuned = tune_get(nmax, nmaps, mode);
-    if (tuned > 0) Bt = std::min(tuned, bt_cap);
-  }
+  TuneEntry tuned_e{};
+  const TuneEntry* tp = nprob == 1 ? tune_get(nmax, nmaps, mode) : nullptr;
+  if (tp) tuned_e = *tp;                     // copied: tune_put may grow the table
+  const bool tuned = tp != nullptr;
+  if (tuned && tuned_e.bt > 0) Bt = std::min(tuned_e.bt, bt_cap);
   if (Bt > npoints) Bt = npoints;
   const int L = lmax_all + 1;
   Sizer z;
@@ -1331,12 +1345,18 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
       CF_DEV(hipMemcpyAsync(x.D, map_dev[p], sizeof(double) * nmaps * h.n, hipMemcpyDeviceToDevice, c.s));
     int b = Bt;
     int64_t i0 = 0;
-    // autotuning of the batch size: time one replay for each candidate on the first call of a shape
-    if (ex && ex->autotune && nprob == 1 && tune_get(h.n, nmaps, mode) == 0 && npoints >= 2) {
-      int best = Bt;
+    if (tuned) { x.panel = tuned_e.panel; x.tile = tuned_e.tile; }
+    // autotuning on the first call of a shape: time one batch per candidate, in three rounds
+    // (points per batch; then outer panel width; then GEMM tile), each round keeping the best
+    // rate; the tuning batches are part of the scan's own points.
+    if (ex && ex->autotune && nprob == 1 && !tuned && npoints >= 2) {
       double best_rate = 0.0;
-      for (int cand : {2, 4, 8, 16}) {
-        if (cand > bt_cap || cand > npoints - i0) break;
+      TuneEntry best{h.n, nmaps, mode, Bt, 0, 0};
+      auto trial = [&](int cand, int panel, int tile, bool* ran) -> int {
+        *ran = false;
+        if (cand > bt_cap || cand > npoints - i0) return CF_OK;
+        x.panel = panel;
+        x.tile = tile;
         if (use_graph) { if (int st = scan_replay(x, i0, cand, 0, i0p)) return st; }   // capture first
         hipEvent_t e0, e1;
         CF_DEV(hipEventCreate(&e0));
@@ -1351,11 +1371,29 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         const double rate = cand / (double)ms;
-        if (rate > best_rate) { best_rate = rate; best = cand; }
+        if (rate > best_rate) { best_rate = rate; best.bt = cand; best.panel = panel; best.tile = tile; }
         i0 += cand;
+        *ran = true;
+        return CF_OK;
+      };
+      bool ran = false;
+      for (int cand : {2, 4, 8, 16}) {
+        if (int st = trial(cand, 0, 0, &ran)) return st;
+        if (!ran) break;
       }
-      tune_put(h.n, nmaps, mode, best);
-      b = best;
+      if (h.n > 512)
+        for (int panel : {256, 512}) {
+          if (int st = trial(best.bt, panel, best.tile, &ran)) return st;
+          if (!ran) break;
+        }
+      for (int tile : {64, 128}) {
+        if (int st = trial(best.bt, best.panel, tile, &ran)) return st;
+        if (!ran) break;
+      }
+      tune_put(best);
+      b = best.bt;
+      x.panel = best.panel;
+      x.tile = best.tile;
     }
     const int64_t nfull = (npoints - i0) / b;
     if (use_graph && nfull >= 1) {

@@ -74,6 +74,7 @@ struct GemmDesc {
   int batch; int64_t sA, sB, sC;          // batch count and element strides
   int mode;                               // 0 FP64 MFMA, 1 FP32 MFMA, 2 split-BF16 x3 MFMA
   int tag;                                // 1: Z = G^T G (a separately named kernel instance)
+  int tile;                               // 0: by size; 64 or 128: that workgroup tile
 };
 hipError_t gemm_f64(const GemmDesc& g, hipStream_t s);
 
@@ -92,6 +93,8 @@ struct Factor {
   int* fail = nullptr;                                 // first non-positive pivot (atomicMin)
   int batch = 1;
   int mode = 0;                                        // GEMM mode of the bulk updates and solves
+  int panel = 0;                                       // outer panel width (0: 256 single, 512 batched)
+  int tile = 0;                                        // GEMM tile of the updates (0: by size)
 };
 // Streams for the factorisation: s carries the critical path (diagonal blocks, panels and the
 // lookahead column update), s1 the bulk trailing updates, s2 the 256-block inverses.

@@ -455,6 +455,8 @@ hipError_t gemm_f64(const GemmDesc& d, hipStream_t s) {
     // C = beta * C (alpha term vanishes): not needed by any caller; treat as a no-op only when beta == 1
     return d.beta == 1.0 ? hipSuccess : hipErrorInvalidValue;
   }
+  if (d.tile == 128) return launch_tile<128, 128>(d, s);
+  if (d.tile == 64) return launch_tile<64, 64>(d, s);
   const int64_t batch = d.batch > 0 ? d.batch : 1;
   const int64_t big = ((d.M + 127) / 128) * ((d.N + 127) / 128) * batch;
   if (big >= 480) return launch_tile<128, 128>(d, s);

@@ -269,6 +269,7 @@ GemmDesc upd(const Factor& F, int64_t r0, int64_t c0, int64_t M, int64_t N, int6
   g.alpha = -1.0; g.beta = 1.0; g.lower = 1; g.diag_off = c0 - r0;
   g.batch = F.batch; g.sA = F.sL; g.sB = F.sL; g.sC = F.sL;
   g.mode = F.mode;
+  g.tile = F.tile;
   return g;
 }
 
@@ -282,6 +283,7 @@ GemmDesc xupd(const Factor& F, double* X, int64_t rx, int64_t k0, int64_t k1, in
   u.alpha = -1.0; u.beta = 1.0;
   u.batch = F.batch; u.sA = F.sL; u.sB = F.sL; u.sC = F.sL;
   u.mode = F.mode;
+  u.tile = F.tile;
   return u;
 }
 
@@ -302,7 +304,7 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
   // Outer panel width: a single factorisation is bound by its chain of diagonal blocks and keeps
   // 256-column panels; a batch is bound by its trailing updates, which run markedly faster as
   // rank-512 products (the C tile is read and written half as often per flop).
-  const int64_t W = nb > 1 ? 512 : 256;
+  const int64_t W = F.panel > 0 ? F.panel : (nb > 1 ? 512 : 256);
   const int64_t rows = F.rows > n ? F.rows : n;
   auto rows_for = [&](int64_t pe) { return (F.rows_early > 0 && pe <= F.p_early) ? F.rows_early : rows; };
   double* X = F.L + n * lda;                 // extra rows

@@ -264,3 +264,10 @@ def test_loglike_autotune_records_a_batch_size(tmp_path, monkeypatch):
     got = cf.loglike_batch([p], clp, [maps], device=True, autotune=True)
     ref, _ = likelihood.scan(p, maps, clp[:, 0])
     np.testing.assert_allclose(to_np(got["m2lnL"])[:, 0], ref, rtol=TOL)
+    lines = (tmp_path / "tune.txt").read_text().splitlines()
+    say("  tuned:", lines)
+    assert len(lines) == 1 and f"n={p.n} nmaps=2 mode=0 batch=" in lines[0] and "tile=" in lines[0]
+    # the recorded shape is reused: no second tuning, same results
+    again = cf.loglike_batch([p], clp, [maps], device=True, autotune=True)
+    assert len((tmp_path / "tune.txt").read_text().splitlines()) == 1
+    np.testing.assert_allclose(to_np(again["m2lnL"])[:, 0], ref, rtol=TOL)
