@@ -1348,48 +1348,47 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
     if (tuned) { x.panel = tuned_e.panel; x.tile = tuned_e.tile; }
     // autotuning on the first call of a shape: time one batch per candidate, in three rounds
     // (points per batch; then outer panel width; then GEMM tile), each round keeping the best
-    // rate; the tuning batches are part of the scan's own points.
+    // rate.  Trials run the first points of the scan (best of two timings each); the scan itself
+    // then runs in full with the chosen shape, so every output comes from one configuration.
     if (ex && ex->autotune && nprob == 1 && !tuned && npoints >= 2) {
       double best_rate = 0.0;
       TuneEntry best{h.n, nmaps, mode, Bt, 0, 0};
-      auto trial = [&](int cand, int panel, int tile, bool* ran) -> int {
-        *ran = false;
-        if (cand > bt_cap || cand > npoints - i0) return CF_OK;
+      const bool verbose = getenv("CF_TUNE_VERBOSE") != nullptr;
+      auto trial = [&](int cand, int panel, int tile) -> int {
+        if (cand > bt_cap || cand > npoints) return CF_OK;
         x.panel = panel;
         x.tile = tile;
-        if (use_graph) { if (int st = scan_replay(x, i0, cand, 0, i0p)) return st; }   // capture first
+        if (use_graph) { if (int st = scan_replay(x, 0, cand, 0, i0p)) return st; }   // capture first
         hipEvent_t e0, e1;
         CF_DEV(hipEventCreate(&e0));
         CF_DEV(hipEventCreate(&e1));
-        CF_DEV(hipEventRecord(e0, c.s));
-        if (use_graph) { if (int st = scan_replay(x, i0, cand, 1, i0p)) return st; }
-        else if (int st = scan_batch(x, i0, cand, nullptr, nullptr)) return st;
-        CF_DEV(hipEventRecord(e1, c.s));
-        CF_DEV(hipEventSynchronize(e1));
-        float ms = 0.f;
-        CF_DEV(hipEventElapsedTime(&ms, e0, e1));
+        float best_ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+          CF_DEV(hipEventRecord(e0, c.s));
+          if (use_graph) { if (int st = scan_replay(x, 0, cand, 1, i0p)) return st; }
+          else if (int st = scan_batch(x, 0, cand, nullptr, nullptr)) return st;
+          CF_DEV(hipEventRecord(e1, c.s));
+          CF_DEV(hipEventSynchronize(e1));
+          float ms = 0.f;
+          CF_DEV(hipEventElapsedTime(&ms, e0, e1));
+          if (rep == 0 || ms < best_ms) best_ms = ms;
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        const double rate = cand / (double)ms;
+        const double rate = cand / (double)best_ms;
+        if (verbose)
+          fprintf(stderr, "cf autotune n=%d nmaps=%d mode=%d batch=%d panel=%d tile=%d: %.3f ms per point\n",
+                  h.n, nmaps, mode, cand, panel, tile, best_ms / cand);
         if (rate > best_rate) { best_rate = rate; best.bt = cand; best.panel = panel; best.tile = tile; }
-        i0 += cand;
-        *ran = true;
         return CF_OK;
       };
-      bool ran = false;
-      for (int cand : {2, 4, 8, 16}) {
-        if (int st = trial(cand, 0, 0, &ran)) return st;
-        if (!ran) break;
-      }
+      for (int cand : {2, 4, 8, 16})
+        if (int st = trial(cand, 0, 0)) return st;
       if (h.n > 512)
-        for (int panel : {256, 512}) {
-          if (int st = trial(best.bt, panel, best.tile, &ran)) return st;
-          if (!ran) break;
-        }
-      for (int tile : {64, 128}) {
-        if (int st = trial(best.bt, best.panel, tile, &ran)) return st;
-        if (!ran) break;
-      }
+        for (int panel : {256, 512})
+          if (int st = trial(best.bt, panel, best.tile)) return st;
+      for (int tile : {64, 128})
+        if (int st = trial(best.bt, best.panel, tile)) return st;
       tune_put(best);
       b = best.bt;
       x.panel = best.panel;

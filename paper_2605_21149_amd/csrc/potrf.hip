@@ -8,6 +8,7 @@
 // L^-1 Y recurses on halves of the row range: leaves multiply by the inverted 64 x 64 diagonal
 // block, interior nodes are GEMM updates.  Every flop outside the 64 x 64 blocks runs on MFMA.
 #include "cf_internal.h"
+#include <functional>
 
 #include <climits>
 
@@ -308,29 +309,53 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
   const int64_t rows = F.rows > n ? F.rows : n;
   auto rows_for = [&](int64_t pe) { return (F.rows_early > 0 && pe <= F.p_early) ? F.rows_early : rows; };
   double* X = F.L + n * lda;                 // extra rows
+  // One 64-column block: factor and invert the diagonal block, then X <- X L11^-T for the column
+  // panel below it (in place; each tile owns its rows).
+  auto block = [&](int64_t q) -> hipError_t {
+    const int b = (int)((n - q) < NB ? (n - q) : NB);
+    const int blk = (int)(q / NB);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, nb), dim3(256), 0, s, F.L, lda, F.sL, q, b, F.Li64,
+                       F.sLi64, F.ldpart, F.sPart, blk, F.fail);
+    CF_HIP_TRY(hipGetLastError());
+    const int64_t below = n - (q + b);
+    if (below <= 0) return hipSuccess;
+    GemmDesc g{};
+    g.M = below; g.N = b; g.K = b;
+    g.A = F.L + (q + b) * lda + q; g.lda = lda; g.at = 0;
+    g.B = F.Li64 + (int64_t)blk * NB * NB; g.ldb = NB; g.bt = 1;
+    g.C = F.L + (q + b) * lda + q; g.ldc = lda;
+    g.alpha = 1.0; g.beta = 0.0; g.lower = 0;
+    g.batch = nb; g.sA = F.sL; g.sB = F.sLi64; g.sC = F.sL;
+    return gemm_f64(g, s);
+  };
+  // Right-looking panel: after each block, a rank-64 update of the panel's remaining columns.
+  // Each launch is short (K = 64), which suits a single factorisation whose launches fill only
+  // part of the chip and whose chain is bound by launch latency.
+  auto panel_right = [&](int64_t c0, int64_t c1) -> hipError_t {
+    for (int64_t q = c0; q < c1; q += NB) {
+      CF_HIP_TRY(block(q));
+      const int64_t qe = q + NB;
+      if (qe < c1) CF_HIP_TRY(gemm_f64(upd(F, qe, qe, n - qe, c1 - qe, q, NB), s));
+    }
+    return hipSuccess;
+  };
+  // Recursive panel: factor the left half, update the right half with one product of rank equal
+  // to the left half's width, factor the right half.  The same flops as the right-looking order,
+  // but half of them in rank-(W/2) products, which run several times faster per flop than rank-64
+  // ones once a batch fills the chip.
+  std::function<hipError_t(int64_t, int64_t)> panel_rec = [&](int64_t c0, int64_t c1) -> hipError_t {
+    if (c1 - c0 <= NB) return block(c0);
+    const int64_t nbk = (c1 - c0 + NB - 1) / NB;
+    const int64_t mid = c0 + ((nbk + 1) / 2) * NB;
+    CF_HIP_TRY(panel_rec(c0, mid));
+    CF_HIP_TRY(gemm_f64(upd(F, mid, mid, n - mid, c1 - mid, c0, mid - c0), s));
+    return panel_rec(mid, c1);
+  };
+  const bool rec = nb > 1;   // measured on batches of 8 at n = 5952: 20.0 -> 18.5 ms
   for (int64_t c = 0; c < n; c += W) {
     const int64_t pe = (c + W < n) ? c + W : n;
     // ---- critical path: the diagonal blocks and panels of this outer panel (rows of C only)
-    for (int64_t q = c; q < pe; q += NB) {
-      const int b = (int)((n - q) < NB ? (n - q) : NB);
-      const int blk = (int)(q / NB);
-      hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, nb), dim3(256), 0, s, F.L, lda, F.sL, q, b, F.Li64,
-                         F.sLi64, F.ldpart, F.sPart, blk, F.fail);
-      CF_HIP_TRY(hipGetLastError());
-      const int64_t below = n - (q + b);
-      if (below <= 0) continue;
-      {   // column panel below the block: X <- X L11^-T, in place (each tile owns its rows)
-        GemmDesc g{};
-        g.M = below; g.N = b; g.K = b;
-        g.A = F.L + (q + b) * lda + q; g.lda = lda; g.at = 0;
-        g.B = F.Li64 + (int64_t)blk * NB * NB; g.ldb = NB; g.bt = 1;
-        g.C = F.L + (q + b) * lda + q; g.ldc = lda;
-        g.alpha = 1.0; g.beta = 0.0; g.lower = 0;
-        g.batch = nb; g.sA = F.sL; g.sB = F.sLi64; g.sC = F.sL;
-        CF_HIP_TRY(gemm_f64(g, s));
-      }
-      if (q + b < pe) CF_HIP_TRY(gemm_f64(upd(F, q + b, q + b, below, pe - (q + b), q, b), s));
-    }
+    CF_HIP_TRY(rec ? panel_rec(c, pe) : panel_right(c, pe));
     CF_HIP_TRY(hipEventRecord(st.eL, s));
     // ---- keep the host at most two panels ahead of the device.  Measured: with every panel of
     //      every stream queued up front, the device dispatches the critical chain markedly later
