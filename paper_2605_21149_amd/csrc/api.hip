@@ -1106,13 +1106,16 @@ int scan_batch(const ScanCtx& x, int64_t i0, int b, int64_t* i0p, Timer* tm) {
   // a2: per-point weights c^XY_l
   const double* clb = i0p ? x.cl_dev + (int64_t)x.p * 6 * x.lstride
                           : x.cl_dev + (i0 * x.nprob + x.p) * 6 * (int64_t)x.lstride;
+  // points of a batch share each pixel pair's recurrences in groups of kCovIB
+  const int inter = b > 1 ? kCovIB : 1;
   CF_DEV(launch_tables(clb, x.S->bl, x.S->pl, h.lmin, h.lmax, b, (int64_t)x.nprob * 6 * x.lstride,
-                       x.lstride, x.cwb, nullptr, nullptr, nullptr, c.s, i0p));
+                       x.lstride, x.cwb, nullptr, nullptr, nullptr, c.s, i0p, inter));
   // a3: covariance of every point of the batch.  FP64: slot = [C; d^T] (n + nmaps rows), so that
   // the factorisation also yields u^T = (L^-1 d)^T; mixed: slot = C (solved and refined apart).
   const int64_t slot = x.mode ? n * n : (n + nmaps) * n;
-  CF_DEV(launch_cov_build(x.S->P, x.cwb, 6 * (int64_t)Lp, b, x.prob->noise_kind, x.S->noise,
-                          x.prob->noise_rank, x.S->noise_U, x.Cb, n, slot, x.mode ? 0 : 1, x.flags, c.s));
+  CF_DEV(launch_cov_build(x.S->P, x.cwb, 6 * (int64_t)Lp * inter, b, x.prob->noise_kind, x.S->noise,
+                          x.prob->noise_rank, x.S->noise_U, x.Cb, n, slot, x.mode ? 0 : 1, x.flags, c.s,
+                          inter));
   if (x.mode)
     CF_DEV(hipMemcpyAsync(x.C0b, x.Cb, sizeof(double) * b * n * n, hipMemcpyDeviceToDevice, c.s));
   else
@@ -1272,7 +1275,8 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
     z.add<double>((size_t)npoints * nprob * nmaps * 2 + (size_t)npoints * nprob);
   }
   const int Bw = bt_cap;   // workspace sized for the largest batch the tuner may pick
-  z.add<double>((size_t)Bw * 6 * L);
+  const size_t ncw = (size_t)(Bw + kCovIB - 1) / kCovIB * kCovIB * 6 * L;   // whole chunks
+  z.add<double>(ncw);
   z.add<double>((size_t)Bw * (nmax + (mode ? 0 : nmaps)) * nmax);
   z.add<double>((size_t)Bw * ((nmax + kNB - 1) / kNB) * kNB * kNB);
   z.add<double>((size_t)Bw * (nmax / 256) * 256 * 256);
@@ -1313,7 +1317,7 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   ScanCtx x;
   x.c = &c; x.nprob = nprob; x.nmaps = nmaps; x.lstride = lstride; x.mode = mode; x.refine = refine;
   x.cl_dev = cl_dev;
-  x.cwb = bp.take<double>((size_t)Bw * 6 * L);
+  x.cwb = bp.take<double>(ncw);
   x.Cb = bp.take<double>((size_t)Bw * (nmax + (mode ? 0 : nmaps)) * nmax);
   x.Linv = bp.take<double>((size_t)Bw * ((nmax + kNB - 1) / kNB) * kNB * kNB);
   x.Li256 = bp.take<double>((size_t)Bw * (nmax / 256) * 256 * 256);

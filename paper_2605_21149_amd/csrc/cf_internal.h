@@ -20,6 +20,7 @@ constexpr int kMaxL = 1024;          // lmax bound of the ABI
 constexpr int kNB = 64;              // diagonal block of the blocked Cholesky / triangular solves
 constexpr int kPixRec = 10;          // doubles per pixel record: n(3), e_theta(3), e_phi(2), z, phi
 constexpr int kCoef = 8;             // doubles per multipole of the recurrence table
+constexpr int kCovIB = 8;            // scan points sharing one pixel-pair recurrence in k_cov_build
 
 // Per-multipole recurrence coefficients (table [lmax+1][kCoef]):
 //   0: aP, 1: gP            P_{l+1}   = aP mu P_l - gP P_{l-1}
@@ -50,17 +51,22 @@ hipError_t launch_geometry(const int* ring_idx, int nside, const double* theta, 
 // Items (scan points) i < nitems: spectra at cl + i*cl_stride, row x at + x*cl_ld.
 // Outputs cw, lam: [nitems][6][lmax+1]; wl, coef: item 0 only (nullable).
 // i0p (nullable): device-side item offset added to every item index (captured scan batches).
+// interleave > 1: cw instead laid out [chunk][lmax+1][6][interleave] (item i in chunk
+// i / interleave, slot i % interleave), zero-filled up to a whole number of chunks.
 hipError_t launch_tables(const double* cl, const double* bl, const double* pl, int lmin, int lmax,
                          int nitems, int64_t cl_stride, int64_t cl_ld, double* cw, double* wl,
-                         double* lam, double* coef, hipStream_t s, const int64_t* i0p = nullptr);
+                         double* lam, double* coef, hipStream_t s, const int64_t* i0p = nullptr,
+                         int interleave = 1);
 
 // ---------------------------------------------------------------- covariance assembly
-// C (n x n, ld) = S + N for a batch: cw/C advance by cw_stride / c_stride per batch item.
+// C (n x n, ld) = S + N for a batch: C advances by c_stride per batch item.  interleave 1: cw
+// [item][6][lmax+1], advancing by cw_stride per item; interleave kCovIB: cw in the interleaved
+// layout of launch_tables, advancing by cw_stride per chunk of kCovIB items.
 // lower_only: write only entries on or below the diagonal.  noise_kind 0 diag [n], 1 dense [n][n].
 hipError_t launch_cov_build(const DevProblem& P, const double* cw, int64_t cw_stride, int nbatch,
                             int noise_kind, const double* noise, int noise_rank,
                             const double* noise_U, double* C, int64_t ldc, int64_t c_stride,
-                            int lower_only, int* flag, hipStream_t s);
+                            int lower_only, int* flag, hipStream_t s, int interleave = 1);
 
 // ---------------------------------------------------------------- dense FP64 kernels
 struct GemmDesc {

@@ -11,16 +11,22 @@
 //   <T_i P_j*> = -e^{-2i psi_j} (xi_TE - i xi_TB),  <P_i T_j> = -e^{2i psi_i} (xi_TE + i xi_TB),
 // with P = Q + iU.  cos 2psi, sin 2psi come from the tangent components (a, b) of the other
 // pixel's direction without trigonometry; coincident and antipodal pairs take the meridian.
-// Consecutive threads own consecutive j, so every store of the nmaps^2 outputs is coalesced.
+// Consecutive threads own consecutive j, so every store of the outputs is coalesced.
 #include "cf_internal.h"
 
 namespace cf {
 namespace {
 
-template <int FIELDS>
+// IB points of a scan share one pixel pair: the recurrences (which depend only on the pair) run
+// once and feed IB sets of sums, and the noise entry is read once for all of them.  IB == 1 reads
+// weights laid out [item][field][l] (item stride cw_stride); IB > 1 reads the interleaved layout
+// [chunk][l][field][IB] (chunk stride cw_stride), zero-padded past the last point, so that the
+// 6 * IB weights of one l are contiguous.  Every point's sums follow the same operation order as
+// with IB == 1, so results do not depend on how points are grouped.
+template <int FIELDS, int IB>
 __global__ __launch_bounds__(256) void k_cov_build(
     const double* __restrict__ pix, int npx, int n, int lmax, const double* __restrict__ coef,
-    const double* __restrict__ cw_base, int64_t cw_stride, int noise_kind,
+    const double* __restrict__ cw_base, int64_t cw_stride, int nitems, int noise_kind,
     const double* __restrict__ noise, int noise_rank, const double* __restrict__ noise_U,
     double* __restrict__ C_base, int64_t ldc, int64_t c_stride, int lower_only, int* flag) {
   constexpr bool HT = (FIELDS & 1) != 0;   // T present
@@ -28,53 +34,58 @@ __global__ __launch_bounds__(256) void k_cov_build(
   constexpr int NM = (HT ? 1 : 0) + (HP ? 2 : 0);
   const int j = blockIdx.x * 64 + (threadIdx.x & 63);
   const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
-  const int item = blockIdx.z;
+  const int item0 = blockIdx.z * IB;
   if (i >= npx || j >= npx) return;
+  const int cnt = nitems - item0 < IB ? nitems - item0 : IB;
   const int L = lmax + 1;
-  const double* cw = cw_base + (int64_t)item * cw_stride;
-  double* C = C_base + (int64_t)item * c_stride;
+  const double* cw = cw_base + (int64_t)blockIdx.z * cw_stride;
+  auto W = [&](int x, int l, int t) -> double {
+    return IB == 1 ? cw[x * L + l] : cw[((int64_t)l * 6 + x) * IB + t];
+  };
 
   const double* pi = pix + (int64_t)i * kPixRec;
   const double* pj = pix + (int64_t)j * kPixRec;
   double mu = pi[0] * pj[0] + pi[1] * pj[1] + pi[2] * pj[2];
   mu = fmin(1.0, fmax(-1.0, mu));
 
-  double xtt = 0, xp = 0, xm = 0, xeb = 0, xte = 0, xtb = 0;
+  double xtt[IB], xp[IB], xm[IB], xeb[IB], xte[IB], xtb[IB];
+#pragma unroll
+  for (int t = 0; t < IB; ++t) xtt[t] = xp[t] = xm[t] = xeb[t] = xte[t] = xtb[t] = 0.0;
   if (HT) {
-    const double* ctt = cw;                         // TT row
     double p0 = 1.0, p1 = mu;
-    xtt = ctt[0] + (lmax >= 1 ? ctt[1] * mu : 0.0);
+#pragma unroll
+    for (int t = 0; t < IB; ++t) xtt[t] = W(0, 0, t) + (lmax >= 1 ? W(0, 1, t) * mu : 0.0);
     for (int l = 1; l < lmax; ++l) {
       const double* q = coef + l * kCoef;
       double p2 = q[0] * mu * p1 - q[1] * p0;
-      xtt = fma(ctt[l + 1], p2, xtt);
+#pragma unroll
+      for (int t = 0; t < IB; ++t) xtt[t] = fma(W(0, l + 1, t), p2, xtt[t]);
       p0 = p1; p1 = p2;
     }
   }
   if (HP && lmax >= 2) {
-    const double* cee = cw + 1 * L;
-    const double* cbb = cw + 2 * L;
-    const double* cte = cw + 3 * L;
-    const double* ctb = cw + 4 * L;
-    const double* ceb = cw + 5 * L;
     double hp = 0.5 * (1.0 + mu), hm = 0.5 * (1.0 - mu);
     double a0 = 0.0, a1 = hp * hp;          // d^l_22 at l-1, l
     double b0 = 0.0, b1 = hm * hm;          // d^l_2-2
     double c0 = 0.0, c1 = 0.6123724356957945 * (1.0 - mu * mu);   // d^l_20, sqrt(6)/4
     for (int l = 2;; ++l) {
-      double sp = cee[l] + cbb[l], sm = cee[l] - cbb[l];
-      xp = fma(sp, a1, xp);
-      xm = fma(sm, b1, xm);
-      xeb = fma(ceb[l], b1, xeb);
-      if (HT) {
-        xte = fma(cte[l], c1, xte);
-        xtb = fma(ctb[l], c1, xtb);
+#pragma unroll
+      for (int t = 0; t < IB; ++t) {
+        const double ee = W(1, l, t), bb = W(2, l, t);
+        double sp = ee + bb, sm = ee - bb;
+        xp[t] = fma(sp, a1, xp[t]);
+        xm[t] = fma(sm, b1, xm[t]);
+        xeb[t] = fma(W(5, l, t), b1, xeb[t]);
+        if (HT) {
+          xte[t] = fma(W(3, l, t), c1, xte[t]);
+          xtb[t] = fma(W(4, l, t), c1, xtb[t]);
+        }
       }
       if (l == lmax) break;
       const double* q = coef + l * kCoef;
-      double t = q[2] * mu;
-      double a2 = (t - q[3]) * a1 - q[4] * a0;
-      double b2 = (t + q[3]) * b1 - q[4] * b0;
+      double tq = q[2] * mu;
+      double a2 = (tq - q[3]) * a1 - q[4] * a0;
+      double b2 = (tq + q[3]) * b1 - q[4] * b0;
       a0 = a1; a1 = a2; b0 = b1; b1 = b2;
       if (HT) {
         double c2 = q[5] * mu * c1 - q[6] * c0;
@@ -83,9 +94,8 @@ __global__ __launch_bounds__(256) void k_cov_build(
     }
   }
 
-  double out[NM][NM];
-  int k0 = 0;
-  if (HT) { out[0][0] = xtt; k0 = 1; }
+  // rotation to the pixels' local frames (depends on the pair only)
+  double rm = 0, im = 0, rp = 0, ip = 0, c2i = 0, s2i = 0, c2j = 0, s2j = 0;
   if (HP) {
     // psi_i: at pixel i toward j; psi_j: at pixel j toward i (tangent components of the other n)
     double ai = pj[0] * pi[3] + pj[1] * pi[4] + pj[2] * pi[5];
@@ -95,40 +105,50 @@ __global__ __launch_bounds__(256) void k_cov_build(
     double ri = ai * ai + bi * bi, rj = aj * aj + bj * bj;
     if (ri < 1e-12) { ai = 1.0; bi = 0.0; ri = 1.0; }
     if (rj < 1e-12) { aj = 1.0; bj = 0.0; rj = 1.0; }
-    double c2i = (ai * ai - bi * bi) / ri, s2i = 2.0 * ai * bi / ri;
-    double c2j = (aj * aj - bj * bj) / rj, s2j = 2.0 * aj * bj / rj;
-    double rm = c2i * c2j + s2i * s2j, im = s2i * c2j - c2i * s2j;   // e^{2i(psi_i - psi_j)}
-    double rp = c2i * c2j - s2i * s2j, ip = s2i * c2j + c2i * s2j;   // e^{2i(psi_i + psi_j)}
-    double ppc_r = rm * xp, ppc_i = im * xp;
-    double pp_r = rp * xm - 2.0 * ip * xeb, pp_i = ip * xm + 2.0 * rp * xeb;
-    out[k0][k0] = 0.5 * (ppc_r + pp_r);             // Q_i Q_j
-    out[k0 + 1][k0 + 1] = 0.5 * (ppc_r - pp_r);     // U_i U_j
-    out[k0][k0 + 1] = 0.5 * (pp_i - ppc_i);         // Q_i U_j
-    out[k0 + 1][k0] = 0.5 * (pp_i + ppc_i);         // U_i Q_j
-    if (HT) {
-      out[0][1] = -(c2j * xte - s2j * xtb);         // T_i Q_j
-      out[0][2] = -(c2j * xtb + s2j * xte);         // T_i U_j
-      out[1][0] = -(c2i * xte - s2i * xtb);         // Q_i T_j
-      out[2][0] = -(s2i * xte + c2i * xtb);         // U_i T_j
-    }
+    c2i = (ai * ai - bi * bi) / ri; s2i = 2.0 * ai * bi / ri;
+    c2j = (aj * aj - bj * bj) / rj; s2j = 2.0 * aj * bj / rj;
+    rm = c2i * c2j + s2i * s2j; im = s2i * c2j - c2i * s2j;   // e^{2i(psi_i - psi_j)}
+    rp = c2i * c2j - s2i * s2j; ip = s2i * c2j + c2i * s2j;   // e^{2i(psi_i + psi_j)}
   }
+  // entry (a, b) of the NM x NM pixel-pair block for point t
+  auto entry = [&](int a, int b, int t) -> double {
+    const int k0 = HT ? 1 : 0;
+    if (HT && a == 0 && b == 0) return xtt[t];
+    if (HP && a >= k0 && b >= k0) {
+      const double ppc_r = rm * xp[t], ppc_i = im * xp[t];
+      const double pp_r = rp * xm[t] - 2.0 * ip * xeb[t], pp_i = ip * xm[t] + 2.0 * rp * xeb[t];
+      if (a == k0 && b == k0) return 0.5 * (ppc_r + pp_r);           // Q_i Q_j
+      if (a == k0 + 1 && b == k0 + 1) return 0.5 * (ppc_r - pp_r);   // U_i U_j
+      if (a == k0) return 0.5 * (pp_i - ppc_i);                      // Q_i U_j
+      return 0.5 * (pp_i + ppc_i);                                   // U_i Q_j
+    }
+    if (a == 0 && b == 1) return -(c2j * xte[t] - s2j * xtb[t]);     // T_i Q_j
+    if (a == 0 && b == 2) return -(c2j * xtb[t] + s2j * xte[t]);     // T_i U_j
+    if (a == 1 && b == 0) return -(c2i * xte[t] - s2i * xtb[t]);     // Q_i T_j
+    return -(s2i * xte[t] + c2i * xtb[t]);                           // U_i T_j
+  };
 
 #pragma unroll
   for (int a = 0; a < NM; ++a) {
 #pragma unroll
     for (int b = 0; b < NM; ++b) {
-      int64_t row = (int64_t)a * npx + i;
-      int64_t col = (int64_t)b * npx + j;
+      const int64_t row = (int64_t)a * npx + i;
+      const int64_t col = (int64_t)b * npx + j;
       if (lower_only && col > row) continue;
-      double v = out[a][b];
-      if (noise_kind == 1) {
-        v += noise[row * n + col];
-      } else if (row == col) {
-        v += noise[row];
+      double nv = 0.0;
+      const bool add_n = noise_kind == 1 || row == col;
+      if (noise_kind == 1) nv = noise[row * n + col];
+      else if (row == col) nv = noise[row];
+#pragma unroll
+      for (int t = 0; t < IB; ++t) {
+        if (t >= cnt) break;
+        double v = entry(a, b, t);
+        if (add_n) v += nv;
+        for (int r = 0; r < noise_rank; ++r)
+          v = fma(noise_U[row * noise_rank + r], noise_U[col * noise_rank + r], v);
+        if (!isfinite(v)) atomicOr(flag, 1);
+        C_base[(int64_t)(item0 + t) * c_stride + row * ldc + col] = v;
       }
-      for (int r = 0; r < noise_rank; ++r) v = fma(noise_U[row * noise_rank + r], noise_U[col * noise_rank + r], v);
-      if (!isfinite(v)) atomicOr(flag, 1);
-      C[row * ldc + col] = v;
     }
   }
 }
@@ -138,18 +158,24 @@ __global__ __launch_bounds__(256) void k_cov_build(
 hipError_t launch_cov_build(const DevProblem& P, const double* cw, int64_t cw_stride, int nbatch,
                             int noise_kind, const double* noise, int noise_rank,
                             const double* noise_U, double* C, int64_t ldc, int64_t c_stride,
-                            int lower_only, int* flag, hipStream_t s) {
+                            int lower_only, int* flag, hipStream_t s, int interleave) {
   if (P.npx <= 0 || nbatch <= 0) return hipSuccess;
-  dim3 grid((P.npx + 63) / 64, (P.npx + 3) / 4, nbatch), block(256);
+  if (interleave != 1 && interleave != kCovIB) return hipErrorInvalidValue;
+  const int chunks = (nbatch + interleave - 1) / interleave;
+  dim3 grid((P.npx + 63) / 64, (P.npx + 3) / 4, chunks), block(256);
   int fields = (P.has_t ? 1 : 0) | (P.has_p ? 2 : 0);
-#define CF_COV_ARGS P.pix, P.npx, P.n, P.lmax, P.coef, cw, cw_stride, noise_kind, noise, noise_rank, \
-                    noise_U, C, ldc, c_stride, lower_only, flag
+#define CF_COV_ARGS P.pix, P.npx, P.n, P.lmax, P.coef, cw, cw_stride, nbatch, noise_kind, noise, \
+                    noise_rank, noise_U, C, ldc, c_stride, lower_only, flag
+#define CF_COV_CASE(F)                                                                          \
+  if (interleave == 1) hipLaunchKernelGGL((k_cov_build<F, 1>), grid, block, 0, s, CF_COV_ARGS); \
+  else hipLaunchKernelGGL((k_cov_build<F, kCovIB>), grid, block, 0, s, CF_COV_ARGS);
   switch (fields) {
-    case 1: hipLaunchKernelGGL(k_cov_build<1>, grid, block, 0, s, CF_COV_ARGS); break;
-    case 2: hipLaunchKernelGGL(k_cov_build<2>, grid, block, 0, s, CF_COV_ARGS); break;
-    case 3: hipLaunchKernelGGL(k_cov_build<3>, grid, block, 0, s, CF_COV_ARGS); break;
+    case 1: CF_COV_CASE(1) break;
+    case 2: CF_COV_CASE(2) break;
+    case 3: CF_COV_CASE(3) break;
     default: return hipErrorInvalidValue;
   }
+#undef CF_COV_CASE
 #undef CF_COV_ARGS
   return hipGetLastError();
 }

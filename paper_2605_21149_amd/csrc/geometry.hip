@@ -68,7 +68,7 @@ __global__ void k_geometry(const int* ring_idx, int nside, const double* theta, 
 // coefficients.  One thread per (item, l); items are scan points sharing one problem.
 __global__ void k_tables(const double* cl, const double* bl, const double* pl, int lmin, int lmax,
                          int64_t cl_stride, int64_t cl_ld, double* cw, double* wl, double* lam,
-                         double* coef, const int64_t* i0p) {
+                         double* coef, const int64_t* i0p, int nitems, int inter) {
   const int L = lmax + 1;
   int l = blockIdx.x * blockDim.x + threadIdx.x;
   int item = blockIdx.y;
@@ -78,11 +78,16 @@ __global__ void k_tables(const double* cl, const double* bl, const double* pl, i
   double w = pl ? pl[l] : 1.0;
   double W = b * b * w * w;
   double f = (2.0 * l + 1.0) / (4.0 * pi) * W;
+  const bool real = item < nitems;                   // false: zero padding of the last chunk
   const double* c = cl + (item + (i0p ? *i0p : 0)) * cl_stride;
   for (int x = 0; x < 6; ++x) {
-    double v = c[(int64_t)x * cl_ld + l];
-    if (cw) cw[(int64_t)item * 6 * L + x * L + l] = (l >= lmin) ? f * v : 0.0;
-    if (lam) lam[(int64_t)item * 6 * L + x * L + l] = (l >= lmin) ? W * v : 0.0;
+    double v = real ? c[(int64_t)x * cl_ld + l] : 0.0;
+    if (cw) {
+      const int64_t at = inter > 1 ? (((int64_t)(item / inter) * L + l) * 6 + x) * inter + item % inter
+                                   : (int64_t)item * 6 * L + x * L + l;
+      cw[at] = (l >= lmin) ? f * v : 0.0;
+    }
+    if (lam && real) lam[(int64_t)item * 6 * L + x * L + l] = (l >= lmin) ? W * v : 0.0;
   }
   if (item == 0) {
     if (wl) wl[l] = W;
@@ -122,10 +127,12 @@ hipError_t launch_geometry(const int* ring_idx, int nside, const double* theta, 
 
 hipError_t launch_tables(const double* cl, const double* bl, const double* pl, int lmin, int lmax,
                          int nitems, int64_t cl_stride, int64_t cl_ld, double* cw, double* wl,
-                         double* lam, double* coef, hipStream_t s, const int64_t* i0p) {
+                         double* lam, double* coef, hipStream_t s, const int64_t* i0p, int interleave) {
   int L = lmax + 1;
-  hipLaunchKernelGGL(k_tables, dim3((L + 127) / 128, nitems), dim3(128), 0, s, cl, bl, pl, lmin,
-                     lmax, cl_stride, cl_ld, cw, wl, lam, coef, i0p);
+  if (interleave < 1 || nitems <= 0) return hipErrorInvalidValue;
+  const int padded = (nitems + interleave - 1) / interleave * interleave;
+  hipLaunchKernelGGL(k_tables, dim3((L + 127) / 128, padded), dim3(128), 0, s, cl, bl, pl, lmin,
+                     lmax, cl_stride, cl_ld, cw, wl, lam, coef, i0p, nitems, interleave);
   return hipGetLastError();
 }
 
