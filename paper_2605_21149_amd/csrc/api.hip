@@ -624,7 +624,9 @@ int fisher_core_fp64(const cf_problem* prob, const HostProblem& H, const Staged&
     CF_DEV(gemm_f64(g, s));
     tm.close(ST_SYRK, tz, s);
   }
-  if (qb) {   // w = G^T u  (k x nm)
+  if (qb && nm <= 8) {   // w = G^T u  (k x nm): one streaming pass over the rows of G^T
+    CF_DEV(launch_rowdot(Gt, n, k, n, Dt, n, nm, qb->W, nm, split ? kT : k, p0, s));
+  } else if (qb) {
     GemmDesc w{};
     w.M = k; w.N = nm; w.K = n;
     w.A = Gt; w.lda = n; w.at = 0;
@@ -1350,10 +1352,10 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
     int b = Bt;
     int64_t i0 = 0;
     if (tuned) { x.panel = tuned_e.panel; x.tile = tuned_e.tile; }
-    // autotuning on the first call of a shape: time one batch per candidate, in three rounds
-    // (points per batch; then outer panel width; then GEMM tile), each round keeping the best
-    // rate.  Trials run the first points of the scan (best of two timings each); the scan itself
-    // then runs in full with the chosen shape, so every output comes from one configuration.
+    // autotuning on the first call of a shape: time one batch per candidate, in two rounds
+    // (points per batch; then outer panel width and GEMM tile together), keeping the best rate.
+    // Trials run the first points of the scan (best of two timings each); the scan itself then
+    // runs in full with the chosen shape, so every output comes from one configuration.
     if (ex && ex->autotune && nprob == 1 && !tuned && npoints >= 2) {
       double best_rate = 0.0;
       TuneEntry best{h.n, nmaps, mode, Bt, 0, 0};
@@ -1388,11 +1390,12 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
       };
       for (int cand : {2, 4, 8, 16})
         if (int st = trial(cand, 0, 0)) return st;
-      if (h.n > 512)
-        for (int panel : {256, 512})
-          if (int st = trial(best.bt, panel, best.tile)) return st;
-      for (int tile : {64, 128})
-        if (int st = trial(best.bt, best.panel, tile)) return st;
+      const int bt = best.bt;
+      for (int panel : {0, 256, 512}) {       // panel width and tile jointly (they interact)
+        if (panel && h.n <= 512) continue;
+        for (int tile : {64, 128})
+          if (int st = trial(bt, panel, tile)) return st;
+      }
       tune_put(best);
       b = best.bt;
       x.panel = best.panel;

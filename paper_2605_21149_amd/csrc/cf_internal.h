@@ -126,6 +126,10 @@ hipError_t trsm_lower_t_f64(const Factor& F, double* B, int64_t ldb, int64_t sB,
 
 // W[j][m] = sum_{i < K} A[i][j] U[i][m] for skinny U (nmaps <= 8): partial sums over 32 row chunks
 // in `part` ([32][M][nmaps]) reduced in a fixed order.
+// W[r][m] = A[r][:] . U[m][:] (rows of A, row-major ld lda, K columns; nmaps <= 8 rows of U, ld
+// ldu; W ld ldw).  Rows r >= rskip read only columns >= c0 (the caller guarantees zeros before).
+hipError_t launch_rowdot(const double* A, int64_t lda, int64_t M, int64_t K, const double* U, int64_t ldu,
+                         int nmaps, double* W, int64_t ldw, int64_t rskip, int64_t c0, hipStream_t s);
 hipError_t gemv_tn(const double* A, int64_t lda, int64_t M, int64_t K, const double* U, int nmaps,
                    double* W, int64_t ldw, double* part, hipStream_t s);
 

@@ -405,6 +405,40 @@ __global__ __launch_bounds__(256) void k_gemv_tn_part(const double* __restrict__
     for (int m = 0; m < NM; ++m) part[((int64_t)blockIdx.y * M + j) * NM + m] = acc[m];
   }
 }
+// W[r][m] = sum_c A[r][c] U[m][c] for rows r of A (row-major, ld lda) and NM rows of U (ld ldu):
+// one wave per row, lanes stride over the columns two at a time, a fixed-order shuffle reduction.
+// Rows r >= rskip start at column c0 (their entries before it are zero).
+template <int NM>
+__global__ __launch_bounds__(256) void k_rowdot(const double* __restrict__ A, int64_t lda, int64_t M,
+                                                int64_t K, const double* __restrict__ U, int64_t ldu,
+                                                double* __restrict__ W, int64_t ldw, int64_t rskip,
+                                                int64_t c0) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= M) return;
+  const double* a = A + r * lda;
+  double acc[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) acc[m] = 0.0;
+  int64_t c = (r >= rskip ? c0 : 0) & ~int64_t(1);
+  for (c += 2 * lane; c + 1 < K; c += 128) {
+    const double a0 = a[c], a1 = a[c + 1];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) acc[m] = fma(a1, U[m * ldu + c + 1], fma(a0, U[m * ldu + c], acc[m]));
+  }
+  if (c < K) {
+#pragma unroll
+    for (int m = 0; m < NM; ++m) acc[m] = fma(a[c], U[m * ldu + c], acc[m]);
+  }
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    double v = acc[m];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) W[r * ldw + m] = v;
+  }
+}
+
 __global__ void k_gemv_tn_reduce(const double* part, int64_t M, int nm, int nchunk, double* W, int64_t ldw) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * nm) return;
@@ -573,6 +607,19 @@ hipError_t gemv_tn(const double* A, int64_t lda, int64_t M, int64_t K, const dou
   }
   CF_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_gemv_tn_reduce, dim3(blocks(M * nmaps, 256)), dim3(256), 0, s, part, M, nmaps, NCH, W, ldw);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowdot(const double* A, int64_t lda, int64_t M, int64_t K, const double* U, int64_t ldu,
+                         int nmaps, double* W, int64_t ldw, int64_t rskip, int64_t c0, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  dim3 grid((unsigned)((M + 3) / 4));
+  switch (nmaps) {
+#define CF_RD(NMv) case NMv: hipLaunchKernelGGL(k_rowdot<NMv>, grid, dim3(256), 0, s, A, lda, M, K, U, ldu, W, ldw, rskip, c0); break;
+    CF_RD(1) CF_RD(2) CF_RD(3) CF_RD(4) CF_RD(5) CF_RD(6) CF_RD(7) CF_RD(8)
+#undef CF_RD
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
