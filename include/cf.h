@@ -144,6 +144,46 @@ int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t npoints,
                      double* logdet, const cf_exec* ex, cf_report* rep);
 
 /* ---------------------------------------------------------------------------------------------
+ * Pixel likelihood through the harmonic basis with multipole switching (Sects. 2.3.2, 2.3.4, 2.6;
+ * Eqs. C_switched, N_eff, K_kernel, smw, logdet).  The inference window is the multipole range
+ * [win_lmin, win_lmax] on the harmonic fields win_fields (OR of CF_FIELD_T, CF_FIELD_E,
+ * CF_FIELD_B, a subset of the problem's fields).  Everything outside it stays at the problem's
+ * spectra prob->cl and is absorbed into N_eff = N + fixed signal (Eq. N_eff), factored once by
+ * cf_smw_create together with the maps' solves.  Each point of cf_smw_loglike then costs one
+ * Cholesky factorisation of a k_win x k_win matrix, k_win = nfields_win * ((win_lmax+1)^2 -
+ * win_lmin^2), instead of one of the n x n pixel covariance:
+ *   C = N_eff + V_win^T Lambda_win V_win,  Lambda_win = R R^T per multipole,
+ *   -2 ln L = d^T N_eff^-1 d - |L^-1 R^T V_win N_eff^-1 d|^2 + ln|N_eff| + ln|I + R^T M R|,
+ *   L L^T = I + R^T M R,  M = V_win N_eff^-1 V_win^T,
+ * equal to the -2 ln L of cf_loglike_batch at the same spectra (n ln 2 pi excluded).
+ * Requirements: every spectrum coupling a window field to a field outside the window vanishes in
+ * prob->cl on [win_lmin, win_lmax] (else N_eff need not be positive definite: CF_EINVAL); each
+ * point's spectra restricted to the window fields are positive semi-definite at every window
+ * multipole (else CF_EINVAL).  Only those entries of a point's spectra are read.
+ * ------------------------------------------------------------------------------------------- */
+enum { CF_FIELD_T = 1, CF_FIELD_E = 2, CF_FIELD_B = 4 };
+typedef struct cf_smw cf_smw;
+
+/* Factor N_eff and solve the window's harmonic rows and the maps against it.  maps: [nmaps][n] in
+ * prob->mem space.  The handle keeps device buffers of about 8 (k_win^2 + k_win nmaps) bytes on the
+ * current device and copies of the geometry-independent data it needs; the problem and the maps
+ * may be released after the call.  On error *out is left NULL. */
+int cf_smw_create(const cf_problem* prob, int32_t win_lmin, int32_t win_lmax, uint32_t win_fields,
+                  const double* maps, int32_t nmaps, const cf_exec* ex, cf_smw** out, cf_report* rep);
+
+/* -2 ln L, chi^2 and ln|C| at npoints spectra, on the device the handle was created on.
+ *   cl_points [npoints][6][lstride] (lstride >= lmax+1 of the problem)
+ *   m2lnL [npoints][nmaps];  chi2 same shape (nullable);  logdet [npoints] (nullable)
+ * Memory space of cl_points and the outputs: the problem's mem at creation.  Calls on one handle
+ * must not overlap. */
+int cf_smw_loglike(cf_smw* h, int32_t npoints, const double* cl_points, int32_t lstride, double* m2lnL,
+                   double* chi2, double* logdet, const cf_exec* ex, cf_report* rep);
+
+/* k_win of a handle (or -1), and its release (NULL is a no-op). */
+int64_t cf_smw_dim(const cf_smw* h);
+void cf_smw_destroy(cf_smw* h);
+
+/* ---------------------------------------------------------------------------------------------
  * Likelihood emulator.  Not part of the paper's method: a surrogate of the -2 ln L of
  * cf_loglike_batch over a box of model parameters, whose uncertain or out-of-box queries are
  * sent back to the exact likelihood.

@@ -65,6 +65,7 @@ EXPORTS = ("cf_problem_dim", "cf_problem_nmodes", "cf_cov_build", "cf_fisher", "
            "cf_loglike_batch", "cf_emu_create", "cf_emu_destroy", "cf_emu_param_count", "cf_emu_shape",
            "cf_emu_train", "cf_emu_predict", "cf_emu_get_params", "cf_emu_set_params",
            "cf_emu_forward", "cf_emu_gradient", "cf_emu_adam", "cf_emu_save", "cf_emu_load",
+           "cf_smw_create", "cf_smw_loglike", "cf_smw_dim", "cf_smw_destroy",
            "cf_last_error", "cf_version")
 
 
@@ -138,10 +139,18 @@ def lib():
         L.cf_emu_adam.argtypes = [C.c_void_p, _fp, C.c_double]
         L.cf_emu_save.argtypes = [C.c_void_p, C.c_char_p]
         L.cf_emu_load.argtypes = [C.c_char_p, C.POINTER(C.c_void_p)]
+        L.cf_smw_create.argtypes = [C.POINTER(cf_problem), C.c_int32, C.c_int32, C.c_uint32, _dp, C.c_int32,
+                                    C.POINTER(cf_exec), C.POINTER(C.c_void_p), C.POINTER(cf_report)]
+        L.cf_smw_loglike.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_int32, _dp, _dp, _dp,
+                                     C.POINTER(cf_exec), C.POINTER(cf_report)]
+        L.cf_smw_dim.argtypes = [C.c_void_p]
+        L.cf_smw_dim.restype = C.c_int64
+        L.cf_smw_destroy.argtypes = [C.c_void_p]
+        L.cf_smw_destroy.restype = None
         for name in ("cf_cov_build", "cf_fisher", "cf_qml", "cf_loglike_batch", "cf_emu_create",
                      "cf_emu_train", "cf_emu_predict", "cf_emu_get_params", "cf_emu_set_params",
                      "cf_emu_forward", "cf_emu_gradient", "cf_emu_adam", "cf_emu_save",
-                     "cf_emu_load"):
+                     "cf_emu_load", "cf_smw_create", "cf_smw_loglike"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -359,6 +368,86 @@ def loglike_batch(problems: Sequence, cl_points, maps: Sequence, precision=CF_FP
 
 
 # ------------------------------------------------------------------------------ emulator
+FIELD_BITS = {"T": 1, "E": 2, "B": 4}
+
+
+class SMW:
+    """Pixel likelihood through the harmonic basis with multipole switching (cf_smw_*).
+
+    The window is the multipole range ``window = (lo, hi)`` on the harmonic fields ``fields``
+    (default: all of the problem's).  Construction factors N_eff and solves the maps and the
+    window's harmonic rows against it; ``loglike`` then evaluates -2 ln L at points whose spectra
+    differ from the problem's only inside the window, at the cost of a factorisation of the
+    window's size per point."""
+
+    def __init__(self, problem, maps, window, fields=None, device=False, packed=None):
+        pk = packed or pack_problem(problem, device)
+        if fields is None:
+            fields = {"T": "T", "QU": "EB", "TQU": "TEB"}[problem.fields]
+        bits = sum(FIELD_BITS[f] for f in set(fields))
+        if device:
+            import torch
+            m = maps if _is_torch(maps) else torch.as_tensor(np.ascontiguousarray(maps, np.float64))
+            m = torch.atleast_2d(m.to("cuda", torch.float64)).contiguous()
+        else:
+            m = np.atleast_2d(_host(maps))
+        self.device = device
+        self.nmaps = int(m.shape[0])
+        self.lmax = int(problem.lmax)
+        h = C.c_void_p()
+        rep = cf_report()
+        ex = _exec(_torch_stream() if device else None)
+        st = lib().cf_smw_create(C.byref(pk.struct), int(window[0]), int(window[1]), bits, _ptr(m),
+                                 self.nmaps, C.byref(ex), C.byref(h), C.byref(rep))
+        _check(st, rep)
+        self._h = h
+        self.setup_report = rep.as_dict()
+
+    @property
+    def dim(self) -> int:
+        return int(lib().cf_smw_dim(self._h))
+
+    def loglike(self, cl_points, stage_timing=False, report=False):
+        """-2 ln L [npoints][nmaps], chi^2 (same) and ln|C| [npoints]; cl_points [npoints][6][lstride]."""
+        if not self._h:
+            raise CFError(CF_EINVAL, "handle closed", None)
+        if self.device:
+            import torch
+            clp = cl_points if _is_torch(cl_points) else torch.as_tensor(np.ascontiguousarray(cl_points, np.float64))
+            clp = clp.to("cuda", torch.float64).contiguous()
+        else:
+            clp = _host(cl_points)
+        npoints, lstride = int(clp.shape[0]), int(clp.shape[-1])
+        assert clp.shape[1] == 6
+        m2 = _alloc((npoints, self.nmaps), self.device)
+        x2 = _alloc((npoints, self.nmaps), self.device)
+        ld = _alloc((npoints,), self.device)
+        rep = cf_report()
+        ex = _exec(_torch_stream() if self.device else None, stage_timing)
+        st = lib().cf_smw_loglike(self._h, npoints, _ptr(clp), lstride, _ptr(m2), _ptr(x2), _ptr(ld),
+                                  C.byref(ex), C.byref(rep))
+        _check(st, rep)
+        out = {"m2lnL": m2, "chi2": x2, "logdet": ld}
+        return (out, rep.as_dict()) if report else out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cf_smw_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Emulator:
     """Handle of a cf_emu ensemble (see include/cf.h); every method is one library call."""
 

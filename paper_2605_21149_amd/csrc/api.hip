@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -1431,3 +1432,296 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   if (rep) { rep->flops = flops; rep->n = H[0].n; rep->ir_iters = mode ? refine : 0; rep->n_fallback = Bt; }
   return CF_OK;
 }
+
+// ------------------------------------------------------------------------------- SMW likelihood
+// Handle of the harmonic-basis likelihood: what every point needs, kept on the device it was
+// made on.  M = V_win N_eff^-1 V_win^T [kw][kw] (full), b = V_win N_eff^-1 D [kw][nmaps],
+// chi2N[j] = d_j^T N_eff^-1 d_j, ldN = ln|N_eff|, wl = W_l.
+struct cf_smw {
+  int device = -1;
+  int mem = 0;
+  int n = 0, lmax = 0, wlo = 0, whi = 0, nf = 0, nmaps = 0;
+  int fld[3] = {0, 0, 0};          // harmonic field (T 0, E 1, B 2) of each window slot
+  int64_t kwf = 0, kw = 0;
+  double *M = nullptr, *b = nullptr, *chi2N = nullptr, *ldN = nullptr, *wl = nullptr;
+};
+
+namespace cf {
+namespace {
+
+int spec_row(int a, int b) {   // spectrum row (TT, EE, BB, TE, TB, EB) of a harmonic-field pair
+  if (a > b) std::swap(a, b);
+  if (a == b) return a;
+  if (a == 0) return b == 1 ? 3 : 4;
+  return 5;
+}
+
+void smw_free(cf_smw* h) {
+  if (!h) return;
+  int cur = 0;
+  const bool have = hipGetDevice(&cur) == hipSuccess;
+  const bool sw = have && h->device >= 0 && cur != h->device;
+  if (sw) (void)hipSetDevice(h->device);
+  (void)hipFree(h->M);
+  (void)hipFree(h->b);
+  (void)hipFree(h->chi2N);
+  (void)hipFree(h->ldN);
+  (void)hipFree(h->wl);
+  if (sw) (void)hipSetDevice(cur);
+  delete h;
+}
+
+// N_eff (Eq. N_eff: the problem's spectra without the window's varied entries) factored with
+// the maps and the window's harmonic rows below it, so that the rows come out as
+// (L^-1 D)^T and (L^-1 V_win^T)^T; then M, b, chi2N and ln|N_eff| from those rows.
+int smw_setup(const cf_problem* prob, const HostProblem& H, cf_smw* h, const int* pslot,
+              const std::vector<double>& clf, const double* maps, CallCtx& c, Timer& tm) {
+  const int64_t n = H.n, k = H.k, kw = h->kw, kwf = h->kwf;
+  const int nm = h->nmaps, L = H.lmax + 1;
+  const int64_t rows = n + nm + kw, nblk = (n + kNB - 1) / kNB;
+  Sizer z;
+  size_staging(z, prob, H);
+  z.add<double>((size_t)rows * n);
+  z.add<double>((size_t)n * k);
+  z.add<double>((size_t)nblk * kNB * kNB);
+  z.add<double>((size_t)potrf_scratch(1));
+  z.add<double>((size_t)nblk);
+  z.add<double>((size_t)nm * n);
+  z.add<int>(8);
+  if (int st = ensure_ws(*c.dev, z.off)) return st;
+  Bump bp(c.dev->ws);
+  Staged S;
+  if (int st = stage(bp, prob, H, clf.data(), c.s, S)) return st;
+  double* C = bp.take<double>((size_t)rows * n);
+  double* Y = bp.take<double>((size_t)n * k);
+  double* Linv = bp.take<double>((size_t)nblk * kNB * kNB);
+  double* scr = bp.take<double>((size_t)potrf_scratch(1));
+  double* ldp = bp.take<double>((size_t)nblk);
+  double* mcopy = bp.take<double>((size_t)nm * n);
+  int* flags = bp.take<int>(8);
+  const double* mdev = maps;
+  if (prob->mem == CF_MEM_HOST) {
+    CF_DEV(hipMemcpyAsync(mcopy, maps, sizeof(double) * nm * n, hipMemcpyHostToDevice, c.s));
+    mdev = mcopy;
+  }
+  CF_DEV(launch_fill_int(flags, 1, 0, c.s));
+  CF_DEV(launch_fill_int(flags + 1, 1, INT_MAX, c.s));
+  CF_DEV(launch_ybuild(S.P, Y, k, c.s));
+  tm.mark(ST_YBUILD);
+  CF_DEV(launch_cov_build(S.P, S.cw, 0, 1, prob->noise_kind, S.noise, prob->noise_rank, S.noise_U, C, n, 0, 1,
+                          flags, c.s));
+  CF_DEV(hipMemcpyAsync(C + n * n, mdev, sizeof(double) * nm * n, hipMemcpyDeviceToDevice, c.s));
+  double* Vt = C + (n + nm) * n;
+  const int64_t c0 = (int64_t)h->wlo * h->wlo - (int64_t)H.lmin * H.lmin;   // window's first column in a field
+  for (int q = 0; q < h->nf; ++q)
+    CF_DEV(launch_transpose(Y + (int64_t)pslot[h->fld[q]] * H.kf + c0, n, kwf, k, Vt + q * kwf * n, n, c.s));
+  CF_DEV(hipMemcpyAsync(h->wl, S.wl, sizeof(double) * L, hipMemcpyDeviceToDevice, c.s));
+  tm.mark(ST_BUILD);
+  Factor F;
+  F.L = C; F.n = n; F.ld = n; F.sL = 0;
+  F.Li64 = Linv; F.sLi64 = 0;
+  F.ldpart = ldp; F.sPart = 0;
+  F.fail = flags + 1; F.batch = 1; F.mode = 0;
+  F.rows = rows;
+  // E,B rows vanish on the T pixels: with T first they stay out of the panels before the Q pixels
+  const int64_t kwT = h->fld[0] == 0 ? kwf : 0;
+  if (H.has_t && H.has_p && kw > kwT) { F.rows_early = n + nm + kwT; F.p_early = H.npx; }
+  if (int st = potrf_on(*c.dev, F, scr, c.s, c.dev->aux[1], c.dev->ev + 8)) return st;
+  tm.mark(ST_POTRF);
+  GemmDesc g{};
+  g.M = kw; g.N = kw; g.K = n;
+  g.A = Vt; g.lda = n; g.at = 0;
+  g.B = Vt; g.ldb = n; g.bt = 1;
+  g.C = h->M; g.ldc = kw; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1;
+  CF_DEV(gemm_f64(g, c.s));
+  CF_DEV(launch_symmetrize(h->M, kw, kw, c.s));
+  GemmDesc w{};
+  w.M = kw; w.N = nm; w.K = n;
+  w.A = Vt; w.lda = n; w.at = 0;
+  w.B = C + n * n; w.ldb = n; w.bt = 1;
+  w.C = h->b; w.ldc = nm; w.alpha = 1.0; w.beta = 0.0; w.batch = 1;
+  CF_DEV(gemm_f64(w, c.s));
+  CF_DEV(launch_rowsumsq(C + n * n, nm, n, n, 0, 1, h->chi2N, nm, c.s));
+  CF_DEV(launch_sum_parts(ldp, (int)nblk, nblk, 1, h->ldN, 1, c.s));
+  tm.mark(ST_SYRK);
+  int fl[2];
+  if (int st = read_flags(c, flags, 2, fl)) return st;
+  if (fl[0]) return fail(CF_EINVAL, "non-finite entry of N_eff (check noise and spectra)");
+  if (fl[1] != INT_MAX) return fail(CF_ENOTPD, "N_eff not positive definite (pivot %d)", fl[1]);
+  return CF_OK;
+}
+
+}  // namespace
+}  // namespace cf
+
+extern "C" int cf_smw_create(const cf_problem* prob, int32_t win_lmin, int32_t win_lmax, uint32_t win_fields,
+                             const double* maps, int32_t nmaps, const cf_exec* ex, cf_smw** out,
+                             cf_report* rep) {
+  report_init(rep);
+  if (!out) return fail(CF_EINVAL, "out is NULL");
+  *out = nullptr;
+  HostProblem H;
+  if (int st = check_problem(prob, H, true)) return st;
+  if (win_lmin < H.lmin || win_lmax > H.lmax || win_lmin > win_lmax)
+    return fail(CF_EINVAL, "window [%d, %d] outside [lmin, lmax] = [%d, %d]", win_lmin, win_lmax, H.lmin, H.lmax);
+  if (win_fields == 0 || (win_fields & ~7u)) return fail(CF_EINVAL, "window fields 0x%x invalid", win_fields);
+  const bool present[3] = {H.has_t != 0, H.has_p != 0, H.has_p != 0};
+  int pslot[3] = {-1, -1, -1}, np = 0;
+  for (int f = 0; f < 3; ++f)
+    if (present[f]) pslot[f] = np++;
+  std::unique_ptr<cf_smw, void (*)(cf_smw*)> tmp(new cf_smw, smw_free);   // frees on every error path
+  for (int f = 0; f < 3; ++f) {
+    if (!(win_fields & (1u << f))) continue;
+    if (!present[f]) return fail(CF_EINVAL, "window field %d absent from the problem", f);
+    tmp->fld[tmp->nf++] = f;
+  }
+  const int L = H.lmax + 1;
+  for (int a = 0; a < 3; ++a)
+    for (int b = a; b < 3; ++b) {
+      if (!present[a] || !present[b]) continue;
+      if (((win_fields >> a) & 1u) == ((win_fields >> b) & 1u)) continue;
+      const double* row = prob->cl + (int64_t)spec_row(a, b) * L;
+      for (int l = win_lmin; l <= win_lmax; ++l)
+        if (row[l] != 0.0)
+          return fail(CF_EINVAL, "spectrum row %d couples a window field to a fixed field at l=%d", spec_row(a, b), l);
+    }
+  if (nmaps <= 0 || !maps) return fail(CF_EINVAL, "no maps");
+  if (prob->mem == CF_MEM_HOST && !finite_all(maps, (int64_t)nmaps * H.n)) return fail(CF_EINVAL, "non-finite map value");
+  std::vector<double> clf(prob->cl, prob->cl + 6 * L);
+  for (int a = 0; a < 3; ++a)
+    for (int b = a; b < 3; ++b)
+      if (((win_fields >> a) & 1u) && ((win_fields >> b) & 1u))
+        for (int l = win_lmin; l <= win_lmax; ++l) clf[(size_t)spec_row(a, b) * L + l] = 0.0;
+  cf_smw* h = tmp.get();
+  h->mem = prob->mem; h->n = H.n; h->lmax = H.lmax; h->wlo = win_lmin; h->whi = win_lmax; h->nmaps = nmaps;
+  h->kwf = (int64_t)(win_lmax + 1) * (win_lmax + 1) - (int64_t)win_lmin * win_lmin;
+  h->kw = h->kwf * h->nf;
+  if (h->kw > 32768) return fail(CF_EINVAL, "window of %lld modes too large", (long long)h->kw);
+  CallCtx c;
+  if (int st = c.begin(ex)) return st;
+  CF_DEV(hipGetDevice(&h->device));
+  const size_t kw = (size_t)h->kw;
+  if (hipMalloc(&h->M, sizeof(double) * kw * kw) != hipSuccess ||
+      hipMalloc(&h->b, sizeof(double) * kw * nmaps) != hipSuccess ||
+      hipMalloc(&h->chi2N, sizeof(double) * nmaps) != hipSuccess ||
+      hipMalloc(&h->ldN, sizeof(double)) != hipSuccess || hipMalloc(&h->wl, sizeof(double) * L) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(CF_ENOMEM, "device allocation of the SMW handle failed");
+  }
+  Timer tm;
+  tm.begin(ex && ex->stage_timing, c.s);
+  if (int st = smw_setup(prob, H, h, pslot, clf, maps, c, tm)) return st;
+  CF_DEV(hipStreamSynchronize(c.s));
+  tm.finish(rep);
+  if (rep) {
+    const double nd = H.n, kd = (double)kw;
+    rep->n = H.n; rep->nmodes = h->kw;
+    rep->flops = nd * nd * nd / 3.0 + nd * nd * (kd + nmaps) + nd * kd * (kd + nmaps);
+  }
+  *out = tmp.release();
+  return CF_OK;
+}
+
+extern "C" int cf_smw_loglike(cf_smw* h, int32_t npoints, const double* cl_points, int32_t lstride,
+                              double* m2lnL, double* chi2, double* logdet, const cf_exec* ex, cf_report* rep) {
+  report_init(rep);
+  if (!h) return fail(CF_EINVAL, "handle is NULL");
+  if (npoints <= 0 || !cl_points) return fail(CF_EINVAL, "no scan points");
+  if (!m2lnL) return fail(CF_EINVAL, "m2lnL is NULL");
+  if (lstride < h->lmax + 1) return fail(CF_EINVAL, "lstride %d < lmax + 1 = %d", lstride, h->lmax + 1);
+  int dev = 0;
+  CF_DEV(hipGetDevice(&dev));
+  if (dev != h->device) return fail(CF_EINVAL, "handle made on device %d, current device %d", h->device, dev);
+  const size_t ncl = (size_t)npoints * 6 * lstride;
+  if (h->mem == CF_MEM_HOST && !finite_all(cl_points, (int64_t)ncl)) return fail(CF_EINVAL, "non-finite scan spectra");
+  CallCtx c;
+  if (int st = c.begin(ex)) return st;
+  const int64_t kw = h->kw, kwf = h->kwf;
+  const int nm = h->nmaps, nl = h->whi - h->wlo + 1, nf = h->nf;
+  const int64_t slot = (kw + nm) * kw, nblk = (kw + kNB - 1) / kNB;
+  const int bt_cap = (int)std::min<int64_t>(16, std::max<int64_t>(1, (int64_t(6) << 30) / (slot * 8)));
+  const int Bt = std::min<int>(bt_cap, npoints);
+  Sizer z;
+  if (h->mem == CF_MEM_HOST) {
+    z.add<double>(ncl);
+    z.add<double>((size_t)npoints * nm * 2 + (size_t)npoints);
+  }
+  z.add<double>((size_t)Bt * nl * 9);
+  z.add<double>((size_t)Bt * slot);
+  z.add<double>((size_t)Bt * nblk * kNB * kNB);
+  z.add<double>((size_t)potrf_scratch(Bt));
+  z.add<double>((size_t)Bt * nblk);
+  z.add<double>((size_t)Bt * nm);
+  z.add<double>((size_t)Bt);
+  z.add<int>(8);
+  if (int st = ensure_ws(*c.dev, z.off)) return st;
+  Bump bp(c.dev->ws);
+  const double* cl_dev = cl_points;
+  double *m2_dev = m2lnL, *chi2_dev = chi2, *ld_dev = logdet;
+  if (h->mem == CF_MEM_HOST) {
+    double* t = bp.take<double>(ncl);
+    CF_DEV(hipMemcpyAsync(t, cl_points, sizeof(double) * ncl, hipMemcpyHostToDevice, c.s));
+    cl_dev = t;
+    double* o = bp.take<double>((size_t)npoints * nm * 2 + (size_t)npoints);
+    m2_dev = o;
+    chi2_dev = chi2 ? o + (size_t)npoints * nm : nullptr;
+    ld_dev = logdet ? o + (size_t)npoints * nm * 2 : nullptr;
+  }
+  double* R = bp.take<double>((size_t)Bt * nl * 9);
+  double* K = bp.take<double>((size_t)Bt * slot);
+  double* Linv = bp.take<double>((size_t)Bt * nblk * kNB * kNB);
+  double* pscr = bp.take<double>((size_t)potrf_scratch(Bt));
+  double* ldp = bp.take<double>((size_t)Bt * nblk);
+  double* x2 = bp.take<double>((size_t)Bt * nm);
+  double* ldK = bp.take<double>((size_t)Bt);
+  int* flags = bp.take<int>(8);
+  CF_DEV(launch_fill_int(flags, 1, 0, c.s));
+  CF_DEV(launch_fill_int(flags + 1, 2, INT_MAX, c.s));
+  Timer tm;
+  tm.begin(ex && ex->stage_timing, c.s);
+  for (int64_t i0 = 0; i0 < npoints; i0 += Bt) {
+    const int bb = (int)std::min<int64_t>(Bt, npoints - i0);
+    CF_DEV(launch_smw_lambda(cl_dev + i0 * 6 * lstride, 6 * (int64_t)lstride, lstride, h->wl, h->wlo, nl, nf,
+                             h->fld, bb, R, flags + 2, c.s));
+    CF_DEV(launch_smw_kernel(h->M, kw, kwf, nf, h->wlo, nl, R, bb, K, slot, c.s));
+    CF_DEV(launch_smw_rhs(h->b, nm, kw, kwf, nf, h->wlo, nl, R, bb, K, slot, c.s));
+    tm.mark(ST_BUILD);
+    Factor F;
+    F.L = K; F.n = kw; F.ld = kw; F.sL = slot;
+    F.Li64 = Linv; F.sLi64 = nblk * kNB * kNB;
+    F.ldpart = ldp; F.sPart = nblk;
+    F.fail = flags + 1; F.batch = bb; F.mode = 0;
+    F.rows = kw + nm;
+    if (int st = potrf_on(*c.dev, F, pscr, c.s, c.dev->aux[1], c.dev->ev + 8)) return st;
+    tm.mark(ST_POTRF);
+    CF_DEV(launch_rowsumsq(K + kw * kw, nm, kw, kw, slot, bb, x2, nm, c.s));
+    CF_DEV(launch_sum_parts(ldp, (int)nblk, nblk, bb, ldK, 1, c.s));
+    CF_DEV(launch_smw_finish(h->chi2N, h->ldN, x2, ldK, bb, nm, i0, m2_dev, chi2_dev, ld_dev, c.s));
+    tm.mark(ST_TRSM);
+  }
+  int fl[3];
+  if (int st = read_flags(c, flags, 3, fl)) return st;
+  if (fl[2] != INT_MAX)
+    return fail(CF_EINVAL, "a point's window spectra are not positive semi-definite at l=%d", fl[2]);
+  if (fl[1] != INT_MAX) {
+    if (rep) rep->fail_index = fl[1];
+    return fail(CF_ENOTPD, "I + R^T M R not positive definite (pivot %d)", fl[1]);
+  }
+  if (h->mem == CF_MEM_HOST) {
+    if (int st = copy_out(m2lnL, m2_dev, (size_t)npoints * nm, CF_MEM_HOST, c.s)) return st;
+    if (chi2) if (int st = copy_out(chi2, chi2_dev, (size_t)npoints * nm, CF_MEM_HOST, c.s)) return st;
+    if (logdet) if (int st = copy_out(logdet, ld_dev, (size_t)npoints, CF_MEM_HOST, c.s)) return st;
+  }
+  CF_DEV(hipStreamSynchronize(c.s));
+  tm.finish(rep);
+  if (rep) {
+    const double kd = (double)kw;
+    rep->n = h->n; rep->nmodes = kw; rep->n_fallback = Bt;
+    rep->flops = (double)npoints * (kd * kd * kd / 3.0 + kd * kd * nm + 2.0 * kwf * kwf * nf * nf * nf);
+  }
+  return CF_OK;
+}
+
+extern "C" int64_t cf_smw_dim(const cf_smw* h) { return h ? h->kw : -1; }
+
+extern "C" void cf_smw_destroy(cf_smw* h) { smw_free(h); }

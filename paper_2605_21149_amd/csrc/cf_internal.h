@@ -182,6 +182,20 @@ hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s);
 
+// ---------------------------------------------------------------- harmonic-basis likelihood
+// Per-point pieces of the SMW likelihood with multipole switching (smw.hip).  Window modes are
+// [field slot][l][m] over nf varied fields (fld: harmonic fields T 0, E 1, B 2), kwf per field.
+// R: [batch][nl][3][3] lower factors of Lambda_l; K: per point a slot of [kw + nmaps][kw].
+hipError_t launch_smw_lambda(const double* cl, int64_t cl_stride, int64_t cl_ld, const double* wl, int wlo,
+                             int nl, int nf, const int* fld, int batch, double* R, int* bad, hipStream_t s);
+hipError_t launch_smw_kernel(const double* M, int64_t kw, int64_t kwf, int nf, int wlo, int nl,
+                             const double* R, int batch, double* K, int64_t slot, hipStream_t s);
+hipError_t launch_smw_rhs(const double* b, int nmaps, int64_t kw, int64_t kwf, int nf, int wlo, int nl,
+                          const double* R, int batch, double* K, int64_t slot, hipStream_t s);
+hipError_t launch_smw_finish(const double* chi2N, const double* ldN, const double* x2b, const double* ldK,
+                             int B, int nmaps, int64_t i0, double* m2, double* chi2, double* logdet,
+                             hipStream_t s);
+
 // ---------------------------------------------------------------- likelihood emulator
 // Error text for cf_last_error() from code outside the API translation unit.
 int set_error(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));

@@ -1,0 +1,147 @@
+"""GPU parity of the harmonic-basis likelihood with multipole switching (cf_smw_*): against the
+oracle's SMW likelihood on small problems (every window mode, a ragged last batch), and at the
+full sizes of the scan workloads against the direct likelihood (the pixel-space scan of
+cf_loglike_batch, itself checked against the oracle, and the oracle's direct likelihood at a
+sampled point)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+from oracle import likelihood, smw  # noqa: E402
+from paper_2605_21149_amd import inputs as I  # noqa: E402
+from gpu_common import say, to_np  # noqa: E402
+from oracle_cases import random_spectra, tiny_healpix  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    from paper_2605_21149_amd import cf
+    cf.lib()
+    assert torch.cuda.is_available(), "GPU tests selected but torch sees no GPU"
+
+
+def _cf():
+    from paper_2605_21149_amd import cf
+    return cf
+
+
+def _points(p, seeds):
+    """Point spectra: random positive-definite spectra (the window's entries are what matter)."""
+    return np.stack([random_spectra(p.lmax, s) for s in seeds])
+
+
+def _against_oracle(p, maps, pts, wlo, whi, wf, device):
+    cf = _cf()
+    with cf.SMW(p, maps, (wlo, whi), wf, device=device) as h:
+        out = h.loglike(pts)
+    got = {k: to_np(v) for k, v in out.items()}
+    for i, cl in enumerate(pts):
+        m2, chi2, ld = smw.smw_minus2lnL(p, maps, cl, wlo, whi, wf)
+        np.testing.assert_allclose(got["m2lnL"][i], m2, rtol=1e-9)
+        np.testing.assert_allclose(got["chi2"][i], chi2, rtol=1e-9)
+        np.testing.assert_allclose(got["logdet"][i], ld, rtol=1e-9, atol=1e-9)
+    return got
+
+
+def test_smw_tqu_all_fields_matches_oracle_ragged_batch():
+    say("smw: tiny TQU, window [2, 4] TEB, 20 points (batches of 16 and 4), device arrays")
+    p = tiny_healpix("TQU", nside=2, lmax=6, cut=0.3, lowrank=2)
+    maps = np.random.default_rng(71).standard_normal((3, p.n))
+    _against_oracle(p, maps, _points(p, range(100, 120)), 2, 4, "TEB", device=True)
+
+
+def test_smw_qu_e_window_matches_oracle_host_arrays():
+    say("smw: tiny QU, window [2, 5] E (EB = 0), 3 points, host arrays")
+    p = tiny_healpix("QU", nside=2, lmax=6, cut=0.25)
+    p.cl = p.cl.copy()
+    p.cl[5] = 0.0
+    maps = np.random.default_rng(73).standard_normal((2, p.n))
+    pts = _points(p, (201, 202, 203))
+    _against_oracle(p, maps, pts, 2, 5, "E", device=False)
+
+
+def test_smw_full_window_equals_direct_gpu_likelihood():
+    say("smw: tiny QU, full window [lmin, lmax] EB (N_eff = N) vs cf_loglike_batch")
+    cf = _cf()
+    p = tiny_healpix("QU", nside=2, lmax=5, cut=0.25, lowrank=2)
+    maps = np.random.default_rng(72).standard_normal((2, p.n))
+    pts = _points(p, (301, 302))
+    with cf.SMW(p, maps, (p.lmin, p.lmax), "EB") as h:
+        got = to_np(h.loglike(pts)["m2lnL"])
+    ref = to_np(cf.loglike_batch([p], pts[:, None], [maps])["m2lnL"])[:, 0, :]
+    np.testing.assert_allclose(got, ref, rtol=1e-9)
+
+
+def test_smw_rejects_coupled_window_and_indefinite_points():
+    cf = _cf()
+    p = tiny_healpix("TQU", nside=2, lmax=5, cut=0.3)
+    maps = np.random.default_rng(74).standard_normal((1, p.n))
+    with pytest.raises(cf.CFError) as e:
+        cf.SMW(p, maps, (2, 3), "E")                       # TE couples T and E in the window
+    assert e.value.status == cf.CF_EINVAL
+    with cf.SMW(p, maps, (2, 3), "TEB") as h:
+        bad = _points(p, (401,))
+        bad[0, 3, 3] = 5.0 * np.sqrt(bad[0, 0, 3] * bad[0, 1, 3])   # |TE| > sqrt(TT EE) at l = 3
+        with pytest.raises(cf.CFError) as e2:
+            h.loglike(bad)
+        assert e2.value.status == cf.CF_EINVAL
+
+
+@pytest.mark.timeout(900)
+def test_smw_qu_nside16_scan_full_size():
+    """The QU N_side 16 scan problem (n = 3968) with the EE window l = 2..29 (896 modes), 64 maps:
+    against the direct GPU scan on 8 points and the oracle's direct likelihood at one point."""
+    cf = _cf()
+    import torch
+    say("smw: QU N_side 16, window [2, 29] E, 64 maps, 8 points")
+    p = I.qu_scan_problem(16)
+    maps = I.white_maps(p.n, 64, 403, rms=3.0)
+    pts = I.scan_spectra(I.scan_points(8, seed=401), p.cl)
+    d_maps = torch.as_tensor(maps).cuda()
+    d_pts = torch.as_tensor(np.ascontiguousarray(pts)).cuda()
+    with cf.SMW(p, d_maps, (2, 29), "E", device=True) as h:
+        assert h.dim == 896
+        got = {k: to_np(v) for k, v in h.loglike(d_pts).items()}
+    ref = cf.loglike_batch([p], d_pts[:, None].contiguous(), [d_maps], device=True)
+    ref = {k: to_np(v) for k, v in ref.items()}
+    d = np.abs(got["m2lnL"] - ref["m2lnL"][:, 0, :]).max()
+    say(f"  max |d(-2lnL)| vs direct GPU scan: {d:.3e}")
+    assert d <= 1e-3
+    assert np.abs(got["logdet"] - ref["logdet"][:, 0]).max() <= 1e-3
+    m2o, _, ldo = likelihood.minus2lnL(p, maps[:4], cl=pts[3])
+    say(f"  max |d(-2lnL)| vs oracle direct at point 3: {np.abs(got['m2lnL'][3, :4] - m2o).max():.3e}")
+    np.testing.assert_allclose(got["m2lnL"][3, :4], m2o, rtol=0, atol=1e-3)
+    np.testing.assert_allclose(got["logdet"][3], ldo, rtol=0, atol=1e-3)
+
+
+@pytest.mark.timeout(900)
+def test_smw_tqu_nside16_all_fields_full_size():
+    """The TQU N_side 16 problem of the bench (n = 5952), window l = 2..29 on T, E, B (2688 modes,
+    TE coupling T and E), 64 maps: against the direct GPU scan on 4 points."""
+    cf = _cf()
+    import torch
+    say("smw: TQU N_side 16, window [2, 29] TEB, 64 maps, 4 points")
+    p = I.tqu_problem_nside16(dense_noise=True)
+    maps = I.white_maps(p.n, 64, 403, rms=3.0)
+    pts = I.scan_spectra(I.scan_points(4, seed=401), p.cl)
+    d_maps = torch.as_tensor(maps).cuda()
+    d_pts = torch.as_tensor(np.ascontiguousarray(pts)).cuda()
+    pk = cf.pack_problem(p, device=True)
+    with cf.SMW(p, d_maps, (2, 29), "TEB", device=True, packed=pk) as h:
+        assert h.dim == 2688
+        got = {k: to_np(v) for k, v in h.loglike(d_pts).items()}
+    ref = cf.loglike_batch([p], d_pts[:, None].contiguous(), [d_maps], device=True, packed=[pk])
+    ref = {k: to_np(v) for k, v in ref.items()}
+    d = np.abs(got["m2lnL"] - ref["m2lnL"][:, 0, :]).max()
+    say(f"  max |d(-2lnL)| vs direct GPU scan: {d:.3e}")
+    assert d <= 1e-3
+    assert np.abs(got["logdet"] - ref["logdet"][:, 0]).max() <= 1e-3
