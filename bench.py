@@ -32,6 +32,8 @@ def parse():
                     help="only run one device-to-device copy of MIB MiB (HBM counter calibration)")
     ap.add_argument("--tune-cache", default="", metavar="PATH",
                     help="autotuning table to use (default: a fresh one, tuned during warmup)")
+    ap.add_argument("--no-smw", action="store_true",
+                    help="skip the harmonic-basis (SMW, multipole switching) likelihood measurement")
     ap.add_argument("--emulator", action="store_true",
                     help="also train and measure the likelihood emulator on the QU N_side 16 scan problem")
     ap.add_argument("--emu-train", type=int, default=200000, help="exact training points")
@@ -184,6 +186,46 @@ def cpu_baseline(problem, bins, cl_points, maps_qml, maps_scan):
                        f"extrapolated step {step:.1f} s (host BLAS threads {threads})")}
 
 
+def smw_section(cf, I, problem, packed, d_maps_scan, direct_m2, direct_pts_per_s, npoints=64, reps=3):
+    """Harmonic-basis likelihood with multipole switching (cf_smw_*): the EE window l = 2..29 of the
+    scan model, on all fields of the TQU problem (TE couples T and E) and on E alone for the QU
+    N_side 16 scan problem.  Setup = N_eff factorisation with the maps' and the window's solves;
+    the scan rate counts every point's K' build, factorisation and log det.  Accuracy: the largest
+    |d(-2 ln L)| against the direct pixel-space scan at the step's points."""
+    import torch
+    out = {}
+    cases = [("tqu_nside16", problem, packed, d_maps_scan, "TEB"),
+             ("qu_nside16", I.qu_scan_problem(16), None, None, "E")]
+    for name, p, pk, d_maps, wf in cases:
+        pk = pk or cf.pack_problem(p, device=True)
+        if d_maps is None:
+            d_maps = torch.as_tensor(I.white_maps(p.n, NMAPS_SCAN, 403, rms=3.0)).cuda()
+        pts = torch.as_tensor(np.ascontiguousarray(I.scan_spectra(I.scan_points(npoints, seed=401), p.cl))).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = cf.SMW(p, d_maps, (2, 29), wf, device=True, packed=pk)
+        torch.cuda.synchronize()
+        setup_ms = 1e3 * (time.perf_counter() - t0)
+        h.loglike(pts[:SCAN_POINTS])
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = h.loglike(pts)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        rec = {"window": f"l 2-29, fields {wf}", "k_win": h.dim, "n": p.n, "setup_ms": setup_ms,
+               "points": npoints, "scan_ms": 1e3 * min(ts), "points_per_s": npoints / min(ts),
+               "map_evals_per_s": npoints * NMAPS_SCAN / min(ts)}
+        if name == "tqu_nside16":
+            got = res["m2lnL"][:SCAN_POINTS].cpu().numpy()
+            rec["max_abs_dm2lnL_vs_direct"] = float(np.abs(got - direct_m2).max())
+            rec["direct_points_per_s"] = direct_pts_per_s
+        h.close()
+        out[name] = rec
+    return out
+
+
 def mixed_precision(cf, I, problem, bins, packed, d_maps_qml, d_cl, d_maps_scan, reps=3):
     """Fisher+QML and likelihood-batch times for FP64, FP32-MFMA and split-BF16x3 paths, with the
     errors of the mixed results against the FP64 path (F: relative Frobenius; y, b: in units of
@@ -294,6 +336,12 @@ def main():
                                              packed=[packed])[1]["ms_stage"])
     mixed = None if args.no_mixed else mixed_precision(cf, I, problem, bins, packed, d_maps_qml, d_cl,
                                                           d_maps_scan)
+    smw = None
+    if not args.no_smw:
+        direct_m2 = cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True, packed=[packed],
+                                     autotune=True)["m2lnL"][:, 0, :].cpu().numpy()
+        smw = smw_section(cf, I, problem, packed, d_maps_scan, direct_m2,
+                          SCAN_POINTS / (np.median(scan_ms) * 1e-3))
     # roofline kernel: the largest single launch of the step, the FP64 MFMA symmetric product
     # forming the E,B x E,B block of Z = G^T G (k_gemm<128,128,false,true,1>), timed with HIP
     # events on the stream it runs on.  Algorithmic flops: the lower triangle with the diagonal
@@ -326,6 +374,7 @@ def main():
         "stages_fisher_qml_ms": dict(zip(cf.STAGES, [round(float(x), 4) for x in stage])),
         "stages_loglike_ms": dict(zip(cf.STAGES, [round(float(x), 4) for x in scan_stage])),
         "mixed_precision": mixed,
+        "smw": smw,
         "roofline": {"bound": "mfma", "kernel": "k_gemm<128,128,false,true,1> FP64 (Z_EB,EB = G_EB^T G_EB)",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic},

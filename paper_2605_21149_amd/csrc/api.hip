@@ -1639,7 +1639,9 @@ extern "C" int cf_smw_loglike(cf_smw* h, int32_t npoints, const double* cl_point
   const int64_t kw = h->kw, kwf = h->kwf;
   const int nm = h->nmaps, nl = h->whi - h->wlo + 1, nf = h->nf;
   const int64_t slot = (kw + nm) * kw, nblk = (kw + kNB - 1) / kNB;
-  const int bt_cap = (int)std::min<int64_t>(16, std::max<int64_t>(1, (int64_t(6) << 30) / (slot * 8)));
+  // points per batch: up to 128 within 6 GB (each batch pays the chain of the window's diagonal
+  //   blocks once; measured at 896 modes: 14.7k points/s at 16 per batch, 40.9k at 128)
+  const int bt_cap = (int)std::min<int64_t>(128, std::max<int64_t>(1, (int64_t(6) << 30) / (slot * 8)));
   const int Bt = std::min<int>(bt_cap, npoints);
   Sizer z;
   if (h->mem == CF_MEM_HOST) {
