@@ -34,6 +34,8 @@ def parse():
                     help="autotuning table to use (default: a fresh one, tuned during warmup)")
     ap.add_argument("--no-smw", action="store_true",
                     help="skip the harmonic-basis (SMW, multipole switching) likelihood measurement")
+    ap.add_argument("--smw-only", action="store_true",
+                    help="only run the SMW likelihood measurement and print its JSON")
     ap.add_argument("--emulator", action="store_true",
                     help="also train and measure the likelihood emulator on the QU N_side 16 scan problem")
     ap.add_argument("--emu-train", type=int, default=200000, help="exact training points")
@@ -214,9 +216,12 @@ def smw_section(cf, I, problem, packed, d_maps_scan, direct_m2, direct_pts_per_s
             res = h.loglike(pts)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
-        rec = {"window": f"l 2-29, fields {wf}", "k_win": h.dim, "n": p.n, "setup_ms": setup_ms,
+        k = h.dim
+        flops = k ** 3 / 3.0 + k * k * NMAPS_SCAN     # per point: factorisation of [K'; b'^T]
+        rec = {"window": f"l 2-29, fields {wf}", "k_win": k, "n": p.n, "setup_ms": setup_ms,
                "points": npoints, "scan_ms": 1e3 * min(ts), "points_per_s": npoints / min(ts),
-               "map_evals_per_s": npoints * NMAPS_SCAN / min(ts)}
+               "map_evals_per_s": npoints * NMAPS_SCAN / min(ts),
+               "achieved_tflops": npoints * flops / min(ts) / 1e12}
         if name == "tqu_nside16":
             got = res["m2lnL"][:SCAN_POINTS].cpu().numpy()
             rec["max_abs_dm2lnL_vs_direct"] = float(np.abs(got - direct_m2).max())
@@ -298,6 +303,11 @@ def main():
     d_maps_scan = torch.as_tensor(maps_scan).to(dev)
     d_cl = torch.as_tensor(np.ascontiguousarray(cl_points)).to(dev)
     torch.cuda.synchronize()
+    if args.smw_only:
+        direct = cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True, packed=[packed])
+        print(json.dumps({"smw": smw_section(cf, I, problem, packed, d_maps_scan,
+                                             direct["m2lnL"][:, 0, :].cpu().numpy(), None)}), flush=True)
+        return
 
     def step(timing):
         q, rq = cf.qml(problem, bins, d_maps_qml, device=True, stage_timing=timing, report=True,

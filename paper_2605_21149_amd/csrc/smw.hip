@@ -81,8 +81,8 @@ __global__ void k_smw_lambda(const double* __restrict__ cl, int64_t cl_stride, i
 }
 
 // K' = I + R^T M R for every point: one thread per (r_i, r_j) reads the nf x nf field block of M
-// at those positions once and writes K' for all field pairs.  M: [kw][kw] (ld kw), K': slot of
-// [kw + nmaps][kw] per point (the first kw rows).
+// at those positions once and writes the lower-triangle entries of K' for all field pairs.
+// M: [kw][kw] (ld kw), K': slot of [kw + nmaps][kw] per point (the first kw rows).
 __global__ __launch_bounds__(256) void k_smw_kernel(const double* __restrict__ M, int64_t kw, int64_t kwf,
                                                     int nf, int wlo, int nl, const double* __restrict__ R,
                                                     double* __restrict__ K, int64_t slot) {
@@ -105,7 +105,8 @@ __global__ __launch_bounds__(256) void k_smw_kernel(const double* __restrict__ M
         v = fma(Ri[c * 3 + fi], s, v);
       }
       if (fi == fj && ri == rj) v += 1.0;
-      Kp[(fi * kwf + ri) * kw + fj * kwf + rj] = v;
+      const int64_t row = fi * kwf + ri, col = fj * kwf + rj;
+      if (col <= row) Kp[row * kw + col] = v;   // the factorisation reads the lower triangle only
     }
 }
 
