@@ -172,6 +172,21 @@ def deconvolve(F, q):
     return sla.cho_solve(fac, np.atleast_2d(q).T).T
 
 
+def inverse_sqrt(F, cutoff=1e-12):
+    """F^-1/2 = U Xi^-1/2 U^T from the eigendecomposition F = U Xi U^T, with eigenvalues below
+    cutoff times the largest set to zero (Eq. decorrelated and the regularisation beside it)."""
+    xi, U = np.linalg.eigh(np.asarray(F, dtype=np.float64))
+    keep = xi > cutoff * xi.max()
+    w = np.zeros_like(xi)
+    w[keep] = 1.0 / np.sqrt(xi[keep])
+    return (U * w[None, :]) @ U.T
+
+
+def decorrelate(F, q, cutoff=1e-12):
+    """C_hat^decorr = F^-1/2 q for each row of q (Eq. decorrelated)."""
+    return (inverse_sqrt(F, cutoff) @ np.atleast_2d(q).T).T
+
+
 def bin_matrix(lmin, lmax, lo, hi):
     """P_Sigma [n_b][n_l]: 1 where l lies in bin b (binning identity of the validation section)."""
     nl = lmax - lmin + 1
