@@ -143,6 +143,16 @@ int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t npoints,
                      int32_t nmaps, int32_t precision, double* m2lnL, double* chi2,
                      double* logdet, const cf_exec* ex, cf_report* rep);
 
+/* Decorrelated normalisation (Sect. 2.5, Eq. decorrelated): out[v] = F^-1/2 q[v] with
+ * F^-1/2 = U Xi^-1/2 U^T from the eigendecomposition F = U Xi U^T (cyclic Jacobi in FP64), the
+ * eigenvalues below 1e-12 of the largest set to zero.  F: [K][K], only its lower triangle is read;
+ * q, out: [nvec][K] (nvec = 0 with q = out = NULL computes only Fmhalf_out); Fmhalf_out: [K][K]
+ * F^-1/2 (nullable; with it the caller can carry theory spectra through the same window F^1/2).
+ * 1 <= K <= 1024.  All arrays in memory space mem.  CF_ENOCONV if the Jacobi sweeps do not reach
+ * 1e-15 relative off-diagonal norm within 60 sweeps; cf_report.ir_iters = sweeps run. */
+int cf_decorrelate(const double* F, int32_t K, const double* q, int32_t nvec, int32_t mem, double* out,
+                   double* Fmhalf_out, const cf_exec* ex, cf_report* rep);
+
 /* ---------------------------------------------------------------------------------------------
  * Pixel likelihood through the harmonic basis with multipole switching (Sects. 2.3.2, 2.3.4, 2.6;
  * Eqs. C_switched, N_eff, K_kernel, smw, logdet).  The inference window is the multipole range

@@ -65,7 +65,7 @@ EXPORTS = ("cf_problem_dim", "cf_problem_nmodes", "cf_cov_build", "cf_fisher", "
            "cf_loglike_batch", "cf_emu_create", "cf_emu_destroy", "cf_emu_param_count", "cf_emu_shape",
            "cf_emu_train", "cf_emu_predict", "cf_emu_get_params", "cf_emu_set_params",
            "cf_emu_forward", "cf_emu_gradient", "cf_emu_adam", "cf_emu_save", "cf_emu_load",
-           "cf_smw_create", "cf_smw_loglike", "cf_smw_dim", "cf_smw_destroy",
+           "cf_smw_create", "cf_smw_loglike", "cf_smw_dim", "cf_smw_destroy", "cf_decorrelate",
            "cf_last_error", "cf_version")
 
 
@@ -143,6 +143,8 @@ def lib():
                                     C.POINTER(cf_exec), C.POINTER(C.c_void_p), C.POINTER(cf_report)]
         L.cf_smw_loglike.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_int32, _dp, _dp, _dp,
                                      C.POINTER(cf_exec), C.POINTER(cf_report)]
+        L.cf_decorrelate.argtypes = [_dp, C.c_int32, _dp, C.c_int32, C.c_int32, _dp, _dp,
+                                     C.POINTER(cf_exec), C.POINTER(cf_report)]
         L.cf_smw_dim.argtypes = [C.c_void_p]
         L.cf_smw_dim.restype = C.c_int64
         L.cf_smw_destroy.argtypes = [C.c_void_p]
@@ -150,7 +152,7 @@ def lib():
         for name in ("cf_cov_build", "cf_fisher", "cf_qml", "cf_loglike_batch", "cf_emu_create",
                      "cf_emu_train", "cf_emu_predict", "cf_emu_get_params", "cf_emu_set_params",
                      "cf_emu_forward", "cf_emu_gradient", "cf_emu_adam", "cf_emu_save",
-                     "cf_emu_load", "cf_smw_create", "cf_smw_loglike"):
+                     "cf_emu_load", "cf_smw_create", "cf_smw_loglike", "cf_decorrelate"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -368,6 +370,28 @@ def loglike_batch(problems: Sequence, cl_points, maps: Sequence, precision=CF_FP
 
 
 # ------------------------------------------------------------------------------ emulator
+def decorrelate(F, q=None, device=False, report=False):
+    """Decorrelated estimates F^-1/2 q (Eq. decorrelated) for each row of q, and F^-1/2 itself.
+    Returns (out [nvec][K] or None, Fmhalf [K][K])."""
+    if device:
+        import torch
+        Fd = (F if _is_torch(F) else torch.as_tensor(np.ascontiguousarray(F, np.float64))).to("cuda", torch.float64).contiguous()
+        qd = None if q is None else torch.atleast_2d((q if _is_torch(q) else torch.as_tensor(np.ascontiguousarray(q, np.float64))).to("cuda", torch.float64)).contiguous()
+    else:
+        Fd = _host(F)
+        qd = None if q is None else np.atleast_2d(_host(q))
+    K = int(Fd.shape[0])
+    nvec = 0 if qd is None else int(qd.shape[0])
+    out = _alloc((nvec, K), device) if nvec else None
+    R = _alloc((K, K), device)
+    rep = cf_report()
+    ex = _exec(_torch_stream() if device else None)
+    st = lib().cf_decorrelate(_ptr(Fd), K, _ptr(qd), nvec, CF_MEM_DEVICE if device else CF_MEM_HOST,
+                              _ptr(out), _ptr(R), C.byref(ex), C.byref(rep))
+    _check(st, rep)
+    return ((out, R), rep.as_dict()) if report else (out, R)
+
+
 FIELD_BITS = {"T": 1, "E": 2, "B": 4}
 
 

@@ -1727,3 +1727,66 @@ extern "C" int cf_smw_loglike(cf_smw* h, int32_t npoints, const double* cl_point
 extern "C" int64_t cf_smw_dim(const cf_smw* h) { return h ? h->kw : -1; }
 
 extern "C" void cf_smw_destroy(cf_smw* h) { smw_free(h); }
+
+extern "C" int cf_decorrelate(const double* F, int32_t K, const double* q, int32_t nvec, int32_t mem,
+                              double* out, double* Fmhalf_out, const cf_exec* ex, cf_report* rep) {
+  report_init(rep);
+  if (!F || K < 1 || K > 1024) return fail(CF_EINVAL, "K=%d outside [1, 1024] or F NULL", K);
+  if (nvec < 0 || (nvec > 0 && (!q || !out))) return fail(CF_EINVAL, "nvec=%d with q=%p out=%p", nvec,
+                                                          (const void*)q, (void*)out);
+  if (nvec == 0 && !Fmhalf_out) return fail(CF_EINVAL, "nothing to compute");
+  if (mem != CF_MEM_HOST && mem != CF_MEM_DEVICE) return fail(CF_EINVAL, "unknown mem %d", mem);
+  const int64_t kk = (int64_t)K * K;
+  if (mem == CF_MEM_HOST) {
+    if (!finite_all(F, kk)) return fail(CF_EINVAL, "non-finite F");
+    if (nvec > 0 && !finite_all(q, (int64_t)K * nvec)) return fail(CF_EINVAL, "non-finite q");
+  }
+  CallCtx c;
+  if (int st = c.begin(ex)) return st;
+  Sizer z;
+  if (mem == CF_MEM_HOST) {
+    z.add<double>(kk);
+    z.add<double>((size_t)K * nvec);
+    z.add<double>((size_t)K * nvec);
+  }
+  z.add<double>(kk);
+  z.add<double>(kk);
+  z.add<double>(kk);
+  z.add<double>(K);
+  z.add<int>(8);
+  if (int st = ensure_ws(*c.dev, z.off)) return st;
+  Bump bp(c.dev->ws);
+  const double* Fd = F;
+  const double* qd = q;
+  double* od = out;
+  if (mem == CF_MEM_HOST) {
+    double* t = bp.take<double>(kk);
+    CF_DEV(hipMemcpyAsync(t, F, sizeof(double) * kk, hipMemcpyHostToDevice, c.s));
+    Fd = t;
+    double* tq = bp.take<double>((size_t)K * nvec);
+    if (nvec > 0) CF_DEV(hipMemcpyAsync(tq, q, sizeof(double) * K * nvec, hipMemcpyHostToDevice, c.s));
+    qd = tq;
+    od = bp.take<double>((size_t)K * nvec);
+  }
+  double* A = bp.take<double>(kk);
+  double* U = bp.take<double>(kk);
+  double* R = bp.take<double>(kk);
+  double* w = bp.take<double>(K);
+  int* info = bp.take<int>(8);
+  Timer tm;
+  tm.begin(ex && ex->stage_timing, c.s);
+  CF_DEV(launch_inverse_sqrt(Fd, K, A, U, w, R, 60, 1e-12, info, c.s));
+  if (nvec > 0) CF_DEV(launch_apply_rows(R, qd, K, nvec, od, c.s));
+  tm.mark(ST_QML);
+  int fl[2];
+  if (int st = read_flags(c, info, 2, fl)) return st;
+  if (rep) rep->ir_iters = fl[0];
+  if (fl[1]) return fail(CF_ENOCONV, "Jacobi sweeps did not converge in %d sweeps", fl[0]);
+  if (nvec > 0 && mem == CF_MEM_HOST)
+    if (int st = copy_out(out, od, (size_t)K * nvec, CF_MEM_HOST, c.s)) return st;
+  if (Fmhalf_out)
+    if (int st = copy_out(Fmhalf_out, R, (size_t)kk, mem, c.s)) return st;
+  CF_DEV(hipStreamSynchronize(c.s));
+  tm.finish(rep);
+  return CF_OK;
+}

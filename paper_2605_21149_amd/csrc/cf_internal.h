@@ -182,6 +182,14 @@ hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t s);
 
+// ---------------------------------------------------------------- decorrelated normalisation
+// R = F^-1/2 (lower triangle of F [K][K] read, K <= 1024) by one-workgroup cyclic Jacobi: A, U, R
+// [K][K] and w [K] scratch/outputs (U eigenvectors, w the cut Xi^-1/2); info[2]: sweeps, not
+// converged.  out[v] = R q[v] for nvec rows q [nvec][K].
+hipError_t launch_inverse_sqrt(const double* F, int K, double* A, double* U, double* w, double* R,
+                               int max_sweeps, double cutoff, int* info, hipStream_t s);
+hipError_t launch_apply_rows(const double* R, const double* q, int K, int nvec, double* out, hipStream_t s);
+
 // ---------------------------------------------------------------- harmonic-basis likelihood
 // Per-point pieces of the SMW likelihood with multipole switching (smw.hip).  Window modes are
 // [field slot][l][m] over nf varied fields (fld: harmonic fields T 0, E 1, B 2), kwf per field.
