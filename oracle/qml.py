@@ -90,6 +90,32 @@ def bias_dense(problem, spectra, lo, hi, C=None):
     return out
 
 
+def cross_dense(problem1, problem2, spectra, lo, hi, maps1, maps2):
+    """Cross-QML of two data sets filtered independently (Eq. q_cross):
+      q_A = 1/2 d1^T C1^-1 P_A C2^-1 d2     (per map pair j: maps1[j], maps2[j])
+      W_AB = 1/2 tr[C1^-1 P_A C2^-1 P_B]    (the mode-mixing matrix beside Eq. q_cross)
+      C_hat = W^-1 q                        (deconvolved as in Eq. qml_estimate; no noise bias)
+    The two problems share geometry, spectra, beam and window (so P_A and S are common) and differ
+    in their noise.  Returns (q [nmaps][k], W [k][k], C_hat [nmaps][k])."""
+    f1 = sla.cho_factor(cv.total_covariance(problem1), lower=True)
+    f2 = sla.cho_factor(cv.total_covariance(problem2), lower=True)
+    x1 = sla.cho_solve(f1, np.atleast_2d(maps1).T)          # C1^-1 d1
+    x2 = sla.cho_solve(f2, np.atleast_2d(maps2).T)          # C2^-1 d2
+    pars = parameters(spectra, lo, hi)
+    P = [derivative_dense(problem1, *p) for p in pars]
+    A1 = [sla.cho_solve(f1, Pa) for Pa in P]                # C1^-1 P_A
+    A2 = [sla.cho_solve(f2, Pa) for Pa in P]                # C2^-1 P_A
+    k = len(pars)
+    q = np.zeros((x1.shape[1], k))
+    W = np.zeros((k, k))
+    for a in range(k):
+        q[:, a] = 0.5 * np.sum(x1 * (P[a] @ x2), axis=0)
+        for b in range(k):
+            W[a, b] = 0.5 * np.sum(A1[a] * A2[b].T)         # tr[C1^-1 P_a C2^-1 P_b]
+    chat = np.linalg.solve(W, q.T).T
+    return q, W, chat
+
+
 # ---------------------------------------------------------------------------
 # harmonic (Z) route
 # ---------------------------------------------------------------------------
