@@ -130,6 +130,17 @@ int cf_qml(const cf_problem* prob, const cf_bins* bins, const double* maps, int3
            int32_t precision, double* y_out, double* bias_out, double* chat_out, double* F_out,
            const cf_exec* ex, cf_report* rep);
 
+/* Cross-QML of two data sets filtered independently (Eq. q_cross, Sect. 2.2 "Cross-correlation"):
+ *   q_out    [nmaps][ns*nb]  q^x_b = 1/2 d1^T C1^-1 P_b C2^-1 d2 for the map pairs (maps1[j], maps2[j])
+ *   chat_out [nmaps][ns*nb]  W^-1 q^x (no noise-bias term: the two noises are independent)
+ *   W_out    [(ns*nb)^2]     mode-mixing matrix W_bb' = 1/2 tr[C1^-1 P_b C2^-1 P_b'] (nullable)
+ * prob1 and prob2 describe the two data sets: C_a = S + N_a with the same geometry, fields,
+ * l-range, spectra, beam, pixel window and memory space (else CF_EINVAL); they differ in their
+ * noise.  maps1, maps2: [nmaps][n].  FP64. */
+int cf_qml_cross(const cf_problem* prob1, const cf_problem* prob2, const cf_bins* bins, const double* maps1,
+                 const double* maps2, int32_t nmaps, double* q_out, double* chat_out, double* W_out,
+                 const cf_exec* ex, cf_report* rep);
+
 /* Pixel likelihood over a parameter scan (Eq. pixel_likelihood, Sect. 2.6):
  *   -2 ln L_{i,p,j} = d_{p,j}^T C_{i,p}^-1 d_{p,j} + ln|C_{i,p}|  (n ln 2 pi excluded)
  * for points i < npoints, problems p < nprob and maps j < nmaps.

@@ -65,7 +65,7 @@ EXPORTS = ("cf_problem_dim", "cf_problem_nmodes", "cf_cov_build", "cf_fisher", "
            "cf_loglike_batch", "cf_emu_create", "cf_emu_destroy", "cf_emu_param_count", "cf_emu_shape",
            "cf_emu_train", "cf_emu_predict", "cf_emu_get_params", "cf_emu_set_params",
            "cf_emu_forward", "cf_emu_gradient", "cf_emu_adam", "cf_emu_save", "cf_emu_load",
-           "cf_smw_create", "cf_smw_loglike", "cf_smw_dim", "cf_smw_destroy", "cf_decorrelate",
+           "cf_smw_create", "cf_smw_loglike", "cf_smw_dim", "cf_smw_destroy", "cf_decorrelate", "cf_qml_cross",
            "cf_last_error", "cf_version")
 
 
@@ -143,6 +143,8 @@ def lib():
                                     C.POINTER(cf_exec), C.POINTER(C.c_void_p), C.POINTER(cf_report)]
         L.cf_smw_loglike.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_int32, _dp, _dp, _dp,
                                      C.POINTER(cf_exec), C.POINTER(cf_report)]
+        L.cf_qml_cross.argtypes = [C.POINTER(cf_problem), C.POINTER(cf_problem), C.POINTER(cf_bins), _dp, _dp,
+                                   C.c_int32, _dp, _dp, _dp, C.POINTER(cf_exec), C.POINTER(cf_report)]
         L.cf_decorrelate.argtypes = [_dp, C.c_int32, _dp, C.c_int32, C.c_int32, _dp, _dp,
                                      C.POINTER(cf_exec), C.POINTER(cf_report)]
         L.cf_smw_dim.argtypes = [C.c_void_p]
@@ -152,7 +154,7 @@ def lib():
         for name in ("cf_cov_build", "cf_fisher", "cf_qml", "cf_loglike_batch", "cf_emu_create",
                      "cf_emu_train", "cf_emu_predict", "cf_emu_get_params", "cf_emu_set_params",
                      "cf_emu_forward", "cf_emu_gradient", "cf_emu_adam", "cf_emu_save",
-                     "cf_emu_load", "cf_smw_create", "cf_smw_loglike", "cf_decorrelate"):
+                     "cf_emu_load", "cf_smw_create", "cf_smw_loglike", "cf_decorrelate", "cf_qml_cross"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -335,6 +337,32 @@ def qml(p, bins, maps, precision=CF_FP64, device=False, stage_timing=False, repo
                       _ptr(b), _ptr(ch), _ptr(F), C.byref(ex), C.byref(rep))
     _check(st, rep)
     out = {"y": y, "bias": b, "chat": ch, "F": F}
+    return (out, rep.as_dict()) if report else out
+
+
+def qml_cross(p1, p2, bins, maps1, maps2, device=False, stage_timing=False, report=False,
+              packed=None):
+    """Cross-QML of two data sets (same model, different noise): dict(q, chat, W)."""
+    pk1, pk2 = packed or (pack_problem(p1, device), pack_problem(p2, device))
+    bs, keep = pack_bins(bins)
+    K = len(bins.spectra) * bs.nbins
+
+    def _maps(m):
+        if device:
+            import torch
+            t = m if _is_torch(m) else torch.as_tensor(np.ascontiguousarray(m, np.float64))
+            return torch.atleast_2d(t.to("cuda", torch.float64)).contiguous()
+        return np.atleast_2d(_host(m))
+    m1, m2 = _maps(maps1), _maps(maps2)
+    nmaps = int(m1.shape[0])
+    assert m2.shape[0] == nmaps
+    q, ch, W = _alloc((nmaps, K), device), _alloc((nmaps, K), device), _alloc((K, K), device)
+    rep = cf_report()
+    ex = _exec(_torch_stream() if device else None, stage_timing)
+    st = lib().cf_qml_cross(C.byref(pk1.struct), C.byref(pk2.struct), C.byref(bs), _ptr(m1), _ptr(m2), nmaps,
+                            _ptr(q), _ptr(ch), _ptr(W), C.byref(ex), C.byref(rep))
+    _check(st, rep)
+    out = {"q": q, "chat": ch, "W": W}
     return (out, rep.as_dict()) if report else out
 
 

@@ -1790,3 +1790,122 @@ extern "C" int cf_decorrelate(const double* F, int32_t K, const double* q, int32
   tm.finish(rep);
   return CF_OK;
 }
+
+namespace cf {
+namespace {
+// The two data sets of a cross-QML share everything but the noise: geometry, fields, l-range,
+// spectra, beam and window (so that S and every P_b are common), and the memory space.
+int check_same_model(const cf_problem* a, const cf_problem* b, const HostProblem& Ha, const HostProblem& Hb) {
+  const int L = Ha.lmax + 1;
+  auto same = [](const double* x, const double* y, int64_t n) {
+    if (!x || !y) return x == y;
+    return std::memcmp(x, y, sizeof(double) * n) == 0;
+  };
+  if (a->nside != b->nside || a->fields != b->fields || Ha.lmin != Hb.lmin || Ha.lmax != Hb.lmax ||
+      Ha.n != Hb.n || a->mem != b->mem)
+    return fail(CF_EINVAL, "cross-QML data sets differ in geometry, fields, l-range or memory space");
+  if (a->nside > 0) {
+    if (Ha.ring != Hb.ring) return fail(CF_EINVAL, "cross-QML data sets differ in their masks");
+  } else if (!same(a->theta, b->theta, Ha.npx) || !same(a->phi, b->phi, Ha.npx)) {
+    return fail(CF_EINVAL, "cross-QML data sets differ in their directions");
+  }
+  if (!same(a->cl, b->cl, 6LL * L) || !same(a->bl, b->bl, L) || !same(a->pl, b->pl, L))
+    return fail(CF_EINVAL, "cross-QML data sets differ in spectra, beam or pixel window");
+  return CF_OK;
+}
+}  // namespace
+}  // namespace cf
+
+extern "C" int cf_qml_cross(const cf_problem* prob1, const cf_problem* prob2, const cf_bins* bins,
+                            const double* maps1, const double* maps2, int32_t nmaps, double* q_out,
+                            double* chat_out, double* W_out, const cf_exec* ex, cf_report* rep) {
+  report_init(rep);
+  HostProblem H1, H2;
+  if (int st = check_problem(prob1, H1, true)) return st;
+  if (int st = check_problem(prob2, H2, true)) return st;
+  if (int st = check_same_model(prob1, prob2, H1, H2)) return st;
+  HostBins B;
+  if (int st = check_bins(bins, H1, B)) return st;
+  if (nmaps <= 0 || !maps1 || !maps2) return fail(CF_EINVAL, "no maps");
+  if (!q_out || !chat_out) return fail(CF_EINVAL, "q_out and chat_out are required");
+  if (prob1->mem == CF_MEM_HOST && (!finite_all(maps1, (int64_t)nmaps * H1.n) || !finite_all(maps2, (int64_t)nmaps * H1.n)))
+    return fail(CF_EINVAL, "non-finite map value");
+  CallCtx c;
+  if (int st = c.begin(ex)) return st;
+  const int K = B.ns * B.nb;
+  const int nl = H1.lmax - H1.lmin + 1, np = H1.nfm * H1.nfm;
+  const cf_problem* probs[2] = {prob1, prob2};
+  const double* maps[2] = {maps1, maps2};
+  Sizer z;
+  for (int a = 0; a < 2; ++a) {
+    size_staging(z, probs[a], H1);
+    fisher_ws(H1, B, z, 0, nmaps);
+    z.add<double>((size_t)nmaps * H1.n);        // maps copy (host inputs)
+    z.add<double>((size_t)H1.n * nmaps);        // D
+    z.add<double>((size_t)H1.n * nmaps);        // U
+    z.add<double>((size_t)H1.k * nmaps);        // w
+    z.add<double>((size_t)32 * H1.k * nmaps);   // partial sums
+  }
+  z.add<double>((size_t)nl * (nl + 1) / 2 * np * np);   // cross Gram
+  z.add<double>((size_t)K * K);                         // W
+  z.add<double>((size_t)K * K);                         // W copy for the solve
+  z.add<double>((size_t)nmaps * K);                     // q
+  z.add<double>((size_t)nmaps * K);                     // chat
+  if (int st = ensure_ws(*c.dev, z.off)) return st;
+  Bump bp(c.dev->ws);
+  Staged S[2];
+  FisherBufs f[2];
+  QmlBufs qb[2];
+  Timer tm;
+  tm.begin(ex && ex->stage_timing, c.s);
+  for (int a = 0; a < 2; ++a) {
+    if (int st = stage(bp, probs[a], H1, nullptr, c.s, S[a])) return st;
+    fisher_take(bp, H1, B, f[a], 0, nmaps);
+    double* mcopy = bp.take<double>((size_t)nmaps * H1.n);
+    qb[a].D = bp.take<double>((size_t)H1.n * nmaps);
+    qb[a].U = bp.take<double>((size_t)H1.n * nmaps);
+    qb[a].W = bp.take<double>((size_t)H1.k * nmaps);
+    qb[a].part = bp.take<double>((size_t)32 * H1.k * nmaps);
+    qb[a].nmaps = nmaps;
+    qb[a].maps = maps[a];
+    if (prob1->mem == CF_MEM_HOST) {
+      CF_DEV(hipMemcpyAsync(mcopy, maps[a], sizeof(double) * nmaps * H1.n, hipMemcpyHostToDevice, c.s));
+      qb[a].maps = mcopy;
+    }
+    CF_DEV(hipMemcpyAsync(f[a].lo, B.lo.data(), sizeof(int) * B.nb, hipMemcpyHostToDevice, c.s));
+    CF_DEV(hipMemcpyAsync(f[a].hi, B.hi.data(), sizeof(int) * B.nb, hipMemcpyHostToDevice, c.s));
+    if (int st = fisher_core(probs[a], H1, S[a], f[a], &qb[a], c, tm, 0)) return st;
+  }
+  double* gx = bp.take<double>((size_t)nl * (nl + 1) / 2 * np * np);
+  double* W = bp.take<double>((size_t)K * K);
+  double* Ww = bp.take<double>((size_t)K * K);
+  double* q = bp.take<double>((size_t)nmaps * K);
+  double* chat = bp.take<double>((size_t)nmaps * K);
+  // W^x_AB = 1/2 tr[C1^-1 P_A C2^-1 P_B] from <Z2, Z1> block products; q^x = 1/2 w1^T E_A w2
+  CF_DEV(launch_gram_cross(S[0].P, f[0].Z, f[1].Z, H1.k, gx, c.s));
+  const SpecSel sel = make_sel(B, f[0]);
+  CF_DEV(launch_fisher_assemble(S[0].P, sel, gx, W, c.s, true));
+  tm.mark(ST_REDUCE);
+  CF_DEV(launch_quad_assemble(S[0].P, sel, qb[0].W, nmaps, nmaps, q, c.s, qb[1].W));
+  CF_DEV(hipMemcpyAsync(Ww, W, sizeof(double) * K * K, hipMemcpyDeviceToDevice, c.s));
+  CF_DEV(launch_small_spd_solve(Ww, K, q, chat, nmaps, f[0].flags + 2, c.s));
+  tm.mark(ST_QML);
+  for (int a = 0; a < 2; ++a)
+    if (int st = check_factor_flags(c, f[a], rep)) return st;
+  {
+    int fl3[3];
+    if (int st = read_flags(c, f[0].flags, 3, fl3)) return st;
+    if (fl3[2] != INT_MAX) {
+      if (rep) rep->fail_index = fl3[2];
+      return fail(CF_ENOTPD, "mode-mixing matrix not positive definite at pivot %d", fl3[2]);
+    }
+  }
+  if (int st = copy_out(q_out, q, (size_t)nmaps * K, prob1->mem, c.s)) return st;
+  if (int st = copy_out(chat_out, chat, (size_t)nmaps * K, prob1->mem, c.s)) return st;
+  if (W_out)
+    if (int st = copy_out(W_out, W, (size_t)K * K, prob1->mem, c.s)) return st;
+  CF_DEV(hipStreamSynchronize(c.s));
+  tm.finish(rep);
+  if (rep) { rep->n = H1.n; rep->nmodes = H1.k; rep->flops = 2.0 * fisher_flops(H1); }
+  return CF_OK;
+}

@@ -143,6 +143,9 @@ hipError_t launch_symmetrize(double* Z, int64_t k, int64_t ldz, hipStream_t s);
 // Gram[l][l'][p][q] for l >= l' (p, q over the nfm^2 field pairs, upper-triangular q >= p).
 hipError_t launch_gram(const DevProblem& P, const double* Z, int64_t ldz, double* gram,
                        double* ztr, hipStream_t s);
+// Cross Gram of Z1 and Z2 (cross-QML): per l >= l', the nfm^4 values <Z2^{p1}, Z1^{p2}>.
+hipError_t launch_gram_cross(const DevProblem& P, const double* Z1, const double* Z2, int64_t ldz, double* gx,
+                             hipStream_t s);
 struct SpecSel {
   int ns;            // selected spectra
   int spec[6];       // spectrum ids (0..5 TT,EE,BB,TE,TB,EB)
@@ -151,11 +154,13 @@ struct SpecSel {
   const int* hi;     // device [nb]
 };
 hipError_t launch_fisher_assemble(const DevProblem& P, const SpecSel& S, const double* gram,
-                                  double* F, hipStream_t s);
+                                  double* F, hipStream_t s,
+                                  bool cross = false);
 hipError_t launch_bias_assemble(const DevProblem& P, const SpecSel& S, const double* gram,
                                 const double* ztr, double* bias, hipStream_t s);
 hipError_t launch_quad_assemble(const DevProblem& P, const SpecSel& S, const double* w, int64_t ldw,
-                                int nmaps, double* y, hipStream_t s);
+                                int nmaps, double* y, hipStream_t s,
+                                const double* w2 = nullptr);
 // Cholesky solve of the small SPD system F X = R (k x k, nrhs columns given as rows [nrhs][k]).
 hipError_t launch_small_spd_solve(double* F, int k, const double* R, double* X, int nrhs, int* fail,
                                   hipStream_t s);

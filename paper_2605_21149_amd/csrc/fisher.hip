@@ -110,6 +110,56 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ Z, int6
   }
 }
 
+// Cross Gram of two projected inverses (cross-QML): for every l >= l' and every pair of field
+// pairs, gx[(p1, p2)] = <Z2^{p1}_{l l'}, Z1^{p2}_{l l'}>_F with p = a * NF + d (no symmetry in
+// (p1, p2), so all NP^2 are kept).  Per-thread partial sums, then a fixed-order wave and
+// workgroup reduction.
+template <int NF>
+__global__ __launch_bounds__(256) void k_gram_cross(const double* __restrict__ Z1, const double* __restrict__ Z2,
+                                                    int64_t ldz, int lmin, int kf, double* __restrict__ gx) {
+  constexpr int NP = NF * NF, NQ = NP * NP;
+  __shared__ double red[4][NQ];
+  const int pid = blockIdx.x;
+  int li = (int)((sqrt(8.0 * pid + 1.0) - 1.0) * 0.5);
+  while (li * (li + 1) / 2 > pid) --li;
+  while ((li + 1) * (li + 2) / 2 <= pid) ++li;
+  const int lj = pid - li * (li + 1) / 2;
+  const int l = lmin + li, lp = lmin + lj;
+  const int nm = 2 * l + 1, nmp = 2 * lp + 1;
+  const int64_t rb = (int64_t)l * l - (int64_t)lmin * lmin;
+  const int64_t cb = (int64_t)lp * lp - (int64_t)lmin * lmin;
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  for (int e = threadIdx.x; e < nm * nmp; e += 256) {
+    const int m = e / nmp, mp = e % nmp;
+    double z1[NP], z2[NP];
+#pragma unroll
+    for (int a = 0; a < NF; ++a)
+#pragma unroll
+      for (int d = 0; d < NF; ++d) {
+        const int64_t at = ((int64_t)a * kf + rb + m) * ldz + (int64_t)d * kf + cb + mp;
+        z1[a * NF + d] = Z1[at];
+        z2[a * NF + d] = Z2[at];
+      }
+#pragma unroll
+    for (int p1 = 0; p1 < NP; ++p1)
+#pragma unroll
+      for (int p2 = 0; p2 < NP; ++p2) acc[p1 * NP + p2] = fma(z2[p1], z1[p2], acc[p1 * NP + p2]);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double v = acc[q];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) red[wave][q] = v;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < NQ; q += 256)
+    gx[(int64_t)pid * NQ + q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+}
+
 // spectrum id (0..5 = TT,EE,BB,TE,TB,EB) -> its absolute field letters (0 T, 1 E, 2 B)
 __device__ __forceinline__ void spec_fields(int s, int& x, int& y) {
   const int X[6] = {0, 1, 2, 0, 0, 1}, Yv[6] = {0, 1, 2, 1, 2, 2};
@@ -123,6 +173,7 @@ __device__ __forceinline__ int field_pair_spec(int f, int g) {   // absolute let
 struct GramView {
   const double* gram;
   int lmin, nf, np, nq;
+  int cross;      // 1: gram holds the full cross Gram <Z2^{p1}, Z1^{p2}> (np^2 per l >= l')
   int off;        // absolute letter -> harmonic field index: idx = letter - off (QU: E->0, B->1)
   __device__ double get(int l, int lp, int x, int y, int u, int v) const {
     // <Z^{xy}_{l l'}, Z^{uv}_{l l'}> with fields as harmonic indices
@@ -130,8 +181,9 @@ struct GramView {
     int p1, p2;
     if (li >= lj) { p1 = x * nf + y; p2 = u * nf + v; }
     else { int t = li; li = lj; lj = t; p1 = y * nf + x; p2 = v * nf + u; }
-    if (p1 > p2) { int t = p1; p1 = p2; p2 = t; }
     int64_t pid = (int64_t)li * (li + 1) / 2 + lj;
+    if (cross) return gram[(pid * np + p1) * np + p2];   // <Z2^{xy}, Z1^{uv}>: order kept
+    if (p1 > p2) { int t = p1; p1 = p2; p2 = t; }
     return gram[pid * nq + qidx(p1, p2, np)];
   }
 };
@@ -214,8 +266,9 @@ __global__ __launch_bounds__(256) void k_bias_assemble(GramView G, const double*
 }
 
 // y[map][A] = 1/2 sum_{l in b} W_l sum_{(a,c) in sigma} sum_m w[a,l,m] w[c,l,m];  w is [k][ldw].
-__global__ void k_quad_assemble(const double* w, int64_t ldw, int nmaps, int lmin, int kf, int off,
-                                int ns, int s0, int s1, int s2, int s3, int s4, int s5, int nb,
+// With w2 (cross-QML, Eq. q_cross): the bilinear form 1/2 sum w1[a] w2[c] over sigma instead.
+__global__ void k_quad_assemble(const double* w, const double* w2, int64_t ldw, int nmaps, int lmin, int kf,
+                                int off, int ns, int s0, int s1, int s2, int s3, int s4, int s5, int nb,
                                 const int* lo, const int* hi, const double* wl, double* y) {
   const int K = ns * nb;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -230,12 +283,20 @@ __global__ void k_quad_assemble(const double* w, int64_t ldw, int nmaps, int lmi
   for (int l = lo[ba]; l <= hi[ba]; ++l) {
     const int64_t base = (int64_t)l * l - (int64_t)lmin * lmin;
     double t = 0.0;
-    for (int m = 0; m < 2 * l + 1; ++m) {
-      const double wa = w[((int64_t)xa * kf + base + m) * ldw + map];
-      const double wc = w[((int64_t)ya * kf + base + m) * ldw + map];
-      t = fma(wa, wc, t);
+    if (w2) {
+      for (int m = 0; m < 2 * l + 1; ++m) {
+        const int64_t ia = ((int64_t)xa * kf + base + m) * ldw + map, ic = ((int64_t)ya * kf + base + m) * ldw + map;
+        t = fma(w[ia], w2[ic], t);
+        if (xa != ya) t = fma(w[ic], w2[ia], t);
+      }
+    } else {
+      for (int m = 0; m < 2 * l + 1; ++m) {
+        const double wa = w[((int64_t)xa * kf + base + m) * ldw + map];
+        const double wc = w[((int64_t)ya * kf + base + m) * ldw + map];
+        t = fma(wa, wc, t);
+      }
+      if (xa != ya) t *= 2.0;
     }
-    if (xa != ya) t *= 2.0;
     sum = fma(wl[l], t, sum);
   }
   y[(int64_t)map * K + A] = 0.5 * sum;
@@ -465,6 +526,7 @@ GramView make_view(const DevProblem& P, const double* gram) {
   G.gram = gram; G.lmin = P.lmin; G.nf = P.nfm; G.np = P.nfm * P.nfm;
   G.nq = G.np * (G.np + 1) / 2;
   G.off = P.has_t ? 0 : 1;   // QU only: E is harmonic field 0
+  G.cross = 0;
   return G;
 }
 
@@ -491,11 +553,26 @@ hipError_t launch_gram(const DevProblem& P, const double* Z, int64_t ldz, double
   return hipGetLastError();
 }
 
+hipError_t launch_gram_cross(const DevProblem& P, const double* Z1, const double* Z2, int64_t ldz, double* gx,
+                             hipStream_t s) {
+  const int nl = P.lmax - P.lmin + 1;
+  const unsigned npairs = (unsigned)(nl * (nl + 1) / 2);
+  switch (P.nfm) {
+    case 1: hipLaunchKernelGGL(k_gram_cross<1>, dim3(npairs), dim3(256), 0, s, Z1, Z2, ldz, P.lmin, P.kf, gx); break;
+    case 2: hipLaunchKernelGGL(k_gram_cross<2>, dim3(npairs), dim3(256), 0, s, Z1, Z2, ldz, P.lmin, P.kf, gx); break;
+    case 3: hipLaunchKernelGGL(k_gram_cross<3>, dim3(npairs), dim3(256), 0, s, Z1, Z2, ldz, P.lmin, P.kf, gx); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_fisher_assemble(const DevProblem& P, const SpecSel& S, const double* gram,
-                                  double* F, hipStream_t s) {
+                                  double* F, hipStream_t s, bool cross) {
   const int K = S.ns * S.nb;
+  GramView G = make_view(P, gram);
+  G.cross = cross ? 1 : 0;
   hipLaunchKernelGGL(k_fisher_assemble, dim3(blocks((int64_t)K * K, 128)), dim3(128), 0, s,
-                     make_view(P, gram), S.ns, S.spec[0], S.spec[1], S.spec[2], S.spec[3], S.spec[4],
+                     G, S.ns, S.spec[0], S.spec[1], S.spec[2], S.spec[3], S.spec[4],
                      S.spec[5], S.nb, S.lo, S.hi, P.wl, F);
   return hipGetLastError();
 }
@@ -510,9 +587,9 @@ hipError_t launch_bias_assemble(const DevProblem& P, const SpecSel& S, const dou
 }
 
 hipError_t launch_quad_assemble(const DevProblem& P, const SpecSel& S, const double* w, int64_t ldw,
-                                int nmaps, double* y, hipStream_t s) {
+                                int nmaps, double* y, hipStream_t s, const double* w2) {
   const int K = S.ns * S.nb;
-  hipLaunchKernelGGL(k_quad_assemble, dim3(blocks((int64_t)K * nmaps, 128)), dim3(128), 0, s, w, ldw,
+  hipLaunchKernelGGL(k_quad_assemble, dim3(blocks((int64_t)K * nmaps, 128)), dim3(128), 0, s, w, w2, ldw,
                      nmaps, P.lmin, P.kf, P.has_t ? 0 : 1, S.ns, S.spec[0], S.spec[1], S.spec[2],
                      S.spec[3], S.spec[4], S.spec[5], S.nb, S.lo, S.hi, P.wl, y);
   return hipGetLastError();
