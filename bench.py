@@ -34,6 +34,8 @@ def parse():
                     help="autotuning table to use (default: a fresh one, tuned during warmup)")
     ap.add_argument("--no-smw", action="store_true",
                     help="skip the harmonic-basis (SMW, multipole switching) likelihood measurement")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the cross-QML and decorrelated-normalisation timings")
     ap.add_argument("--smw-only", action="store_true",
                     help="only run the SMW likelihood measurement and print its JSON")
     ap.add_argument("--emulator", action="store_true",
@@ -231,6 +233,39 @@ def smw_section(cf, I, problem, packed, d_maps_scan, direct_m2, direct_pts_per_s
     return out
 
 
+def qml_extras(cf, I, problem, bins, packed, d_maps_qml, reps=3):
+    """Cross-QML of the TQU problem with a second data set (same model, diagonal noise of 2 to
+    4 uK^2, one map pair) and the decorrelated normalisation of the step's QML estimates (K = 72):
+    median device-synchronised wall times."""
+    import copy
+    import torch
+    p2 = copy.copy(problem)
+    p2.noise_dense = np.diag(np.random.default_rng(31).uniform(2.0, 4.0, problem.n))
+    pk2 = cf.pack_problem(p2, device=True)
+    d_maps2 = torch.as_tensor(I.white_maps(problem.n, 1, 203, rms=3.0)).cuda()
+    tc, td, sweeps = [], [], 0
+    out = None
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = cf.qml_cross(problem, p2, bins, d_maps_qml, d_maps2, device=True, packed=(packed, pk2))
+        torch.cuda.synchronize()
+        tc.append(time.perf_counter() - t0)
+    q = cf.qml(problem, bins, d_maps_qml, device=True, packed=packed)
+    qq = q["y"] - q["bias"][None, :]
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        (_, _), rep = cf.decorrelate(q["F"], qq, device=True, report=True)
+        torch.cuda.synchronize()
+        td.append(time.perf_counter() - t0)
+        sweeps = rep["ir_iters"]
+    W = out["W"].cpu().numpy()
+    return {"cross_qml": {"ms": 1e3 * float(np.median(tc[1:])), "n": problem.n, "K": int(W.shape[0]),
+                          "W_min_eigenvalue_over_max": float(np.linalg.eigvalsh(W).min() / np.linalg.eigvalsh(W).max())},
+            "decorrelate": {"ms": 1e3 * float(np.median(td[1:])), "K": int(qq.shape[1]), "jacobi_sweeps": int(sweeps)}}
+
+
 def mixed_precision(cf, I, problem, bins, packed, d_maps_qml, d_cl, d_maps_scan, reps=3):
     """Fisher+QML and likelihood-batch times for FP64, FP32-MFMA and split-BF16x3 paths, with the
     errors of the mixed results against the FP64 path (F: relative Frobenius; y, b: in units of
@@ -346,6 +381,7 @@ def main():
                                              packed=[packed])[1]["ms_stage"])
     mixed = None if args.no_mixed else mixed_precision(cf, I, problem, bins, packed, d_maps_qml, d_cl,
                                                           d_maps_scan)
+    extras = None if args.no_extras else qml_extras(cf, I, problem, bins, packed, d_maps_qml)
     smw = None
     if not args.no_smw:
         direct_m2 = cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True, packed=[packed],
@@ -385,6 +421,7 @@ def main():
         "stages_loglike_ms": dict(zip(cf.STAGES, [round(float(x), 4) for x in scan_stage])),
         "mixed_precision": mixed,
         "smw": smw,
+        "qml_extras": extras,
         "roofline": {"bound": "mfma", "kernel": "k_gemm<128,128,false,true,1> FP64 (Z_EB,EB = G_EB^T G_EB)",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic},
