@@ -405,6 +405,9 @@ int potrf_on(Device& d, Factor& F, double* scratch, hipStream_t s, hipStream_t s
   CF_DEV(hipStreamWaitEvent(d.bulk, ev[3], 0));
   CF_DEV(hipStreamWaitEvent(d.bulk2, ev[3], 0));
   Streams st{d.crit, d.bulk, d.bulk2, ev[0], ev[1], ev[2], d.ring};
+  // the lookahead update runs on the bulk CUs, ahead of the trailing update (measured on the
+  // n = 5952 factorisation with its solves: 9.6 -> 9.0-9.3 ms)
+  st.eA = ev[5];
   CF_DEV(potrf_f64(F, scratch, st));
   CF_DEV(hipEventRecord(ev[4], d.crit));
   CF_DEV(hipStreamWaitEvent(s, ev[4], 0));

@@ -108,6 +108,9 @@ struct Streams {
   hipStream_t s, s1, s2;
   hipEvent_t eL, eB, eI;
   hipEvent_t* ring = nullptr;   // 4 events: host-side pacing of the panel loop (nullable)
+  // Lookahead update issued on s1 ahead of the trailing update (eA: its completion), for streams
+  // whose s owns only a few CUs; nullptr: the lookahead runs on s.
+  hipEvent_t eA = nullptr;
 };
 // Scratch for the 256-block inverses: batch * (2*64*64 + 128*128) doubles.
 inline int64_t potrf_scratch(int batch) { return (int64_t)batch * (2 * 64 * 64 + 128 * 128); }

@@ -404,8 +404,16 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     }
     if (pe >= n) break;
     // ---- lookahead: the next panel's columns on the critical path, after the previous bulk update
-    if (pending_b) CF_HIP_TRY(hipStreamWaitEvent(s, st.eB, 0));
-    CF_HIP_TRY(gemm_f64(upd(F, pe, pe, n - pe, pn - pe, c, pe - c), s));
+    if (st.eA) {
+      // on the bulk CUs, after the previous trailing update (stream order) and this panel's chain
+      CF_HIP_TRY(hipStreamWaitEvent(st.s1, st.eL, 0));
+      CF_HIP_TRY(gemm_f64(upd(F, pe, pe, n - pe, pn - pe, c, pe - c), st.s1));
+      CF_HIP_TRY(hipEventRecord(st.eA, st.s1));
+      CF_HIP_TRY(hipStreamWaitEvent(s, st.eA, 0));
+    } else {
+      if (pending_b) CF_HIP_TRY(hipStreamWaitEvent(s, st.eB, 0));
+      CF_HIP_TRY(gemm_f64(upd(F, pe, pe, n - pe, pn - pe, c, pe - c), s));
+    }
     // ---- bulk trailing update beyond the next panel (side stream, overlaps the next panel)
     if (pn < n) {
       CF_HIP_TRY(hipStreamWaitEvent(st.s1, st.eL, 0));
