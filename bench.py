@@ -399,6 +399,17 @@ def main():
     syrk_ms = stage[4]
     achieved = syrk_flops / (syrk_ms * 1e-3) / 1e12
     traffic = _traffic("k_gemm<128,128,false,true,1>")
+    # whole factorisations against the same peak, algorithmic flops only: n^3/3 for the Cholesky and
+    # m^2 per right-hand side solved over m rows (the E,B columns of Y vanish above the first Q
+    # pixel, so they are solved over n - p0 rows; the T columns and the map over all n)
+    nT = 48 * 48 - 4
+    fac_fisher = n ** 3 / 3.0 + (nT + 1) * n ** 2 + (6900 - nT) * (n - p0) ** 2
+    fac_scan = SCAN_POINTS * (n ** 3 / 3.0 + NMAPS_SCAN * n ** 2)
+    factorisation = {}
+    for key, fl, ms in (("fisher", fac_fisher, stage[1]), ("loglike", fac_scan, scan_stage[1])):
+        tf = fl / (ms * 1e-3) / 1e12
+        factorisation[key] = {"flops": fl, "ms": round(float(ms), 4), "tflops": tf,
+                              "frac": tf / PEAK_FP64_TFLOPS}
     out = {
         "metric": "Fisher wall time & −2lnL evals/s, FP64 vs mixed/emulator, Nside16 TQU",
         "value": 1000.0 / ms_step,
@@ -422,6 +433,7 @@ def main():
         "mixed_precision": mixed,
         "smw": smw,
         "qml_extras": extras,
+        "factorisation": factorisation,
         "roofline": {"bound": "mfma", "kernel": "k_gemm<128,128,false,true,1> FP64 (Z_EB,EB = G_EB^T G_EB)",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic},

@@ -457,9 +457,13 @@ hipError_t gemm_f64(const GemmDesc& d, hipStream_t s) {
   }
   if (d.tile == 128) return launch_tile<128, 128>(d, s);
   if (d.tile == 64) return launch_tile<64, 64>(d, s);
+  // 128 x 128 tiles only for long contractions over enough tiles to fill the chip.  Measured on
+  // rank-256 and rank-512 updates (the factorisation's trailing and solve-row updates, single and
+  // batched): 64 x 64 tiles are faster there at every size, the shorter workgroups balancing better
+  // and leaving slots free sooner for the kernels of the critical chain.
   const int64_t batch = d.batch > 0 ? d.batch : 1;
   const int64_t big = ((d.M + 127) / 128) * ((d.N + 127) / 128) * batch;
-  if (big >= 480) return launch_tile<128, 128>(d, s);
+  if (big >= 480 && d.K > 512) return launch_tile<128, 128>(d, s);
   return launch_tile<64, 64>(d, s);
 }
 
