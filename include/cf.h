@@ -159,8 +159,10 @@ int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t npoints,
  * eigenvalues below 1e-12 of the largest set to zero.  F: [K][K], only its lower triangle is read;
  * q, out: [nvec][K] (nvec = 0 with q = out = NULL computes only Fmhalf_out); Fmhalf_out: [K][K]
  * F^-1/2 (nullable; with it the caller can carry theory spectra through the same window F^1/2).
- * 1 <= K <= 1024.  All arrays in memory space mem.  CF_ENOCONV if the Jacobi sweeps do not reach
- * 1e-15 relative off-diagonal norm within 60 sweeps; cf_report.ir_iters = sweeps run. */
+ * 1 <= K <= 1024.  All arrays in memory space mem.  A rotation is skipped when |a_pq| is at most
+ * max(1e-15 sqrt(|a_pp a_qq|), 2e-17 |F|_F); CF_ENOCONV if a sweep still rotates after 60 sweeps;
+ * cf_report.ir_iters = sweeps run.  Host arrays are checked for NaN/Inf (CF_EINVAL); device
+ * arrays are not. */
 int cf_decorrelate(const double* F, int32_t K, const double* q, int32_t nvec, int32_t mem, double* out,
                    double* Fmhalf_out, const cf_exec* ex, cf_report* rep);
 
