@@ -299,6 +299,31 @@ def mixed_precision(cf, I, problem, bins, packed, d_maps_qml, d_cl, d_maps_scan,
     return out
 
 
+def host_input_step(cf, problem, bins, maps_qml, maps_scan, cl_points, steps=3):
+    """The same step with every input in host memory (numpy arrays, mem = CF_MEM_HOST): the library
+    copies the dense noise covariance, the maps and the scan spectra to the device on each call and
+    the results back, so this rate includes the PCIe transfers.  Reported beside the device-resident
+    rate, never as the bench value."""
+    import torch
+    pk = cf.pack_problem(problem, device=False)
+    cl = np.ascontiguousarray(cl_points)
+
+    def step():
+        cf.qml(problem, bins, maps_qml, packed=pk)
+        cf.loglike_batch([problem], cl, [maps_scan], packed=[pk], autotune=True)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    return {"steps": steps, "ms_per_step": ms, "steps_per_s": 1e3 / ms,
+            "bytes_in_per_step": int(2 * problem.n * problem.n * 8 + maps_qml.size * 8 + maps_scan.size * 8
+                                     + cl.size * 8)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -382,6 +407,8 @@ def main():
     mixed = None if args.no_mixed else mixed_precision(cf, I, problem, bins, packed, d_maps_qml, d_cl,
                                                           d_maps_scan)
     extras = None if args.no_extras else qml_extras(cf, I, problem, bins, packed, d_maps_qml)
+    host_inputs = None if args.no_extras else host_input_step(cf, problem, bins, maps_qml, maps_scan,
+                                                                 cl_points)
     smw = None
     if not args.no_smw:
         direct_m2 = cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True, packed=[packed],
@@ -433,6 +460,7 @@ def main():
         "mixed_precision": mixed,
         "smw": smw,
         "qml_extras": extras,
+        "host_inputs": host_inputs,
         "factorisation": factorisation,
         "roofline": {"bound": "mfma", "kernel": "k_gemm<128,128,false,true,1> FP64 (Z_EB,EB = G_EB^T G_EB)",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
