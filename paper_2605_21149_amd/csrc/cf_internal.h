@@ -174,6 +174,12 @@ hipError_t launch_colsumsq(const double* U, int64_t rows, int64_t cols, int64_t 
 // out[b][r] = sum_c X[b][r][c]^2 for a batch of row-major (rows x cols, ld ldx) matrices.
 hipError_t launch_rowsumsq(const double* X, int64_t rows, int64_t cols, int64_t ldx, int64_t sX, int batch,
                            double* out, int64_t sOut, hipStream_t s);
+// Stochastic log-det correction of a mixed-precision factor: probe blocks (+-1 by a counter hash)
+// written (sub = 0) or subtracted (sub = 1) for B blocks of n x m, and ld[b] += mean over the m
+// probes of t1 - n - t2 / 2.
+hipError_t launch_probes(double* P, int64_t n, int64_t m, int B, int sub, hipStream_t s);
+hipError_t launch_ld_correct(double* ld, const double* t1, const double* t2, int B, int64_t m, int64_t n,
+                             hipStream_t s);
 hipError_t launch_coldot(const double* U, const double* V, int64_t rows, int64_t cols, int64_t ld,
                          int64_t sU, int64_t sV, int batch, double* out, int64_t sOut, hipStream_t s);
 hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s);

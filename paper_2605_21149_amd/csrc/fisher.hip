@@ -659,8 +659,51 @@ hipError_t launch_scan_finish(const double* chi2b, const double* ldb, int B, int
   return hipGetLastError();
 }
 
+// Probe vectors of the stochastic log-det correction: entry (i, j) of the n x m probe block is
+// +1 or -1 by the low bit of splitmix64 (Steele, Lea and Flood 2014) of the counter i * m + j,
+// the same for every point of a batch.
+__device__ __forceinline__ double probe_sign(int64_t i, int64_t j, int64_t m) {
+  uint64_t z = 0x3c6ef372fe94f82aull + (uint64_t)(i * m + j) * 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  return (z & 1) ? 1.0 : -1.0;
+}
+
+// P[b][i][j] = z(i, j) (sub = 0) or P[b][i][j] -= z(i, j) (sub = 1), P: B blocks of n x m.
+__global__ void k_probes(double* P, int64_t n, int64_t m, int B, int sub) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)B * n * m) return;
+  const int64_t r = idx % (n * m), i = r / m, j = r % m;
+  const double z = probe_sign(i, j, m);
+  P[idx] = sub ? P[idx] - z : z;
+}
+
+// ld[b] += (1/m) sum_j (t1[b][j] - n - t2[b][j] / 2): the estimate of tr X - |X|_F^2 / 2 with
+// t1 = z^T X z + z^T z and t2 = |X z|^2 per probe.
+__global__ void k_ld_correct(double* ld, const double* t1, const double* t2, int B, int64_t m, int64_t n) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double s = 0.0;
+  for (int64_t j = 0; j < m; ++j) s += (t1[b * m + j] - (double)n) - 0.5 * t2[b * m + j];
+  ld[b] += s / (double)m;
+}
+
 __global__ void k_set_i64(int64_t* p, int64_t v) { if (threadIdx.x == 0) *p = v; }
 __global__ void k_add_i64(int64_t* p, int64_t v) { if (threadIdx.x == 0) *p += v; }
+
+hipError_t launch_probes(double* P, int64_t n, int64_t m, int B, int sub, hipStream_t s) {
+  const int64_t tot = (int64_t)B * n * m;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_probes, dim3(blocks(tot, 256)), dim3(256), 0, s, P, n, m, B, sub);
+  return hipGetLastError();
+}
+
+hipError_t launch_ld_correct(double* ld, const double* t1, const double* t2, int B, int64_t m, int64_t n,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_ld_correct, dim3((B + 63) / 64), dim3(64), 0, s, ld, t1, t2, B, m, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, s, p, v);
