@@ -266,6 +266,41 @@ def qml_extras(cf, I, problem, bins, packed, d_maps_qml, reps=3):
             "decorrelate": {"ms": 1e3 * float(np.median(td[1:])), "K": int(qq.shape[1]), "jacobi_sweeps": int(sweeps)}}
 
 
+def qu_scan(cf, I, npoints=256, reps=3):
+    """The two-problem QU likelihood scan (N_side 8, n = 1088, and N_side 16, n = 3968, in one call,
+    64 maps each) on a bounded sample of the scan's parameter box: points/s (one point = both
+    problems) and map evaluations/s, FP64 and FP32 mixed (with the refined chi^2 and the log-det
+    correction), and the mixed path's largest |d(-2 ln L)| against FP64.  Autotuning is off: a
+    multi-problem call takes the default batch."""
+    import torch
+    pa, pb = I.qu_scan_problem(8), I.qu_scan_problem(16)
+    pks = [cf.pack_problem(pa, device=True), cf.pack_problem(pb, device=True)]
+    maps = [torch.as_tensor(I.white_maps(pa.n, 64, 402, rms=3.0)).cuda(),
+            torch.as_tensor(I.white_maps(pb.n, 64, 403, rms=3.0)).cuda()]
+    pts = I.scan_points(npoints, seed=401)
+    clp = np.zeros((npoints, 2, 6, pb.lmax + 1))
+    clp[:, 0, :, :pa.lmax + 1] = I.scan_spectra(pts, pa.cl)
+    clp[:, 1] = I.scan_spectra(pts, pb.cl)
+    d_cl = torch.as_tensor(clp).cuda()
+    out, ref = {"n": [pa.n, pb.n], "points": npoints, "maps": 64}, None
+    for prec, name in ((cf.CF_FP64, "fp64"), (cf.CF_MIXED_FP32, "fp32")):
+        ts, res = [], None
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = cf.loglike_batch([pa, pb], d_cl, maps, precision=prec, device=True, packed=pks)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts[1:]))
+        m2 = res["m2lnL"].cpu().numpy()
+        out[name] = {"ms": 1e3 * t, "points_per_s": npoints / t, "map_evals_per_s": 2 * 64 * npoints / t}
+        if ref is None:
+            ref = m2
+        else:
+            out[name]["max_abs_dm2lnL_vs_fp64"] = float(np.abs(m2 - ref).max())
+    return out
+
+
 def mixed_precision(cf, I, problem, bins, packed, d_maps_qml, d_cl, d_maps_scan, reps=3):
     """Fisher+QML and likelihood-batch times for FP64, FP32-MFMA and split-BF16x3 paths, with the
     errors of the mixed results against the FP64 path (F: relative Frobenius; y, b: in units of
@@ -407,6 +442,7 @@ def main():
     mixed = None if args.no_mixed else mixed_precision(cf, I, problem, bins, packed, d_maps_qml, d_cl,
                                                           d_maps_scan)
     extras = None if args.no_extras else qml_extras(cf, I, problem, bins, packed, d_maps_qml)
+    scan_qu = None if args.no_extras else qu_scan(cf, I)
     host_inputs = None if args.no_extras else host_input_step(cf, problem, bins, maps_qml, maps_scan,
                                                                  cl_points)
     smw = None
@@ -461,6 +497,7 @@ def main():
         "smw": smw,
         "qml_extras": extras,
         "host_inputs": host_inputs,
+        "qu_scan": scan_qu,
         "factorisation": factorisation,
         "roofline": {"bound": "mfma", "kernel": "k_gemm<128,128,false,true,1> FP64 (Z_EB,EB = G_EB^T G_EB)",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",

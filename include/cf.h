@@ -150,8 +150,8 @@ int cf_qml_cross(const cf_problem* prob1, const cf_problem* prob2, const cf_bins
  * Geometry, beam, window and noise come from probs[p]; its cl is not used.  Memory space
  * of cl_points, maps and outputs: probs[0].mem.  Mixed precisions: chi^2 from FP64-refined solves;
  * ln|C| = ln|L L^T| of the mixed factor L plus a stochastic estimate of tr X - |X|_F^2 / 2,
- * X = L^-1 (C - L L^T) L^-T, from 128 fixed +-1 probe vectors (deterministic; standard deviation
- * about 0.125 |X|_F). */
+ * X = L^-1 (C - L L^T) L^-T, from 384 fixed +-1 probe vectors with FP64 solves (deterministic;
+ * standard deviation about 0.07 |X|_F). */
 int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t npoints,
                      const double* cl_points, int32_t lstride, const double* const* maps,
                      int32_t nmaps, int32_t precision, double* m2lnL, double* chi2,

@@ -42,8 +42,10 @@ int fail(int code, const char* fmt, ...) {
 constexpr int kEvents = 16;
 constexpr int kGraphMaxN = 2048;   // scans of larger problems launch eagerly
 // Probes of the mixed path's stochastic log-det correction: the estimate's standard deviation is
-// about sqrt(2 / kLdProbes) |X|_F (measured |X|_F = 2e-3 for FP32 updates at n = 5952).
-constexpr int64_t kLdProbes = 128;
+// about sqrt(2 / kLdProbes) |X|_F.  Measured with FP32 updates: 2.5e-4 at 256 probes on the QU
+// N_side 16 scan problem (|X|_F about 2.8e-3), against biases of ln|C| of the FP32 factor of up to
+// 1e-3 there and 2e-3 at n = 5952; 384 probes keep a deviation of 1e-3 beyond five of them.
+constexpr int64_t kLdProbes = 384;
 struct Device {
   std::mutex mu;
   hipStream_t stream = nullptr;
@@ -1177,19 +1179,23 @@ int scan_batch(const ScanCtx& x, int64_t i0, int b, int64_t* i0p, Timer* tm) {
   CF_DEV(launch_sum_parts(x.ldp, (int)nblk, nblk, b, x.ldb, 1, c.s));
   if (x.mode) {
     // ln|C| = ln|L L^T| + tr X - |X|_F^2 / 2 + O(|X|^3), X = L^-1 E L^-T, E = C - L L^T the
-    // factor's error.  With y = L^-T z and v = C y for a probe z of +-1 entries, z^T X z =
+    // mixed factor's error.  With y = L^-T z and v = C y for a probe z of +-1 entries, z^T X z =
     // y^T v - z^T z and X z = L^-1 v - z, so each probe costs two triangular solves and one
     // product with the FP64 copy of C, and E is never formed.
+    // The two solves run in FP64 against the mixed factor (its inverted diagonal blocks are FP64):
+    // y^T v - z^T z cancels to about |X|, so y must be accurate far beyond FP32.
     const int64_t m = kLdProbes;
+    Factor F64 = F;
+    F64.mode = 0;
     CF_DEV(launch_probes(x.Pz, n, m, b, 0, c.s));
-    CF_DEV(trsm_lower_t_f64(F, x.Pz, m, n * m, x.Pw, m, n * m, m, c.s));      // Pw = y (Pz consumed)
+    CF_DEV(trsm_lower_t_f64(F64, x.Pz, m, n * m, x.Pw, m, n * m, m, c.s));    // Pw = y (Pz consumed)
     GemmDesc v{};
     v.M = n; v.N = m; v.K = n;
     v.A = x.C0b; v.lda = n; v.B = x.Pw; v.ldb = m; v.C = x.Pz; v.ldc = m;
     v.alpha = 1.0; v.beta = 0.0; v.batch = b; v.sA = n * n; v.sB = n * m; v.sC = n * m;
     CF_DEV(gemm_f64(v, c.s));                                                  // Pz = v = C y
     CF_DEV(launch_coldot(x.Pw, x.Pz, n, m, m, n * m, n * m, b, x.T1, m, c.s));  // y^T v
-    CF_DEV(trsm_lower_f64(F, x.Pz, m, n * m, x.Pw, m, n * m, m, 0, c.s));     // Pw = L^-1 v
+    CF_DEV(trsm_lower_f64(F64, x.Pz, m, n * m, x.Pw, m, n * m, m, 0, c.s));   // Pw = L^-1 v
     CF_DEV(launch_probes(x.Pw, n, m, b, 1, c.s));                             // X z
     CF_DEV(launch_colsumsq(x.Pw, n, m, m, n * m, b, x.T2, m, c.s));
     CF_DEV(launch_ld_correct(x.ldb, x.T1, x.T2, b, m, n, c.s));
