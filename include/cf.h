@@ -116,7 +116,9 @@ int cf_cov_build(const cf_problem* prob, double* C_out, int64_t* n_out,
 
 /* Fisher matrix F_bb' = 1/2 tr[C^-1 P_b C^-1 P_b'] (Eq. fisher) with native bins (Sect. 2.4),
  * evaluated as block Frobenius products of Z = Y^T C^-1 Y (Eqs. projected_inv,
- * fisher_harmonic, sparse_trace).  F_out: [(ns*nb)^2] in prob->mem space. */
+ * fisher_harmonic, sparse_trace).  F_out: [(ns*nb)^2] in prob->mem space.  Mixed precisions
+ * factor C with FP32 or split-BF16x3 updates and refine C^-1 Y once with an FP64 residual
+ * (Z = G^T G + G^T L^-1 (Y - C L^-T G), G = L^-1 Y, products in FP64). */
 int cf_fisher(const cf_problem* prob, const cf_bins* bins, int32_t precision, double* F_out,
               const cf_exec* ex, cf_report* rep);
 

@@ -459,6 +459,7 @@ int read_flags(CallCtx& c, const int* dflags, int nflags, int* out) {
 // ------------------------------------------------------------------------------- Fisher core
 struct FisherBufs {
   double *C, *C0, *Y, *G, *Z, *Linv, *Li256, *scratch, *ldpart, *gram, *ztr, *F;
+  double *Gc, *Xr;   // mixed: copy of G and L^-T G for the refinement of C^-1 Y
   int* lo;
   int* hi;
   int* flags;   // [0] non-finite covariance, [1] first failing pivot, [2] F pivot failure
@@ -467,7 +468,7 @@ struct FisherBufs {
 // Buffers of the Fisher path.  FP64 factorises [C; D^T; Y^T] (n + nm + k rows, ld n) in one
 // pass, so that u^T = (L^-1 d)^T and G^T = (L^-1 Y)^T come out of the factorisation as the rows
 // below C.  Mixed: C, Y and G apart, plus an FP64 copy of C for the refinement residuals.
-struct FisherSizes { size_t C, C0, Y, G, Li256; };
+struct FisherSizes { size_t C, C0, Y, G, Li256, Gc, Xr; };
 FisherSizes fisher_sizes(const HostProblem& H, int mode, int nm) {
   const size_t n = H.n, k = H.k;
   FisherSizes q;
@@ -476,6 +477,8 @@ FisherSizes fisher_sizes(const HostProblem& H, int mode, int nm) {
   q.Y = n * k;
   q.G = mode ? n * k : 1;
   q.Li256 = mode ? (n / 256) * 256 * 256 : 1;
+  q.Gc = mode ? n * k : 1;   // refinement of C^-1 Y (mixed)
+  q.Xr = mode ? n * k : 1;
   return q;
 }
 
@@ -488,6 +491,8 @@ size_t fisher_ws(const HostProblem& H, const HostBins& B, Sizer& z, int mode, in
   z.add<double>(q.C0);
   z.add<double>(q.Y);
   z.add<double>(q.G);
+  z.add<double>(q.Gc);
+  z.add<double>(q.Xr);
   z.add<double>((size_t)H.k * H.k);
   z.add<double>((size_t)((H.n + kNB - 1) / kNB) * kNB * kNB);
   z.add<double>(q.Li256);
@@ -511,6 +516,8 @@ void fisher_take(Bump& bp, const HostProblem& H, const HostBins& B, FisherBufs& 
   f.C0 = bp.take<double>(q.C0);
   f.Y = bp.take<double>(q.Y);
   f.G = bp.take<double>(q.G);
+  f.Gc = bp.take<double>(q.Gc);
+  f.Xr = bp.take<double>(q.Xr);
   f.Z = bp.take<double>((size_t)H.k * H.k);
   f.Linv = bp.take<double>((size_t)((H.n + kNB - 1) / kNB) * kNB * kNB);
   f.Li256 = bp.take<double>(q.Li256);
@@ -708,6 +715,10 @@ int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, F
   }
   const bool split = H.has_t && H.has_p;
   const int64_t kT = H.has_t ? H.kf : 0, kP = k - kT;
+  // Z through the mixed factor alone is off by 1e-6 (FP32) to 1e-4 (split-BF16x3) in F and more in
+  // the noise bias: Z runs in FP64 and C^-1 Y gets one FP64 refinement step below
+  const bool zref = mode != 0;
+  const int zmode = zref ? 0 : mode;
   // Y is block diagonal over [T | QU]: the E,B columns vanish on the T rows, so their solve
   // starts at the 64-row block p0 holding the first Q row, and G's E,B columns above p0 are zero.
   const int64_t p0 = split ? (H.npx / kNB) * kNB : 0;
@@ -724,7 +735,7 @@ int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, F
     g.M = kT; g.N = kT; g.K = n;
     g.A = f.G; g.lda = k; g.at = 1;
     g.B = f.G; g.ldb = k; g.bt = 0;
-    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1; g.mode = mode;
+    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1; g.mode = zmode;
     CF_DEV(gemm_f64(g, s));
     // Z rows of E,B against all columns (lower part), over rows >= p0 (aux[0])
     CF_DEV(hipStreamWaitEvent(s1, ev[E_T], 0));
@@ -733,7 +744,7 @@ int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, F
     h.A = f.G + p0 * k + kT; h.lda = k; h.at = 1;
     h.B = f.G + p0 * k; h.ldb = k; h.bt = 0;
     h.C = f.Z + kT * k; h.ldc = k; h.alpha = 1.0; h.beta = 0.0; h.lower = 1; h.diag_off = kT;
-    h.batch = 1; h.mode = mode;
+    h.batch = 1; h.mode = zmode;
     hipEvent_t tz = tm.open(s1);
     CF_DEV(gemm_f64(h, s1));
     tm.close(ST_SYRK, tz, s1);
@@ -763,7 +774,7 @@ int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, F
     g.M = k; g.N = k; g.K = n;
     g.A = f.G; g.lda = k; g.at = 1;
     g.B = f.G; g.ldb = k; g.bt = 0;
-    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1; g.mode = mode;
+    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1; g.mode = zmode;
     hipEvent_t tz = tm.open(s);
     CF_DEV(gemm_f64(g, s));
     tm.close(ST_SYRK, tz, s);
@@ -779,6 +790,26 @@ int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, F
       CF_DEV(hipEventRecord(ev[E_S2], s2));
       CF_DEV(hipStreamWaitEvent(s, ev[E_S2], 0));
     }
+  }
+  if (zref) {
+    // Z = Y^T C^-1 Y with one FP64 refinement of X = C^-1 Y through the mixed factor: X0 = L^-T G,
+    // R = Y - C X0 (FP64 copy of C), W = L^-1 R, so Y^T (X0 + L^-T W) = G^T G + G^T W.  The E,B
+    // columns of G above the first Q block were never written by the split solve: zero them.
+    if (split && p0 > 0) CF_DEV(launch_fill_block(f.G + kT, k, p0, kP, 0.0, s));
+    CF_DEV(hipMemcpyAsync(f.Gc, f.G, sizeof(double) * n * k, hipMemcpyDeviceToDevice, s));
+    CF_DEV(trsm_lower_t_f64(F, f.Gc, k, 0, f.Xr, k, 0, k, s));      // X0 (Gc consumed)
+    CF_DEV(launch_ybuild(P, f.Y, k, s));
+    GemmDesc r{};
+    r.M = n; r.N = k; r.K = n;
+    r.A = f.C0; r.lda = n; r.B = f.Xr; r.ldb = k; r.C = f.Y; r.ldc = k;
+    r.alpha = -1.0; r.beta = 1.0; r.batch = 1;
+    CF_DEV(gemm_f64(r, s));                                          // R = Y - C X0
+    CF_DEV(trsm_lower_f64(F, f.Y, k, 0, f.Gc, k, 0, k, 0, s));      // W = L^-1 R (R consumed)
+    GemmDesc dz{};
+    dz.M = k; dz.N = k; dz.K = n;
+    dz.A = f.G; dz.lda = k; dz.at = 1; dz.B = f.Gc; dz.ldb = k; dz.bt = 0;
+    dz.C = f.Z; dz.ldc = k; dz.alpha = 1.0; dz.beta = 1.0; dz.lower = 1; dz.batch = 1;
+    CF_DEV(gemm_f64(dz, s));                                         // Z += G^T W (lower)
   }
   tm.mark(ST_OTHER);
   CF_DEV(launch_symmetrize(f.Z, k, k, s));

@@ -180,6 +180,8 @@ hipError_t launch_rowsumsq(const double* X, int64_t rows, int64_t cols, int64_t 
 hipError_t launch_probes(double* P, int64_t n, int64_t m, int B, int sub, hipStream_t s);
 hipError_t launch_ld_correct(double* ld, const double* t1, const double* t2, int B, int64_t m, int64_t n,
                              hipStream_t s);
+// A[r][c] = v over a rows x cols block (leading dimension ld).
+hipError_t launch_fill_block(double* A, int64_t ld, int64_t rows, int64_t cols, double v, hipStream_t s);
 hipError_t launch_coldot(const double* U, const double* V, int64_t rows, int64_t cols, int64_t ld,
                          int64_t sU, int64_t sV, int batch, double* out, int64_t sOut, hipStream_t s);
 hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s);

@@ -689,6 +689,13 @@ __global__ void k_ld_correct(double* ld, const double* t1, const double* t2, int
   ld[b] += s / (double)m;
 }
 
+// A[r][c] = v for r < rows, c < cols (leading dimension ld).
+__global__ void k_fill_block(double* A, int64_t ld, int64_t rows, int64_t cols, double v) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  A[(idx / cols) * ld + idx % cols] = v;
+}
+
 __global__ void k_set_i64(int64_t* p, int64_t v) { if (threadIdx.x == 0) *p = v; }
 __global__ void k_add_i64(int64_t* p, int64_t v) { if (threadIdx.x == 0) *p += v; }
 
@@ -702,6 +709,13 @@ hipError_t launch_probes(double* P, int64_t n, int64_t m, int B, int sub, hipStr
 hipError_t launch_ld_correct(double* ld, const double* t1, const double* t2, int B, int64_t m, int64_t n,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_ld_correct, dim3((B + 63) / 64), dim3(64), 0, s, ld, t1, t2, B, m, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_block(double* A, int64_t ld, int64_t rows, int64_t cols, double v, hipStream_t s) {
+  const int64_t tot = rows * cols;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_block, dim3(blocks(tot, 256)), dim3(256), 0, s, A, ld, rows, cols, v);
   return hipGetLastError();
 }
 

@@ -156,3 +156,27 @@ def test_mixed_loglike_tqu_nside16_meets_the_likelihood_tolerance(prec_name):
     say(f"  max |d(-2lnL)| {dm2.max():.2e}, |d ln|C|| {dld.max():.2e}, |d chi2| {dx2.max():.2e}")
     assert dx2.max() < 1e-5
     assert dm2.max() <= 1e-3
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec_name", ["CF_MIXED_FP32", "CF_MIXED_BF16X3"])
+def test_mixed_fisher_tqu_nside16_within_1e6_of_fp64(prec_name):
+    """The bench workload's Fisher matrix and QML estimates in the mixed paths: F within 1e-6
+    (relative Frobenius) of the FP64 path, which matches the oracle at 1e-10 (the first test of
+    this file), through the FP64 refinement of C^-1 Y (without it: 8.5e-7 for FP32, 7.4e-5 for
+    split-BF16x3).  The estimates y, bias and C-hat in units of the Fisher errors within 1e-5."""
+    cf = _cf()
+    prec = getattr(cf, prec_name)
+    p = I.tqu_problem_nside16(dense_noise=True)
+    bins = I.uniform_bins(2, 47, 4, I.SPEC_NAMES)
+    maps = I.white_maps(p.n, 1, 202, rms=3.0)
+    say("mixed fisher tqu nside16:", prec_name)
+    ref = {k: to_np(v) for k, v in cf.qml(p, bins, maps, device=True).items()}
+    got = {k: to_np(v) for k, v in cf.qml(p, bins, maps, precision=prec, device=True).items()}
+    F = ref["F"]
+    fro = np.linalg.norm(got["F"] - F) / np.linalg.norm(F)
+    m = {"y": metric_vec_fisher(got["y"], ref["y"], F), "bias": metric_vec_fisher(got["bias"], ref["bias"], F),
+         "chat": metric_chat(got["chat"], ref["chat"], F)}
+    say(f"  relFro F {fro:.2e}", m)
+    assert fro <= 1e-6
+    assert all(v < 1e-5 for v in m.values()), m
