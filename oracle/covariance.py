@@ -15,7 +15,7 @@ Two independent routes to S:
   and the E/B functions of Eq. EB_from_spin built from spin_y_def with
   ``wigner.wigner_d`` for Q/U.
 
-Conventions (readings of the paper, listed in the design doc):
+Conventions (readings of the paper where it leaves the choice open):
 * data order [T | Q | U] over the same active pixels (Eqs. V_multifield);
 * (Q + iU) = sum a_{2,lm} 2Y_lm, (Q - iU) = sum a_{-2,lm} -2Y_lm with
   a_E = -(a_2 + a_-2)/2, a_B = i (a_2 - a_-2)/2, so that

@@ -14,7 +14,7 @@ Lambda_inf the window's mode covariance,
 
 and -2 ln L = d^T C^-1 d + ln|C| (Eq. pixel_likelihood, n ln 2 pi left out).
 
-Readings (listed in DESIGN.md):
+Readings (where the paper leaves the choice open):
 * The window is a multipole range [wlo, whi] together with a set of harmonic fields ("T", "E",
   "B"); the paper's switching is by multipole only, which is the case of all the problem's
   fields.  Restricting the fields lets a QU scan that varies only EE keep B in N_eff.

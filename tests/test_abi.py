@@ -66,7 +66,7 @@ def test_argument_validation():
     r.noise_diag = r.noise_diag.copy()
     r.noise_diag[3] = np.inf
     assert "noise" in _expect(cf.CF_EINVAL, lambda: cf.cov_build(r))
-    # unsupported precision in this build is rejected, not silently run in FP64
+    # an unknown precision is rejected, not silently run in FP64
     _expect(cf.CF_EINVAL, lambda: cf.fisher(p, bins, precision=7))
 
 
