@@ -362,8 +362,9 @@ def host_input_step(cf, problem, bins, maps_qml, maps_scan, cl_points, steps=3):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              f"(multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
+        print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the path runs on a single GPU; sharding the scan points or the Y columns across "
+              f"GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.calibrate_copy:
@@ -375,7 +376,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 8 * n}), flush=True)
         return
-    # a fresh autotuning table: the first warmup step tunes the likelihood batch for this build
+    # a fresh autotuning table: the first warmup step tunes the likelihood batch of this workload
     if args.tune_cache:
         os.environ["CF_TUNE_CACHE"] = args.tune_cache
     else:
