@@ -220,3 +220,53 @@ def bin_matrix(lmin, lmax, lo, hi):
     for b, (a, c) in enumerate(zip(lo, hi)):
         P[b, a - lmin:c - lmin + 1] = 1.0
     return P
+
+
+def band_fiducial(cl, spectra, lo, hi, chat, fields):
+    """Fiducial of the next iteration of iterative QML (the paper describes the iteration as
+    re-entering the pipeline with the previous estimates in place of the fiducial, Sects. 2.2 and
+    6; the rules below are readings): every estimated band C_hat[s, b] replaces the fiducial of
+    spectrum s as a flat band over the multipoles of bin b; then, at every multipole, the spectrum
+    matrix over the problem's harmonic fields (T; E, B; or T, E, B) is replaced by its nearest
+    positive semi-definite matrix (negative eigenvalues set to zero), so that the next covariance
+    stays positive definite.  cl: [6][lmax + 1] in TT, EE, BB, TE, TB, EB order."""
+    new = np.array(cl, dtype=np.float64, copy=True)
+    for k, (s, a, b) in enumerate(parameters(spectra, lo, hi)):
+        new[SPECS.index(s), a:b + 1] = chat[k]
+    harm = [f for f in ("T", "E", "B") if (f == "T" and "T" in fields) or (f != "T" and "Q" in fields)]
+    idx = {("T", "T"): 0, ("E", "E"): 1, ("B", "B"): 2, ("T", "E"): 3, ("T", "B"): 4, ("E", "B"): 5}
+    for l in range(new.shape[1]):
+        M = np.zeros((len(harm), len(harm)))
+        for i, a in enumerate(harm):
+            for j, b in enumerate(harm):
+                key = (a, b) if (a, b) in idx else (b, a)
+                M[i, j] = new[idx[key], l]
+        xi, U = np.linalg.eigh(M)
+        if xi.min() >= 0.0:
+            continue
+        P = (U * np.maximum(xi, 0.0)[None, :]) @ U.T
+        for i, a in enumerate(harm):
+            for j, b in enumerate(harm):
+                if j >= i:
+                    key = (a, b) if (a, b) in idx else (b, a)
+                    new[idx[key], l] = P[i, j]
+    return new
+
+
+def iterate(problem, spectra, lo, hi, data, max_iter=20, tol=1e-6):
+    """Iterative QML for one map: C_hat^(i) = F(C^(i))^-1 (y - b)(C^(i)) with C^(0) the problem's
+    fiducial and C^(i+1) = band_fiducial(C_hat^(i)); stops when no band moves by more than tol of
+    its Fisher error sqrt((F^-1)_bb) between two iterations.  Returns (C_hat, F, iterations)."""
+    p = problem.__class__(**{**problem.__dict__})
+    p.cl = np.array(problem.cl, dtype=np.float64, copy=True)
+    prev = None
+    for it in range(1, max_iter + 1):
+        r = qml_harmonic(p, spectra, lo, hi, np.atleast_2d(data))
+        chat = r["chat"][0]
+        if prev is not None:
+            sig = np.sqrt(np.diag(np.linalg.inv(r["F"])))
+            if np.max(np.abs(chat - prev) / sig) < tol:
+                return chat, r["F"], it
+        prev = chat
+        p.cl = band_fiducial(p.cl, spectra, lo, hi, chat, problem.fields)
+    return chat, r["F"], max_iter

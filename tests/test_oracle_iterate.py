@@ -1,0 +1,69 @@
+"""Pins of the oracle's iterative QML (oracle/qml.py: band_fiducial, iterate).
+
+The paper states that the single-step QML estimate is one Newton step towards the maximum of the
+pixel likelihood (Eq. pixel_likelihood) and that iterative QML converges to that maximum
+(Sects. 2.2 and 2.6).  With bins that cover every multipole of every spectrum of the fields, the
+covariance is N + sum_b C_b P_b exactly, so at the fixed point the exact likelihood, computed by
+the direct Cholesky route and not by the QML code, must be stationary in the band amplitudes:
+checked by central finite differences.  Also: the spectrum projection keeps S positive
+semi-definite and leaves a positive semi-definite spectrum unchanged."""
+import numpy as np
+
+from oracle import covariance as cv
+from oracle import likelihood, qml
+
+from oracle_cases import tiny_healpix
+
+
+def _data(p, seed):
+    C = cv.total_covariance(p)
+    return np.linalg.cholesky(C) @ np.random.default_rng(seed).standard_normal(p.n)
+
+
+def test_iterative_qml_converges_to_a_stationary_point_of_the_pixel_likelihood():
+    p = tiny_healpix("T", nside=4, lmax=9, cut=0.25)
+    lo = np.array([2, 4, 6, 8]); hi = lo + 1
+    d = _data(p, 71)
+    chat, F, it = qml.iterate(p, ("TT",), lo, hi, d, max_iter=60, tol=1e-10)
+    assert it < 60
+    assert np.all(chat > 0)                                   # the projection stays inactive
+    cl = qml.band_fiducial(p.cl, ("TT",), lo, hi, chat, p.fields)
+    sig = np.sqrt(np.diag(np.linalg.inv(F)))
+    for b in range(len(lo)):
+        h = 1e-3 * sig[b]
+        f = []
+        for sgn in (1, -1):
+            c = cl.copy()
+            c[0, lo[b]:hi[b] + 1] += sgn * h
+            f.append(likelihood.minus2lnL(p, d, cl=c)[0][0])
+        g = (f[0] - f[1]) / (2 * h)
+        assert abs(g) * sig[b] < 1e-5, (b, g * sig[b])
+    # one step from a fiducial far off moves -2 ln L downhill, the fixed point is lower still
+    start = likelihood.minus2lnL(p, d)[0][0]
+    assert likelihood.minus2lnL(p, d, cl=cl)[0][0] < start
+
+
+def test_first_iteration_is_the_single_step_estimate():
+    p = tiny_healpix("QU", nside=2, lmax=6, cut=0.3)
+    lo = np.array([2, 4]); hi = np.array([3, 6])
+    spectra = ("EE", "BB", "EB")
+    d = _data(p, 72)
+    one = qml.qml_harmonic(p, spectra, lo, hi, d[None, :])["chat"][0]
+    chat, _, it = qml.iterate(p, spectra, lo, hi, d, max_iter=1)
+    assert it == 1
+    np.testing.assert_array_equal(chat, one)
+
+
+def test_band_projection_is_psd_and_idempotent_on_psd_spectra():
+    p = tiny_healpix("TQU", nside=2, lmax=6, cut=0.3)
+    lo = np.array([2, 5]); hi = np.array([4, 6])
+    spectra = ("TT", "EE", "BB", "TE", "TB", "EB")
+    rng = np.random.default_rng(73)
+    chat = rng.normal(0.0, 1.0, 12)                          # arbitrary, indefinite bands
+    new = qml.band_fiducial(p.cl, spectra, lo, hi, chat, p.fields)
+    for l in range(2, 7):
+        M = np.array([[new[0, l], new[3, l], new[4, l]], [new[3, l], new[1, l], new[5, l]],
+                      [new[4, l], new[5, l], new[2, l]]])
+        assert np.linalg.eigvalsh(M).min() > -1e-12 * max(1.0, np.abs(M).max())
+    again = qml.band_fiducial(new, (), lo[:0], hi[:0], np.zeros(0), p.fields)
+    np.testing.assert_allclose(again, new, rtol=0, atol=1e-12 * np.abs(new).max())
