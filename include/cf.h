@@ -159,6 +159,22 @@ int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t npoints,
                      int32_t nmaps, int32_t precision, double* m2lnL, double* chi2,
                      double* logdet, const cf_exec* ex, cf_report* rep);
 
+/* Iterative QML for one map (Sects. 2.2 and 2.6: the single-step estimate is one Newton step towards
+ * the maximum of the pixel likelihood; the paper describes the iteration as re-entering the QML with
+ * the previous estimates in place of the fiducial).  Iteration i runs the FP64 QML of cf_qml with
+ * fiducial C^(i) (C^(0) = prob->cl); C^(i+1) takes every estimated band as a flat band over its
+ * multipoles, and at every multipole the spectrum matrix over the problem's harmonic fields is
+ * replaced by its nearest positive semi-definite matrix (negative eigenvalues set to zero).  Stops
+ * at the first iteration whose estimates moved by less than tol Fisher errors sqrt((F^-1)_bb) from
+ * the previous ones.
+ *   map: [n] in prob->mem;  chat_out [ns*nb] and F_out [(ns*nb)^2] (nullable, F at the last
+ *   fiducial) in prob->mem;  cl_out [6][lmax+1] host (nullable): the last fiducial;  iters_out
+ *   host (nullable).
+ * CF_ENOCONV (outputs untouched) if max_iter iterations do not settle; the errors of cf_qml. */
+int cf_qml_iterate(const cf_problem* prob, const cf_bins* bins, const double* map, int32_t max_iter,
+                   double tol, double* chat_out, double* F_out, double* cl_out, int32_t* iters_out,
+                   const cf_exec* ex, cf_report* rep);
+
 /* Decorrelated normalisation (Sect. 2.5, Eq. decorrelated): out[v] = F^-1/2 q[v] with
  * F^-1/2 = U Xi^-1/2 U^T from the eigendecomposition F = U Xi U^T (cyclic Jacobi in FP64), the
  * eigenvalues below 1e-12 of the largest set to zero.  F: [K][K], only its lower triangle is read;

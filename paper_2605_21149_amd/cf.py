@@ -65,7 +65,7 @@ EXPORTS = ("cf_problem_dim", "cf_problem_nmodes", "cf_cov_build", "cf_fisher", "
            "cf_loglike_batch", "cf_emu_create", "cf_emu_destroy", "cf_emu_param_count", "cf_emu_shape",
            "cf_emu_train", "cf_emu_predict", "cf_emu_get_params", "cf_emu_set_params",
            "cf_emu_forward", "cf_emu_gradient", "cf_emu_adam", "cf_emu_save", "cf_emu_load",
-           "cf_smw_create", "cf_smw_loglike", "cf_smw_dim", "cf_smw_destroy", "cf_decorrelate", "cf_qml_cross",
+           "cf_smw_create", "cf_smw_loglike", "cf_smw_dim", "cf_smw_destroy", "cf_decorrelate", "cf_qml_iterate", "cf_qml_cross",
            "cf_last_error", "cf_version")
 
 
@@ -147,6 +147,9 @@ def lib():
                                    C.c_int32, _dp, _dp, _dp, C.POINTER(cf_exec), C.POINTER(cf_report)]
         L.cf_decorrelate.argtypes = [_dp, C.c_int32, _dp, C.c_int32, C.c_int32, _dp, _dp,
                                      C.POINTER(cf_exec), C.POINTER(cf_report)]
+        L.cf_qml_iterate.argtypes = [C.POINTER(cf_problem), C.POINTER(cf_bins), _dp, C.c_int32, C.c_double,
+                                     _dp, _dp, _dp, C.POINTER(C.c_int32), C.POINTER(cf_exec),
+                                     C.POINTER(cf_report)]
         L.cf_smw_dim.argtypes = [C.c_void_p]
         L.cf_smw_dim.restype = C.c_int64
         L.cf_smw_destroy.argtypes = [C.c_void_p]
@@ -154,7 +157,8 @@ def lib():
         for name in ("cf_cov_build", "cf_fisher", "cf_qml", "cf_loglike_batch", "cf_emu_create",
                      "cf_emu_train", "cf_emu_predict", "cf_emu_get_params", "cf_emu_set_params",
                      "cf_emu_forward", "cf_emu_gradient", "cf_emu_adam", "cf_emu_save",
-                     "cf_emu_load", "cf_smw_create", "cf_smw_loglike", "cf_decorrelate", "cf_qml_cross"):
+                     "cf_emu_load", "cf_smw_create", "cf_smw_loglike", "cf_decorrelate", "cf_qml_cross",
+                     "cf_qml_iterate"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -398,6 +402,30 @@ def loglike_batch(problems: Sequence, cl_points, maps: Sequence, precision=CF_FP
 
 
 # ------------------------------------------------------------------------------ emulator
+def qml_iterate(p, bins, data, max_iter=20, tol=1e-6, device=False, report=False, packed=None):
+    """Iterative QML of one map [n]: dict(chat [K], F [K][K] at the last fiducial, cl [6][lmax+1]
+    (host) the last fiducial, iterations)."""
+    pk = packed or pack_problem(p, device)
+    bs, keep = pack_bins(bins)
+    K = len(bins.spectra) * bs.nbins
+    if device:
+        import torch
+        d = data if _is_torch(data) else torch.as_tensor(np.ascontiguousarray(data, np.float64))
+        d = d.to("cuda", torch.float64).contiguous().reshape(-1)
+    else:
+        d = np.ascontiguousarray(_host(data).reshape(-1))
+    chat, F = _alloc((K,), device), _alloc((K, K), device)
+    cl = np.zeros((6, p.lmax + 1))
+    iters = C.c_int32(0)
+    rep = cf_report()
+    ex = _exec(_torch_stream() if device else None)
+    st = lib().cf_qml_iterate(C.byref(pk.struct), C.byref(bs), _ptr(d), int(max_iter), C.c_double(tol),
+                              _ptr(chat), _ptr(F), _ptr(cl), C.byref(iters), C.byref(ex), C.byref(rep))
+    _check(st, rep)
+    out = {"chat": chat, "F": F, "cl": cl, "iterations": int(iters.value)}
+    return (out, rep.as_dict()) if report else out
+
+
 def decorrelate(F, q=None, device=False, report=False):
     """Decorrelated estimates F^-1/2 q (Eq. decorrelated) for each row of q, and F^-1/2 itself.
     Returns (out [nvec][K] or None, Fmhalf [K][K])."""

@@ -1980,3 +1980,182 @@ extern "C" int cf_qml_cross(const cf_problem* prob1, const cf_problem* prob2, co
   if (rep) { rep->n = H1.n; rep->nmodes = H1.k; rep->flops = 2.0 * fisher_flops(H1); }
   return CF_OK;
 }
+
+namespace cf {
+namespace {
+// Nearest positive semi-definite matrix (Frobenius) of a symmetric m x m matrix, m <= 3: cyclic
+// Jacobi eigendecomposition, negative eigenvalues set to zero; left as it is when none is negative.
+void psd_project(double A[3][3], int m) {
+  double a[3][3], v[3][3];
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      a[i][j] = A[i][j];
+      v[i][j] = i == j ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int i = 0; i < m; ++i) {
+      dia += a[i][i] * a[i][i];
+      for (int j = i + 1; j < m; ++j) off += a[i][j] * a[i][j];
+    }
+    if (off <= 1e-34 * dia || off == 0.0) break;
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        if (a[p][q] == 0.0) continue;
+        const double tau = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+        for (int k = 0; k < m; ++k) {   // columns p, q
+          const double x = a[k][p], y = a[k][q];
+          a[k][p] = c * x - s * y;
+          a[k][q] = s * x + c * y;
+        }
+        for (int k = 0; k < m; ++k) {   // rows p, q
+          const double x = a[p][k], y = a[q][k];
+          a[p][k] = c * x - s * y;
+          a[q][k] = s * x + c * y;
+        }
+        for (int k = 0; k < m; ++k) {
+          const double x = v[k][p], y = v[k][q];
+          v[k][p] = c * x - s * y;
+          v[k][q] = s * x + c * y;
+        }
+      }
+  }
+  bool neg = false;
+  for (int i = 0; i < m; ++i) neg = neg || a[i][i] < 0.0;
+  if (!neg) return;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < m; ++k) s += v[i][k] * std::fmax(a[k][k], 0.0) * v[j][k];
+      A[i][j] = s;
+    }
+}
+
+// Next fiducial of iterative QML: every estimated band as a flat band over its multipoles, then the
+// spectrum matrix over the harmonic fields at every multipole projected onto the positive
+// semi-definite matrices.  cl: [6][L] in TT, EE, BB, TE, TB, EB order.
+void band_fiducial(std::vector<double>& cl, int L, const HostBins& B, const HostProblem& H,
+                   const std::vector<double>& chat) {
+  for (int si = 0; si < B.ns; ++si)
+    for (int b = 0; b < B.nb; ++b)
+      for (int l = B.lo[b]; l <= B.hi[b]; ++l) cl[(size_t)B.spec[si] * L + l] = chat[(size_t)si * B.nb + b];
+  int fld[3], m = 0;          // harmonic fields T 0, E 1, B 2
+  if (H.has_t) fld[m++] = 0;
+  if (H.has_p) { fld[m++] = 1; fld[m++] = 2; }
+  auto row = [](int a, int b) {
+    if (a > b) { const int t = a; a = b; b = t; }
+    if (a == b) return a;
+    return a == 0 ? (b == 1 ? 3 : 4) : 5;
+  };
+  for (int l = 0; l < L; ++l) {
+    double M[3][3];
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) M[i][j] = cl[(size_t)row(fld[i], fld[j]) * L + l];
+    psd_project(M, m);
+    for (int i = 0; i < m; ++i)
+      for (int j = i; j < m; ++j) cl[(size_t)row(fld[i], fld[j]) * L + l] = M[i][j];
+  }
+}
+
+// sqrt((F^-1)_bb) for a symmetric positive definite K x K F (row-major), by Cholesky.
+bool fisher_errors(const std::vector<double>& F, int K, std::vector<double>& sig) {
+  std::vector<double> Lc((size_t)K * K, 0.0);
+  for (int j = 0; j < K; ++j) {
+    double d = F[(size_t)j * K + j];
+    for (int k = 0; k < j; ++k) d -= Lc[(size_t)j * K + k] * Lc[(size_t)j * K + k];
+    if (!(d > 0.0)) return false;
+    const double r = std::sqrt(d);
+    Lc[(size_t)j * K + j] = r;
+    for (int i = j + 1; i < K; ++i) {
+      double t = F[(size_t)i * K + j];
+      for (int k = 0; k < j; ++k) t -= Lc[(size_t)i * K + k] * Lc[(size_t)j * K + k];
+      Lc[(size_t)i * K + j] = t / r;
+    }
+  }
+  // (F^-1)_bb = |L^-1 e_b|^2
+  std::vector<double> x(K);
+  sig.assign(K, 0.0);
+  for (int b = 0; b < K; ++b) {
+    double s2 = 0.0;
+    for (int i = 0; i < K; ++i) {
+      double t = i == b ? 1.0 : 0.0;
+      for (int k = b; k < i; ++k) t -= Lc[(size_t)i * K + k] * x[k];
+      x[i] = i < b ? 0.0 : t / Lc[(size_t)i * K + i];
+      s2 += x[i] * x[i];
+    }
+    sig[b] = std::sqrt(s2);
+  }
+  return true;
+}
+
+struct DevArray {
+  double* p = nullptr;
+  ~DevArray() { if (p) (void)hipFree(p); }
+};
+}  // namespace
+}  // namespace cf
+
+extern "C" int cf_qml_iterate(const cf_problem* prob, const cf_bins* bins, const double* map, int32_t max_iter,
+                              double tol, double* chat_out, double* F_out, double* cl_out, int32_t* iters_out,
+                              const cf_exec* ex, cf_report* rep) {
+  report_init(rep);
+  HostProblem H;
+  if (int st = check_problem(prob, H, true)) return st;
+  HostBins B;
+  if (int st = check_bins(bins, H, B)) return st;
+  if (!map || !chat_out) return fail(CF_EINVAL, "map and chat_out are required");
+  if (max_iter < 1 || !(tol > 0.0) || !std::isfinite(tol)) return fail(CF_EINVAL, "max_iter=%d, tol=%g", max_iter, tol);
+  const int K = B.ns * B.nb, L = H.lmax + 1;
+  std::vector<double> cl(prob->cl, prob->cl + 6 * (size_t)L);
+  cf_problem P = *prob;
+  P.cl = cl.data();
+  const bool dev = prob->mem == CF_MEM_DEVICE;
+  std::vector<double> hbuf((size_t)3 * K + (size_t)K * K);
+  DevArray dbuf;
+  if (dev) CF_DEV(hipMalloc(&dbuf.p, sizeof(double) * hbuf.size()));
+  double* base = dev ? dbuf.p : hbuf.data();
+  double *y = base, *b = base + K, *c = base + 2 * K, *F = base + 3 * K;
+  std::vector<double> chat(K), prev(K), Fh((size_t)K * K), sig;
+  double flops = 0.0, ms = 0.0;
+  for (int it = 1; it <= max_iter; ++it) {
+    cf_report r;
+    if (int st = cf_qml(&P, bins, map, 1, CF_FP64, y, b, c, F, ex, &r)) {
+      if (rep) rep->fail_index = r.fail_index;
+      return st;
+    }
+    flops += r.flops;
+    ms += r.ms_total;
+    if (dev) {
+      CF_DEV(hipMemcpy(chat.data(), c, sizeof(double) * K, hipMemcpyDeviceToHost));
+      CF_DEV(hipMemcpy(Fh.data(), F, sizeof(double) * K * K, hipMemcpyDeviceToHost));
+    } else {
+      std::copy(c, c + K, chat.begin());
+      std::copy(F, F + (size_t)K * K, Fh.begin());
+    }
+    if (it > 1) {
+      if (!fisher_errors(Fh, K, sig)) return fail(CF_ENOTPD, "Fisher matrix not positive definite at iteration %d", it);
+      double worst = 0.0;
+      for (int k = 0; k < K; ++k) worst = std::fmax(worst, std::fabs(chat[k] - prev[k]) / sig[k]);
+      if (worst < tol) {
+        if (dev) {
+          CF_DEV(hipMemcpy(chat_out, c, sizeof(double) * K, hipMemcpyDeviceToDevice));
+          if (F_out) CF_DEV(hipMemcpy(F_out, F, sizeof(double) * K * K, hipMemcpyDeviceToDevice));
+        } else {
+          std::copy(chat.begin(), chat.end(), chat_out);
+          if (F_out) std::copy(Fh.begin(), Fh.end(), F_out);
+        }
+        if (cl_out) std::copy(cl.begin(), cl.end(), cl_out);
+        if (iters_out) *iters_out = it;
+        if (rep) { rep->n = H.n; rep->nmodes = H.k; rep->flops = flops; rep->ms_total = ms; rep->ir_iters = it; }
+        return CF_OK;
+      }
+    }
+    prev = chat;
+    band_fiducial(cl, L, B, H, chat);
+  }
+  if (rep) rep->ir_iters = max_iter;
+  return fail(CF_ENOCONV, "iterative QML did not settle within %d iterations (tolerance %g Fisher errors)",
+              max_iter, tol);
+}
