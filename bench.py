@@ -308,6 +308,41 @@ def qu_scan(cf, I, npoints=256, reps=3):
     return out
 
 
+def other_fishers(cf, I, reps=2):
+    """Fisher+QML of one map for the two other QML workloads, median device-synchronised wall time:
+    the spin-0 N_side 8 problem (n = 544, 23 unbinned multipoles; latency-bound) in FP64, and the
+    QU N_side 32 problem (n = 12288, 18424 modes, EE, BB, EB unbinned over l = 2..95, K = 282) in
+    FP64 and in the FP32 mixed path, with the mixed path's F error against FP64."""
+    import torch
+    out = {}
+    for name, p, spectra, precs in (
+            ("t_nside8", I.spin0_problem_nside8(), ("TT",), (cf.CF_FP64,)),
+            ("qu_nside32", I.qu_problem_nside32(), ("EE", "BB", "EB"), (cf.CF_FP64, cf.CF_MIXED_FP32))):
+        bins = I.uniform_bins(p.lmin, p.lmax, 1, spectra)
+        pk = cf.pack_problem(p, device=True)
+        d = torch.as_tensor(I.white_maps(p.n, 1, 302, rms=1.0)).cuda()
+        rec, ref = {"n": p.n, "K": len(spectra) * (p.lmax - p.lmin + 1)}, None
+        for prec in precs:
+            ts, res = [], None
+            for _ in range(reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = cf.qml(p, bins, d, precision=prec, device=True, packed=pk)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            key = "fp64_ms" if prec == cf.CF_FP64 else "fp32_ms"
+            rec[key] = 1e3 * float(np.median(ts[1:]))
+            F = res["F"].cpu().numpy()
+            if ref is None:
+                ref = F
+            else:
+                rec["fp32_err_F_relfro"] = float(np.linalg.norm(F - ref) / np.linalg.norm(ref))
+        out[name] = rec
+        del pk, d
+        torch.cuda.empty_cache()
+    return out
+
+
 def mixed_precision(cf, I, problem, bins, packed, d_maps_qml, d_cl, d_maps_scan, reps=3):
     """Fisher+QML and likelihood-batch times for FP64, FP32-MFMA and split-BF16x3 paths, with the
     errors of the mixed results against the FP64 path (F: relative Frobenius; y, b: in units of
@@ -451,6 +486,7 @@ def main():
                                                           d_maps_scan)
     extras = None if args.no_extras else qml_extras(cf, I, problem, bins, packed, d_maps_qml)
     scan_qu = None if args.no_extras else qu_scan(cf, I)
+    fishers = None if args.no_extras else other_fishers(cf, I)
     host_inputs = None if args.no_extras else host_input_step(cf, problem, bins, maps_qml, maps_scan,
                                                                  cl_points)
     smw = None
@@ -506,6 +542,7 @@ def main():
         "qml_extras": extras,
         "host_inputs": host_inputs,
         "qu_scan": scan_qu,
+        "other_fishers": fishers,
         "factorisation": factorisation,
         "roofline": {"bound": "mfma", "kernel": "k_gemm<128,128,false,true,1> FP64 (Z_EB,EB = G_EB^T G_EB)",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
