@@ -190,17 +190,19 @@ def cpu_baseline(problem, bins, cl_points, maps_qml, maps_scan):
                        f"extrapolated step {step:.1f} s (host BLAS threads {threads})")}
 
 
-def smw_section(cf, I, problem, packed, d_maps_scan, direct_m2, direct_pts_per_s, npoints=64, reps=3):
+def smw_section(cf, I, problem, packed, d_maps_scan, direct_m2, direct_pts_per_s, reps=3):
     """Harmonic-basis likelihood with multipole switching (cf_smw_*): the EE window l = 2..29 of the
     scan model, on all fields of the TQU problem (TE couples T and E) and on E alone for the QU
     N_side 16 scan problem.  Setup = N_eff factorisation with the maps' and the window's solves;
     the scan rate counts every point's K' build, factorisation and log det.  Accuracy: the largest
-    |d(-2 ln L)| against the direct pixel-space scan at the step's points."""
+    |d(-2 ln L)| against the direct pixel-space scan at the step's points.  Points per call: 64 for
+    the TQU window (2688 modes; the library's batches hold about 100 points), 512 for the E window
+    (896 modes; batches of 128), bounded samples of the scans' parameter box."""
     import torch
     out = {}
-    cases = [("tqu_nside16", problem, packed, d_maps_scan, "TEB"),
-             ("qu_nside16", I.qu_scan_problem(16), None, None, "E")]
-    for name, p, pk, d_maps, wf in cases:
+    cases = [("tqu_nside16", problem, packed, d_maps_scan, "TEB", 64),
+             ("qu_nside16", I.qu_scan_problem(16), None, None, "E", 512)]
+    for name, p, pk, d_maps, wf, npoints in cases:
         pk = pk or cf.pack_problem(p, device=True)
         if d_maps is None:
             d_maps = torch.as_tensor(I.white_maps(p.n, NMAPS_SCAN, 403, rms=3.0)).cuda()
