@@ -602,8 +602,10 @@ int fisher_core_fp64(const cf_problem* prob, const HostProblem& H, const Staged&
   if (split) { F.rows_early = n + nm + kT; F.p_early = H.npx; }
   if (int st = potrf_on(*cc.dev, F, f.scratch, s, s2, ev + 8)) return st;
   tm.mark(ST_POTRF);
-  // Z = G^T G, lower blocks.  The symmetric product of the largest field block is the separately
-  // named kernel instance (tag 1) whose launch the stage timer brackets on its own stream.
+  // Z = G^T G, lower blocks.  For T+QU problems the symmetric product of the E,B block is the
+  // separately named kernel instance (tag 1) whose launch the stage timer brackets on its own
+  // stream; other problems' Z products use the plain instance, so that profiles of a process that
+  // runs several problems see one shape under the tagged name.
   if (split) {
     // E,B rows (columns >= p0 only; aux[0]): against the T columns, then the E,B block
     CF_DEV(hipEventRecord(ev[E_L], s));
@@ -635,7 +637,7 @@ int fisher_core_fp64(const cf_problem* prob, const HostProblem& H, const Staged&
     g.M = k; g.N = k; g.K = n;
     g.A = Gt; g.lda = n; g.at = 0;
     g.B = Gt; g.ldb = n; g.bt = 1;
-    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1; g.tag = 1;
+    g.C = f.Z; g.ldc = k; g.alpha = 1.0; g.beta = 0.0; g.lower = 1; g.batch = 1;
     hipEvent_t tz = tm.open(s);
     CF_DEV(gemm_f64(g, s));
     tm.close(ST_SYRK, tz, s);
