@@ -67,3 +67,25 @@ def test_band_projection_is_psd_and_idempotent_on_psd_spectra():
         assert np.linalg.eigvalsh(M).min() > -1e-12 * max(1.0, np.abs(M).max())
     again = qml.band_fiducial(new, (), lo[:0], hi[:0], np.zeros(0), p.fields)
     np.testing.assert_allclose(again, new, rtol=0, atol=1e-12 * np.abs(new).max())
+
+
+def test_band_projection_for_t_and_qu_fields():
+    """T: a negative TT band becomes zero and a positive one is kept.  QU: the 2 x 2 (EE, EB; EB, BB)
+    matrix of an indefinite band becomes its positive part (closed form of the 2 x 2 case) and TT,
+    TE, TB rows stay untouched."""
+    lo = np.array([2, 4]); hi = np.array([3, 6])
+    p = tiny_healpix("T", nside=2, lmax=6, cut=0.3)
+    new = qml.band_fiducial(p.cl, ("TT",), lo, hi, np.array([-0.3, 0.7]), p.fields)
+    assert np.all(new[0, 2:4] == 0.0) and np.all(new[0, 4:7] == 0.7)
+    p = tiny_healpix("QU", nside=2, lmax=6, cut=0.3)
+    chat = np.array([1.0, 0.5, 0.25, 0.2, 0.9, 0.1])           # EE, BB, EB bands (2 bins each)
+    new = qml.band_fiducial(p.cl, ("EE", "BB", "EB"), lo, hi, chat, p.fields)
+    M = np.array([[1.0, 0.9], [0.9, 0.25]])                     # bin 0: EE 1, BB 0.25, EB 0.9
+    xi, U = np.linalg.eigh(M)
+    P = (U * np.maximum(xi, 0)[None, :]) @ U.T
+    for l in (2, 3):
+        np.testing.assert_allclose([new[1, l], new[2, l], new[5, l]], [P[0, 0], P[1, 1], P[0, 1]],
+                                   rtol=0, atol=1e-14)
+    for l in (4, 5, 6):                                          # bin 1 is positive definite: kept
+        np.testing.assert_array_equal([new[1, l], new[2, l], new[5, l]], [0.5, 0.2, 0.1])
+    np.testing.assert_array_equal(new[[0, 3, 4]], p.cl[[0, 3, 4]])
