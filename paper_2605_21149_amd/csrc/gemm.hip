@@ -3,8 +3,12 @@
 // Workgroup tile BM x BN, 4 waves in a 2 x 2 arrangement, each wave owning a (BM/2) x (BN/2)
 // sub-tile built from 16 x 16 blocks of v_mfma_f64_16x16x4.  K advances in slabs of 16 staged
 // through LDS (double-buffered: the next slab is fetched into registers while the current one
-// feeds the MFMAs).  Operands may be stored either way round (at/bt), so the same kernel serves
-// the Cholesky trailing update (A B^T), the triangular-solve updates (A B) and Z = G^T G (A^T B).
+// feeds the MFMAs, and each wave reads the fragments of the next k-step of four while the MFMAs of
+// the current one run).  Global loads are a per-slab scalar base plus a per-lane 32-bit offset
+// fixed for the whole loop and carry no bounds test: edge rows are clamped (they only feed outputs
+// that are never stored) and a partial slab, when BK does not divide K, is taken first with its
+// missing k read as zeros.  Operands may be stored either way round (at/bt), so the same kernel
+// serves the Cholesky trailing update (A B^T), the triangular-solve updates (A B) and Z = G^T G.
 //
 // FP64 MFMA lane layout (measured on gfx950): lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // output register r of lane l is D[l/16 + 4r][l%16].
@@ -116,39 +120,82 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   double* C = g.C + z * g.sC;
   const int64_t M = g.M, N = g.N, K = g.K;
 
-  // Per-thread base pointers: every load of a slab is base + (uniform offset), so only one
-  // 64-bit address per operand stays live across the MFMA loop.
+  // Loads.  In the full slabs every load is unconditional: the address is a per-slab uniform
+  // base plus a per-lane 32-bit byte offset fixed for the whole loop, with rows (columns) past the
+  // matrix edge clamped to its last row (column) -- such rows only feed outputs that are never
+  // stored.  Only a trailing partial slab checks k against K and substitutes zeros.
   //   row-stored operand (k contiguous): thread covers row (tid / BK) + p * (256 / BK), column tid % BK
   //   transposed operand (i contiguous):  thread covers k-row (tid / BM) + p * (256 / BM), column tid % BM
   constexpr int RA = AT ? 256 / BM : 256 / BK;       // rows advanced per load step p
   constexpr int RB = BT ? 256 / BK : 256 / BN;
   const int a_r = AT ? tid / BM : tid / BK, a_c = AT ? tid % BM : tid % BK;
   const int b_r = BT ? tid / BK : tid / BN, b_c = BT ? tid % BK : tid % BN;
-  const double* pa = AT ? A + (int64_t)a_r * g.lda + i0 + a_c : A + (i0 + a_r) * g.lda + a_c;
-  const double* pb = BT ? B + (j0 + b_r) * g.ldb + b_c : B + (int64_t)b_r * g.ldb + j0 + b_c;
   const int64_t lda = g.lda, ldb = g.ldb;
+  uint32_t oa[LA], ob[LB];
+#pragma unroll
+  for (int p = 0; p < LA; ++p) {
+    if (AT) {
+      const int64_t i = i0 + a_c < M ? a_c : M - 1 - i0;
+      oa[p] = (uint32_t)(((int64_t)(a_r + p * RA) * lda + i) * 8);
+    } else {
+      const int64_t r = i0 + a_r + p * RA < M ? a_r + p * RA : M - 1 - i0;
+      oa[p] = (uint32_t)((r * lda + a_c) * 8);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < LB; ++p) {
+    if (BT) {
+      const int64_t r = j0 + b_r + p * RB < N ? b_r + p * RB : N - 1 - j0;
+      ob[p] = (uint32_t)((r * ldb + b_c) * 8);
+    } else {
+      const int64_t j = j0 + b_c < N ? b_c : N - 1 - j0;
+      ob[p] = (uint32_t)(((int64_t)(b_r + p * RB) * ldb + j) * 8);
+    }
+  }
+  // slab base: element (i0, k0) of op(A) and (k0, j0) of op(B)
+  auto base_a = [&](int64_t k0) { return (const char*)(AT ? A + k0 * lda + i0 : A + i0 * lda + k0); };
+  auto base_b = [&](int64_t k0) { return (const char*)(BT ? B + j0 * ldb + k0 : B + k0 * ldb + j0); };
 
   double ra[LA], rb[LB];
-  auto load = [&](int64_t k0) {
+  auto load_full = [&](int64_t k0) {
+    const char* pa = base_a(k0);
+    const char* pb = base_b(k0);
 #pragma unroll
     for (int p = 0; p < LA; ++p) {
-      if (AT) {   // element (i0 + a_c, k0 + a_r + p*RA)
-        const int64_t gk = k0 + a_r + p * RA;
-        ra[p] = (i0 + a_c < M && gk < K) ? pa[(k0 + p * RA) * lda] : 0.0;
-      } else {    // element (i0 + a_r + p*RA, k0 + a_c)
-        const int64_t gi = i0 + a_r + p * RA;
-        ra[p] = (gi < M && k0 + a_c < K) ? pa[(int64_t)p * RA * lda + k0] : 0.0;
-      }
+      uint32_t o = oa[p];
+      asm volatile("" : "+v"(o));   // keeps the 32-bit offset beside its use: scalar base + vector offset
+      ra[p] = *(const double*)(pa + o);
     }
 #pragma unroll
     for (int p = 0; p < LB; ++p) {
-      if (BT) {   // element (k0 + b_c, j0 + b_r + p*RB)
-        const int64_t gj = j0 + b_r + p * RB;
-        rb[p] = (gj < N && k0 + b_c < K) ? pb[(int64_t)p * RB * ldb + k0] : 0.0;
-      } else {    // element (k0 + b_r + p*RB, j0 + b_c)
-        const int64_t gk = k0 + b_r + p * RB;
-        rb[p] = (j0 + b_c < N && gk < K) ? pb[(k0 + p * RB) * ldb] : 0.0;
-      }
+      uint32_t o = ob[p];
+      asm volatile("" : "+v"(o));
+      rb[p] = *(const double*)(pb + o);
+    }
+  };
+  // When BK does not divide K, the first slab is the partial one: it covers k in [-off, BK - off)
+  // with off = (-K) mod BK, the k < 0 entries read k = 0 and are replaced by zero, and every later
+  // slab is full.  (With off = 0 the slabs are the plain [t BK, (t + 1) BK).)
+  const int off = (int)((BK - K % BK) % BK);
+  const int64_t nk = (K + off) / BK;
+  auto load_first = [&]() {
+    const char* pa = base_a(0);
+    const char* pb = base_b(0);
+#pragma unroll
+    for (int p = 0; p < LA; ++p) {
+      const int kk = AT ? a_r + p * RA : a_c;
+      const int kc = kk >= off ? kk - off : 0;   // the k this entry stands for, clamped at 0
+      const uint32_t o = oa[p] - (uint32_t)((kk - kc) * (AT ? lda : 1) * 8);
+      const double v = *(const double*)(pa + o);
+      ra[p] = kk >= off ? v : 0.0;
+    }
+#pragma unroll
+    for (int p = 0; p < LB; ++p) {
+      const int kk = BT ? b_c : b_r + p * RB;
+      const int kc = kk >= off ? kk - off : 0;
+      const uint32_t o = ob[p] - (uint32_t)((kk - kc) * (BT ? 1 : ldb) * 8);
+      const double v = *(const double*)(pb + o);
+      rb[p] = kk >= off ? v : 0.0;
     }
   };
   auto store = [&](int buf) {
@@ -163,40 +210,48 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
       Bs[buf][r * SB + b_c] = rb[p];
     }
   };
+  auto frag = [&](int buf, int kq, double* av, double* bv) {
+    const int kr = kq * 4 + (lane >> 4);
+#pragma unroll
+    for (int a = 0; a < MI; ++a) {
+      const int ii = wr * WM + a * 16 + (lane & 15);
+      av[a] = As[buf][AT ? kr * SA + ii : ii * SA + kr];
+    }
+#pragma unroll
+    for (int b = 0; b < NI; ++b) {
+      const int jj = wc * WN + b * 16 + (lane & 15);
+      bv[b] = Bs[buf][BT ? jj * SB + kr : kr * SB + jj];
+    }
+  };
 
   dbl4 acc[MI][NI];
 #pragma unroll
   for (int a = 0; a < MI; ++a)
 #pragma unroll
     for (int b = 0; b < NI; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+  auto mma = [&](const double* av, const double* bv) {
+#pragma unroll
+    for (int a = 0; a < MI; ++a)
+#pragma unroll
+      for (int b = 0; b < NI; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+  };
 
-  const int64_t nk = (K + BK - 1) / BK;
-  load(0);
+  load_first();
   store(0);
   __syncthreads();
   for (int64_t t = 0; t < nk; ++t) {
     const int cur = (int)(t & 1);
-    if (t + 1 < nk) load((t + 1) * BK);
-#pragma unroll
-    for (int kq = 0; kq < BK / 4; ++kq) {
-      const int kr = kq * 4 + (lane >> 4);
-      double av[MI], bv[NI];
-#pragma unroll
-      for (int a = 0; a < MI; ++a) {
-        const int ii = wr * WM + a * 16 + (lane & 15);
-        av[a] = As[cur][AT ? kr * SA + ii : ii * SA + kr];
-      }
-#pragma unroll
-      for (int b = 0; b < NI; ++b) {
-        const int jj = wc * WN + b * 16 + (lane & 15);
-        bv[b] = Bs[cur][BT ? jj * SB + kr : kr * SB + jj];
-      }
-#pragma unroll
-      for (int a = 0; a < MI; ++a)
-#pragma unroll
-        for (int b = 0; b < NI; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-    }
+    double fa0[MI], fb0[NI], fa1[MI], fb1[NI];
+    frag(cur, 0, fa0, fb0);
+    if (t + 1 < nk) load_full((t + 1) * BK - off);
+    frag(cur, 1, fa1, fb1);
+    mma(fa0, fb0);
+    frag(cur, 2, fa0, fb0);
+    mma(fa1, fb1);
+    frag(cur, 3, fa1, fb1);
+    mma(fa0, fb0);
+    mma(fa1, fb1);
     if (t + 1 < nk) store(cur ^ 1);
     __syncthreads();
   }
@@ -407,6 +462,9 @@ template <int BM, int BN, bool AT, bool BT>
 __global__ __launch_bounds__(256, 2) void k_gemm_lp2(GemmArgs g);
 template <int BM, int BN>
 hipError_t launch_tile(const GemmDesc& d, hipStream_t s) {
+  // The FP64 kernel addresses a slab as a scalar base plus a 32-bit byte offset per lane, which
+  // spans at most BM (or BK) rows of the leading dimension.
+  if (d.mode == 0 && (d.lda >= (int64_t(1) << 22) || d.ldb >= (int64_t(1) << 22))) return hipErrorInvalidValue;
   GemmArgs g;
   g.M = d.M; g.N = d.N; g.K = d.K;
   g.A = d.A; g.lda = d.lda; g.B = d.B; g.ldb = d.ldb; g.C = d.C; g.ldc = d.ldc;
