@@ -498,7 +498,7 @@ def main():
         smw = smw_section(cf, I, problem, packed, d_maps_scan, direct_m2,
                           SCAN_POINTS / (np.median(scan_ms) * 1e-3))
     # roofline kernel: the largest single launch of the step, the FP64 MFMA symmetric product
-    # forming the E,B x E,B block of Z = G^T G (k_gemm<128,128,false,true,1>), timed with HIP
+    # forming the E,B x E,B block of Z = G^T G (k_gemm<64,64,false,true,1>), timed with HIP
     # events on the stream it runs on.  Algorithmic flops: the lower triangle with the diagonal
     # (kP (kP+1) / 2 entries) over the rows from the first Q pixel (G's E,B columns vanish above).
     npx = problem.npix
@@ -507,7 +507,7 @@ def main():
     syrk_flops = kP * (kP + 1) * (n - p0)
     syrk_ms = stage[4]
     achieved = syrk_flops / (syrk_ms * 1e-3) / 1e12
-    traffic = _traffic("k_gemm<128,128,false,true,1>")
+    traffic = _traffic("k_gemm<64,64,false,true,1>")
     # whole factorisations against the same peak, algorithmic flops only: n^3/3 for the Cholesky and
     # m^2 per right-hand side solved over m rows (the E,B columns of Y vanish above the first Q
     # pixel, so they are solved over n - p0 rows; the T columns and the map over all n)
@@ -546,7 +546,7 @@ def main():
         "qu_scan": scan_qu,
         "other_fishers": fishers,
         "factorisation": factorisation,
-        "roofline": {"bound": "mfma", "kernel": "k_gemm<128,128,false,true,1> FP64 (Z_EB,EB = G_EB^T G_EB)",
+        "roofline": {"bound": "mfma", "kernel": "k_gemm<64,64,false,true,1> FP64 (Z_EB,EB = G_EB^T G_EB)",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic},
     }

@@ -515,13 +515,31 @@ hipError_t gemm_f64(const GemmDesc& d, hipStream_t s) {
   }
   if (d.tile == 128) return launch_tile<128, 128>(d, s);
   if (d.tile == 64) return launch_tile<64, 64>(d, s);
-  // 128 x 128 tiles only for long contractions over enough tiles to fill the chip.  Measured on
-  // rank-256 and rank-512 updates (the factorisation's trailing and solve-row updates, single and
-  // batched): 64 x 64 tiles are faster there at every size, the shorter workgroups balancing better
-  // and leaving slots free sooner for the kernels of the critical chain.
+  // Contractions of at most 512 (the factorisation's trailing, lookahead and solve-row updates,
+  // single and batched) run in 64 x 64 tiles: measured faster there at every size, the shorter
+  // workgroups balancing better and leaving slots free sooner for the critical chain.
+  if (d.K <= 512) return launch_tile<64, 64>(d, s);
+  // Longer ones: the tile whose launch needs fewer rounds of resident workgroups (two 128 x 128 or
+  // four 64 x 64 per CU), a round of 128 x 128 tiles costing about 1.86 rounds of 64 x 64 ones
+  // (measured on full rounds of a 6900 x 6900 lower product, K = 5952).  Partial last rounds
+  // dominate otherwise: 666 tiles of 128 (a 4600-row lower product) take two rounds of 512 slots.
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
   const int64_t batch = d.batch > 0 ? d.batch : 1;
-  const int64_t big = ((d.M + 127) / 128) * ((d.N + 127) / 128) * batch;
-  if (big >= 480 && d.K > 512) return launch_tile<128, 128>(d, s);
+  auto tiles = [&](int64_t T) {
+    const int64_t tm = (d.M + T - 1) / T, tn = (d.N + T - 1) / T;
+    if (!d.lower) return tm * tn;
+    int64_t t = 0;
+    for (int64_t r = 0; r < tm; ++r) {   // tiles with j0 < i0 + diag_off + T
+      const int64_t x = r * T + d.diag_off + T;
+      const int64_t c = x <= 0 ? 0 : (x + T - 1) / T;
+      t += c < tn ? c : tn;
+    }
+    return t;
+  };
+  const int64_t r128 = (tiles(128) * batch + 2 * cus - 1) / (2 * cus);
+  const int64_t r64 = (tiles(64) * batch + 4 * cus - 1) / (4 * cus);
+  if (1.86 * (double)r128 < (double)r64) return launch_tile<128, 128>(d, s);
   return launch_tile<64, 64>(d, s);
 }
 
