@@ -317,31 +317,69 @@ __device__ __forceinline__ void k_gemm_lp_body(GemmArgs g) {
   constexpr int RB = BT ? 256 / BK : 256 / BN;
   const int a_r = AT ? tid / BM : tid / BK, a_c = AT ? tid % BM : tid % BK;
   const int b_r = BT ? tid / BK : tid / BN, b_c = BT ? tid % BK : tid % BN;
-  const double* pa = AT ? A + (int64_t)a_r * g.lda + i0 + a_c : A + (i0 + a_r) * g.lda + a_c;
-  const double* pb = BT ? B + (j0 + b_r) * g.ldb + b_c : B + (int64_t)b_r * g.ldb + j0 + b_c;
   const int64_t lda = g.lda, ldb = g.ldb;
-
+  // Loads as in the FP64 kernel: scalar slab base + per-lane 32-bit offset, edge rows clamped, the
+  // partial slab (when BK does not divide K) first with its missing k read as zeros.
+  uint32_t oa[LA], ob[LB];
+#pragma unroll
+  for (int p = 0; p < LA; ++p) {
+    if (AT) {
+      const int64_t i = i0 + a_c < M ? a_c : M - 1 - i0;
+      oa[p] = (uint32_t)(((int64_t)(a_r + p * RA) * lda + i) * 8);
+    } else {
+      const int64_t r = i0 + a_r + p * RA < M ? a_r + p * RA : M - 1 - i0;
+      oa[p] = (uint32_t)((r * lda + a_c) * 8);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < LB; ++p) {
+    if (BT) {
+      const int64_t r = j0 + b_r + p * RB < N ? b_r + p * RB : N - 1 - j0;
+      ob[p] = (uint32_t)((r * ldb + b_c) * 8);
+    } else {
+      const int64_t j = j0 + b_c < N ? b_c : N - 1 - j0;
+      ob[p] = (uint32_t)(((int64_t)(b_r + p * RB) * ldb + j) * 8);
+    }
+  }
+  auto base_a = [&](int64_t k0) { return (const char*)(AT ? A + k0 * lda + i0 : A + i0 * lda + k0); };
+  auto base_b = [&](int64_t k0) { return (const char*)(BT ? B + j0 * ldb + k0 : B + k0 * ldb + j0); };
   double ra[LA], rb[LB];
-  auto load = [&](int64_t k0) {
+  auto load_full = [&](int64_t k0) {
+    const char* pa = base_a(k0);
+    const char* pb = base_b(k0);
 #pragma unroll
     for (int p = 0; p < LA; ++p) {
-      if (AT) {
-        const int64_t gk = k0 + a_r + p * RA;
-        ra[p] = (i0 + a_c < M && gk < K) ? pa[(k0 + p * RA) * lda] : 0.0;
-      } else {
-        const int64_t gi = i0 + a_r + p * RA;
-        ra[p] = (gi < M && k0 + a_c < K) ? pa[(int64_t)p * RA * lda + k0] : 0.0;
-      }
+      uint32_t o = oa[p];
+      asm volatile("" : "+v"(o));
+      ra[p] = *(const double*)(pa + o);
     }
 #pragma unroll
     for (int p = 0; p < LB; ++p) {
-      if (BT) {
-        const int64_t gj = j0 + b_r + p * RB;
-        rb[p] = (gj < N && k0 + b_c < K) ? pb[(int64_t)p * RB * ldb + k0] : 0.0;
-      } else {
-        const int64_t gk = k0 + b_r + p * RB;
-        rb[p] = (j0 + b_c < N && gk < K) ? pb[(k0 + p * RB) * ldb] : 0.0;
-      }
+      uint32_t o = ob[p];
+      asm volatile("" : "+v"(o));
+      rb[p] = *(const double*)(pb + o);
+    }
+  };
+  const int off = (int)((BK - K % BK) % BK);
+  const int64_t nk = (K + off) / BK;
+  auto load_first = [&]() {
+    const char* pa = base_a(0);
+    const char* pb = base_b(0);
+#pragma unroll
+    for (int p = 0; p < LA; ++p) {
+      const int kk = AT ? a_r + p * RA : a_c;
+      const int kc = kk >= off ? kk - off : 0;
+      const uint32_t o = oa[p] - (uint32_t)((kk - kc) * (AT ? lda : 1) * 8);
+      const double v = *(const double*)(pa + o);
+      ra[p] = kk >= off ? v : 0.0;
+    }
+#pragma unroll
+    for (int p = 0; p < LB; ++p) {
+      const int kk = BT ? b_c : b_r + p * RB;
+      const int kc = kk >= off ? kk - off : 0;
+      const uint32_t o = ob[p] - (uint32_t)((kk - kc) * (BT ? 1 : ldb) * 8);
+      const double v = *(const double*)(pb + o);
+      rb[p] = kk >= off ? v : 0.0;
     }
   };
   auto store = [&](int buf) {
@@ -380,13 +418,12 @@ __device__ __forceinline__ void k_gemm_lp_body(GemmArgs g) {
 #pragma unroll
     for (int b = 0; b < NI; ++b) acc[a][b] = flt4{0.f, 0.f, 0.f, 0.f};
 
-  const int64_t nk = (K + BK - 1) / BK;
-  load(0);
+  load_first();
   store(0);
   __syncthreads();
   for (int64_t t = 0; t < nk; ++t) {
     const int cur = (int)(t & 1);
-    if (t + 1 < nk) load((t + 1) * BK);
+    if (t + 1 < nk) load_full((t + 1) * BK - off);
     if (MODE == 2) {
       const int kb = 8 * (lane >> 4);
       bf16x8 ah[MI], al[MI], bh[NI], bl[NI];
@@ -462,9 +499,9 @@ template <int BM, int BN, bool AT, bool BT>
 __global__ __launch_bounds__(256, 2) void k_gemm_lp2(GemmArgs g);
 template <int BM, int BN>
 hipError_t launch_tile(const GemmDesc& d, hipStream_t s) {
-  // The FP64 kernel addresses a slab as a scalar base plus a 32-bit byte offset per lane, which
-  // spans at most BM (or BK) rows of the leading dimension.
-  if (d.mode == 0 && (d.lda >= (int64_t(1) << 22) || d.ldb >= (int64_t(1) << 22))) return hipErrorInvalidValue;
+  // The kernels address a slab as a scalar base plus a 32-bit byte offset per lane, which spans at
+  // most BM (or BK) rows of the leading dimension.
+  if (d.lda >= (int64_t(1) << 22) || d.ldb >= (int64_t(1) << 22)) return hipErrorInvalidValue;
   GemmArgs g;
   g.M = d.M; g.N = d.N; g.K = d.K;
   g.A = d.A; g.lda = d.lda; g.B = d.B; g.ldb = d.ldb; g.C = d.C; g.ldc = d.ldc;
