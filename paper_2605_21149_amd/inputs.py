@@ -232,8 +232,9 @@ def qu_problem_nside32(seed_mask: int = 301) -> Problem:
 
 
 def qu_scan_problem(nside: int) -> Problem:
-    """QU likelihood-scan problems: N_side 8 (C1 geometry and beam, white noise 1 + 1e-2)
-    or N_side 16 (C2 mask and beam, noise 2 I + U U^T on Q,U)."""
+    """QU likelihood-scan problems: N_side 8 (the spin-0 N_side 8 problem's cut and beam, white
+    noise 1 + 1e-2) or N_side 16 (the TQU N_side 16 problem's cut and beam, noise 2 I + U U^T on
+    Q,U)."""
     if nside == 8:
         lmax, cut, fwhm = 24, 15.0, 440.0
     elif nside == 16:

@@ -32,15 +32,12 @@ def _cf():
     return cf
 
 
-@pytest.mark.timeout(900)
-def test_qml_tqu_nside16_full():
-    """n = 5952, 6900 modes, 6 spectra x 12 bins, dense noise: F, y, bias and C_hat in full."""
+def _qml_full(p, seed, label):
     cf = _cf()
-    p = I.tqu_problem_nside16(dense_noise=True)
     bins = I.uniform_bins(2, 47, 4, I.SPEC_NAMES)
-    say("qml tqu nside16 full: oracle ...")
+    say(f"qml {label}: oracle ...")
     C = cv.total_covariance(p)
-    maps = (np.linalg.cholesky(C) @ np.random.default_rng(202).standard_normal(p.n))[None, :]
+    maps = (np.linalg.cholesky(C) @ np.random.default_rng(seed).standard_normal(p.n))[None, :]
     ref = qml.qml_harmonic(p, bins.spectra, bins.lo, bins.hi, maps, C)
     say("  GPU ...")
     got = {k: to_np(v) for k, v in cf.qml(p, bins, maps, device=True).items()}
@@ -51,6 +48,30 @@ def test_qml_tqu_nside16_full():
     say("  metrics", m)
     assert all(v < TOL for v in m.values()), m
     assert np.array_equal(got["F"], got["F"].T)
+
+
+@pytest.mark.timeout(900)
+def test_qml_tqu_nside16_full():
+    """n = 5952, 6900 modes, 6 spectra x 12 bins, dense noise: F, y, bias and C_hat in full."""
+    _qml_full(I.tqu_problem_nside16(dense_noise=True), 202, "tqu nside16 full")
+
+
+@pytest.mark.timeout(900)
+def test_qml_tqu_nside16_ragged_cap_full():
+    """The same spectra, beam and noise model on a seeded spherical cap of 1845 pixels: n = 5535,
+    so every contraction over pixels (K = n, and n - p0 for the E,B rows) ends 15 short of a
+    multiple of 16 and the factorisation's last 64-block is ragged.  F, y, bias, C_hat in full."""
+    base = I.tqu_problem_nside16(dense_noise=False)
+    rng = np.random.default_rng(611)
+    v = rng.standard_normal(3)
+    v /= np.linalg.norm(v)
+    mask = (I._ring_vectors(16) @ v > -0.2).astype(np.uint8)
+    p = I.Problem("tqu_nside16_cap", "TQU", base.lmin, base.lmax, base.cl, base.bl, base.pl, 16, mask)
+    p.noise_diag = np.full(p.n, 2.0)
+    p.noise_U = I.smooth_modes(16, mask, 3, 20, 612)
+    p.noise_dense = p.noise_matrix()
+    assert p.n == 5535 and p.n % 16 == 15
+    _qml_full(p, 613, "tqu nside16 ragged cap")
 
 
 @pytest.mark.timeout(900)
