@@ -371,9 +371,10 @@ def qml_cross(p1, p2, bins, maps1, maps2, device=False, stage_timing=False, repo
 
 
 def loglike_batch(problems: Sequence, cl_points, maps: Sequence, precision=CF_FP64, device=False,
-                  stage_timing=False, report=False, packed=None, no_graph=False, autotune=False):
+                  stage_timing=False, report=False, packed=None, no_graph=False, autotune=False, out=None):
     """-2 ln L over a scan.  cl_points [npoints][nprob][6][lstride]; maps[p] [nmaps][n_p].
-    Returns dict(m2lnL [npoints][nprob][nmaps], chi2 (same), logdet [npoints][nprob])."""
+    Returns dict(m2lnL [npoints][nprob][nmaps], chi2 (same), logdet [npoints][nprob]); out: optional
+    caller-owned (m2lnL, chi2, logdet) arrays of those shapes to write into."""
     pks = packed or [pack_problem(p, device) for p in problems]
     nprob = len(pks)
     arr = (cf_problem * nprob)(*[pk.struct for pk in pks])
@@ -389,9 +390,13 @@ def loglike_batch(problems: Sequence, cl_points, maps: Sequence, precision=CF_FP
     assert clp.shape[1] == nprob and clp.shape[2] == 6
     nmaps = mps[0].shape[0]
     mptr = (_dp * nprob)(*[_ptr(m) for m in mps])
-    m2 = _alloc((npoints, nprob, nmaps), device)
-    x2 = _alloc((npoints, nprob, nmaps), device)
-    ld = _alloc((npoints, nprob), device)
+    if out is not None:
+        m2, x2, ld = out
+        assert tuple(m2.shape) == (npoints, nprob, nmaps) and tuple(ld.shape) == (npoints, nprob)
+    else:
+        m2 = _alloc((npoints, nprob, nmaps), device)
+        x2 = _alloc((npoints, nprob, nmaps), device)
+        ld = _alloc((npoints, nprob), device)
     rep = cf_report()
     ex = _exec(_torch_stream() if device else None, stage_timing, no_graph, autotune)
     st = lib().cf_loglike_batch(arr, nprob, npoints, _ptr(clp), lstride, mptr, nmaps, int(precision),

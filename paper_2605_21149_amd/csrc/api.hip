@@ -419,6 +419,10 @@ int potrf_on(Device& d, Factor& F, double* scratch, hipStream_t s, hipStream_t s
   return CF_OK;
 }
 
+// Releases every device object the library keeps between calls (defined with the scan graphs).
+void release_device_state();
+std::once_flag g_atexit_once;
+
 struct CallCtx {
   Device* dev = nullptr;
   hipStream_t s = nullptr;
@@ -427,6 +431,10 @@ struct CallCtx {
     int id = 0;
     CF_DEV(hipGetDevice(&id));
     if (id < 0 || id >= 64) return fail(CF_EDEVICE, "device id %d unsupported", id);
+    // Registered after the runtime is initialised, so it runs before the runtime's own teardown:
+    // graphs, streams (CU-masked ones included), events and memory go back while the runtime and
+    // any profiler attached to it are still whole.
+    std::call_once(g_atexit_once, [] { std::atexit(release_device_state); });
     dev = &g_dev[id];
     lock = std::unique_lock<std::mutex>(dev->mu);
     if (!dev->stream) {
@@ -1077,6 +1085,34 @@ struct ScanGraph {
 std::mutex g_graph_mu;
 std::vector<ScanGraph> g_graphs[64];
 
+void release_device_state() {
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  for (int id = 0; id < 64; ++id) {
+    Device& d = g_dev[id];
+    // a call still running on another thread at exit keeps its device's state (no deadlock)
+    std::unique_lock<std::mutex> dl(d.mu, std::try_to_lock);
+    if (!dl.owns_lock()) continue;
+    {
+      std::unique_lock<std::mutex> g(g_graph_mu, std::try_to_lock);
+      if (!g.owns_lock()) continue;
+      if (!g_graphs[id].empty() || d.stream) (void)hipSetDevice(id);
+      for (auto& e : g_graphs[id]) (void)hipGraphExecDestroy(e.exec);
+      g_graphs[id].clear();
+    }
+    if (!d.stream && !d.ws && !d.hflags) continue;
+    (void)hipSetDevice(id);
+    (void)hipDeviceSynchronize();
+    for (hipStream_t* st : {&d.stream, &d.aux[0], &d.aux[1], &d.crit, &d.bulk, &d.bulk2})
+      if (*st) { (void)hipStreamDestroy(*st); *st = nullptr; }
+    for (auto& e : d.ev) if (e) { (void)hipEventDestroy(e); e = nullptr; }
+    for (auto& e : d.ring) if (e) { (void)hipEventDestroy(e); e = nullptr; }
+    if (d.ws) { (void)hipFree(d.ws); d.ws = nullptr; d.cap = 0; }
+    if (d.hflags) { (void)hipHostFree(d.hflags); d.hflags = nullptr; }
+  }
+  if (cur >= 0) (void)hipSetDevice(cur);
+}
+
 // Autotuned launch shape of the scan per (n, nmaps, mode): points per batch, outer panel width
 // of the batched factorisation and GEMM tile of its updates; in memory and in a small text file
 // (one line per shape: "scan gfx950 n=.. nmaps=.. mode=.. batch=.. panel=.. tile=..").
@@ -1238,10 +1274,15 @@ int scan_batch(const ScanCtx& x, int64_t i0, int b, int64_t* i0p, Timer* tm) {
   return CF_OK;
 }
 
+// Everything a captured batch bakes into its kernel arguments: shapes, the problem's values passed
+// by value (multipole range, fields, pixel count, noise kind and rank) and every buffer address.
 std::string graph_key(const ScanCtx& x, int b, const char* ws) {
-  char buf[512];
-  snprintf(buf, sizeof buf, "%d|%lld|%d|%d|%d|%d|%d|%d|%d|%d|%zu|%p|%p|%p|%p|%p|%p|%p|%p|%p", x.p,
-           (long long)x.h->n, b, x.nmaps, x.mode, x.refine, x.lstride, x.nprob, x.panel, x.tile, x.layout,
+  char buf[640];
+  const HostProblem& h = *x.h;
+  snprintf(buf, sizeof buf,
+           "%d|%lld|%d|%d|%d|%d|%d|%d|%d|%d|%zu|l%d-%d|f%d%d|px%d|nk%d|nr%d|%p|%p|%p|%p|%p|%p|%p|%p|%p", x.p,
+           (long long)h.n, b, x.nmaps, x.mode, x.refine, x.lstride, x.nprob, x.panel, x.tile, x.layout,
+           h.lmin, h.lmax, h.has_t, h.has_p, h.npx, x.prob->noise_kind, x.prob->noise_rank,
            (const void*)ws,
            (const void*)x.cl_dev, (const void*)x.D, (const void*)x.m2, (const void*)x.chi2,
            (const void*)x.ld, (const void*)x.S->noise, (const void*)x.S->noise_U, (const void*)x.c->s);

@@ -255,6 +255,35 @@ def test_loglike_graph_replay_matches_eager():
     np.testing.assert_allclose(eager[:, 0], ref, rtol=TOL)
 
 
+def test_loglike_graph_key_tracks_problem_values():
+    """Calls on the same buffers, shapes and batch that differ only in values a captured batch bakes
+    into its kernel arguments (lmin 2 -> 3, then the noise's low-rank width 2 -> 1 behind the same
+    address) each match the oracle: none of them replays another's graph."""
+    import copy
+    import torch
+    p = tiny_healpix("QU", nside=4, lmax=9, cut=0.25, lowrank=2)
+    maps = _maps(p, cv.total_covariance(p), 3, 71)
+    clp = I.scan_spectra(I.scan_points(6, seed=72), p.cl)[:, None]
+    d_maps = torch.as_tensor(maps).cuda()
+    d_cl = torch.as_tensor(np.ascontiguousarray(clp)).cuda()
+    pk = cf.pack_problem(p, device=True)
+    out = (torch.empty((6, 1, 3), dtype=torch.float64, device="cuda"),
+           torch.empty((6, 1, 3), dtype=torch.float64, device="cuda"),
+           torch.empty((6, 1), dtype=torch.float64, device="cuda"))
+    U_flat = p.noise_U.reshape(-1)
+    for lmin, rank in ((2, 2), (3, 2), (3, 1), (2, 2)):
+        q = copy.copy(p)
+        q.lmin = lmin
+        q.noise_U = U_flat[:p.n * rank].reshape(p.n, rank)   # the first n*rank doubles of one buffer
+        pk.struct.lmin = lmin
+        pk.struct.noise_rank = rank
+        say(f"graph key: lmin {lmin}, noise rank {rank}")
+        cf.loglike_batch([q], d_cl, [d_maps], device=True, packed=[pk], out=out)
+        ref, ref_ld = likelihood.scan(q, maps, clp[:, 0])
+        np.testing.assert_allclose(to_np(out[0])[:, 0], ref, rtol=TOL)
+        np.testing.assert_allclose(to_np(out[2])[:, 0], ref_ld, rtol=TOL)
+
+
 def test_loglike_autotune_records_a_batch_size(tmp_path, monkeypatch):
     monkeypatch.setenv("CF_TUNE_CACHE", str(tmp_path / "tune.txt"))
     p = tiny_healpix("QU", nside=2, lmax=6, cut=0.2, lowrank=1)

@@ -19,6 +19,10 @@ from gpu_common import say, to_np  # noqa: E402
 from oracle_cases import random_spectra, tiny_healpix  # noqa: E402
 
 pytestmark = pytest.mark.gpu
+# Full-size tolerance (relative, -2 ln L and ln|C|): the FP64 solves against N_eff carry relative
+# errors up to about n u kappa(N_eff) (n <= 5952, kappa about 1.2e4: 8e-9), and the data term's
+# subtraction d^T N_eff^-1 d - |L^-1 b'|^2 amplifies them by about 1.3 on these workloads.
+RTOL = 1e-8
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -99,7 +103,8 @@ def test_smw_rejects_coupled_window_and_indefinite_points():
 @pytest.mark.timeout(900)
 def test_smw_qu_nside16_scan_full_size():
     """The QU N_side 16 scan problem (n = 3968) with the EE window l = 2..29 (896 modes), 64 maps:
-    against the direct GPU scan on 8 points and the oracle's direct likelihood at one point."""
+    against the direct GPU scan on 8 points and the oracle's direct likelihood at one point, at 1e-8
+    relative."""
     cf = _cf()
     import torch
     say("smw: QU N_side 16, window [2, 29] E, 64 maps, 8 points")
@@ -113,20 +118,21 @@ def test_smw_qu_nside16_scan_full_size():
         got = {k: to_np(v) for k, v in h.loglike(d_pts).items()}
     ref = cf.loglike_batch([p], d_pts[:, None].contiguous(), [d_maps], device=True)
     ref = {k: to_np(v) for k, v in ref.items()}
-    d = np.abs(got["m2lnL"] - ref["m2lnL"][:, 0, :]).max()
-    say(f"  max |d(-2lnL)| vs direct GPU scan: {d:.3e}")
-    assert d <= 1e-3
-    assert np.abs(got["logdet"] - ref["logdet"][:, 0]).max() <= 1e-3
+    d = np.abs(got["m2lnL"] - ref["m2lnL"][:, 0, :]).max() / np.abs(ref["m2lnL"]).min()
+    say(f"  max rel |d(-2lnL)| vs direct GPU scan: {d:.3e}")
+    assert d <= RTOL
+    assert np.abs(got["logdet"] - ref["logdet"][:, 0]).max() <= RTOL * np.abs(ref["logdet"]).min()
     m2o, _, ldo = likelihood.minus2lnL(p, maps[:4], cl=pts[3])
-    say(f"  max |d(-2lnL)| vs oracle direct at point 3: {np.abs(got['m2lnL'][3, :4] - m2o).max():.3e}")
-    np.testing.assert_allclose(got["m2lnL"][3, :4], m2o, rtol=0, atol=1e-3)
-    np.testing.assert_allclose(got["logdet"][3], ldo, rtol=0, atol=1e-3)
+    say(f"  max rel |d(-2lnL)| vs oracle direct at point 3: {np.abs(got['m2lnL'][3, :4] / m2o - 1).max():.3e}")
+    np.testing.assert_allclose(got["m2lnL"][3, :4], m2o, rtol=RTOL, atol=0)
+    np.testing.assert_allclose(got["logdet"][3], ldo, rtol=RTOL, atol=0)
 
 
 @pytest.mark.timeout(900)
 def test_smw_tqu_nside16_all_fields_full_size():
     """The TQU N_side 16 problem of the bench (n = 5952), window l = 2..29 on T, E, B (2688 modes,
-    TE coupling T and E), 64 maps: against the direct GPU scan on 4 points."""
+    TE coupling T and E), 64 maps: against the direct GPU scan on 4 points at 1e-8 relative (the
+    oracle's SMW likelihood of this window is compared in the headline tests)."""
     cf = _cf()
     import torch
     say("smw: TQU N_side 16, window [2, 29] TEB, 64 maps, 4 points")
@@ -141,7 +147,7 @@ def test_smw_tqu_nside16_all_fields_full_size():
         got = {k: to_np(v) for k, v in h.loglike(d_pts).items()}
     ref = cf.loglike_batch([p], d_pts[:, None].contiguous(), [d_maps], device=True, packed=[pk])
     ref = {k: to_np(v) for k, v in ref.items()}
-    d = np.abs(got["m2lnL"] - ref["m2lnL"][:, 0, :]).max()
-    say(f"  max |d(-2lnL)| vs direct GPU scan: {d:.3e}")
-    assert d <= 1e-3
-    assert np.abs(got["logdet"] - ref["logdet"][:, 0]).max() <= 1e-3
+    d = np.abs(got["m2lnL"] - ref["m2lnL"][:, 0, :]).max() / np.abs(ref["m2lnL"]).min()
+    say(f"  max rel |d(-2lnL)| vs direct GPU scan: {d:.3e}")
+    assert d <= RTOL
+    assert np.abs(got["logdet"] - ref["logdet"][:, 0]).max() <= RTOL * np.abs(ref["logdet"]).min()

@@ -400,6 +400,48 @@ def test_mlp_adam_first_step_is_signed_lr():
         np.testing.assert_allclose(b - b1, 1e-3 * gb / (np.abs(gb) + 1e-8), rtol=1e-9)
 
 
+def test_mlp_adam_constant_gradient_closed_form():
+    """A constant gradient g over T steps: m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the bias
+    corrections give back exactly g and g^2 at every t and each step moves a parameter by
+    lr g / (|g| + eps): after T steps p_T = p_0 - T lr g / (|g| + eps)."""
+    from oracle import mlp
+    rng = np.random.default_rng(41)
+    params = mlp.init_params([3, 5, 1], rng)
+    grads = [(rng.standard_normal(W.shape), rng.standard_normal(b.shape)) for W, b in params]
+    m = [(np.zeros_like(W), np.zeros_like(b)) for W, b in params]
+    v = [(np.zeros_like(W), np.zeros_like(b)) for W, b in params]
+    p = params
+    lr, b1, b2, eps, T = 2e-3, 0.8, 0.95, 1e-8, 5
+    for t in range(1, T + 1):
+        p, m, v = mlp.adam_step(p, grads, m, v, t, lr, beta1=b1, beta2=b2, eps=eps)
+    for l, ((W0, b0), (gW, gb)) in enumerate(zip(params, grads)):
+        for P0, P, g, mm, vv in ((W0, p[l][0], gW, m[l][0], v[l][0]), (b0, p[l][1], gb, m[l][1], v[l][1])):
+            np.testing.assert_allclose(mm, (1 - b1 ** T) * g, rtol=1e-13, atol=0)
+            np.testing.assert_allclose(vv, (1 - b2 ** T) * g * g, rtol=1e-13, atol=0)
+            np.testing.assert_allclose(P0 - P, T * lr * g / (np.abs(g) + eps), rtol=1e-9, atol=1e-15)
+
+
+def test_mlp_adam_second_step_with_reversed_gradient():
+    """Gradients g then -g: m_2 = -(1 - b1)^2 g, whose bias correction 1 / (1 - b1^2) leaves
+    -(1 - b1) / (1 + b1) g, while v_2 = (1 - b2^2) g^2 corrects back to g^2.  The second step is
+    therefore lr (1 - b1) / (1 + b1) g / (|g| + eps) against the direction of the first."""
+    from oracle import mlp
+    rng = np.random.default_rng(42)
+    params = mlp.init_params([2, 3, 1], rng)
+    g1 = [(rng.standard_normal(W.shape), rng.standard_normal(b.shape)) for W, b in params]
+    g2 = [(-gW, -gb) for gW, gb in g1]
+    zeros = [(np.zeros_like(W), np.zeros_like(b)) for W, b in params]
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    p1, m1, v1 = mlp.adam_step(params, g1, zeros, zeros, 1, lr, beta1=b1, beta2=b2, eps=eps)
+    p2, m2, v2 = mlp.adam_step(p1, g2, m1, v1, 2, lr, beta1=b1, beta2=b2, eps=eps)
+    for l, (gW, gb) in enumerate(g1):
+        for k, g in ((0, gW), (1, gb)):
+            np.testing.assert_allclose(m2[l][k], -(1 - b1) ** 2 * g, rtol=1e-12, atol=1e-18)
+            np.testing.assert_allclose(v2[l][k], (1 - b2 ** 2) * g * g, rtol=1e-12, atol=0)
+            step = lr * (1 - b1) / (1 + b1) * g / (np.abs(g) + eps)
+            np.testing.assert_allclose(p2[l][k] - p1[l][k], step, rtol=1e-9, atol=1e-16)
+
+
 def test_bf16_rounding_matches_definition():
     from oracle import mlp
     x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 2.0 ** -9, 1.0 + 3 * 2.0 ** -9, -3.140625, 1e-3])

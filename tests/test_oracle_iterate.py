@@ -89,3 +89,33 @@ def test_band_projection_for_t_and_qu_fields():
     for l in (4, 5, 6):                                          # bin 1 is positive definite: kept
         np.testing.assert_array_equal([new[1, l], new[2, l], new[5, l]], [0.5, 0.2, 0.1])
     np.testing.assert_array_equal(new[[0, 3, 4]], p.cl[[0, 3, 4]])
+
+
+def test_band_projection_tqu_indefinite_band_closed_form():
+    """A TEB band built as U diag(2, 1, -1/2) U^T with the rational orthonormal basis
+    u1 = (2, 1, -2)/3, u2 = (2, -2, 1)/3, u3 = (1, 2, 2)/3: its nearest positive semi-definite
+    matrix is 2 u1 u1^T + u2 u2^T, i.e. the band plus u3 u3^T / 2, written entry by entry below in
+    ninths.  Every TT, EE, BB, TE, TB and EB entry of the projected band is checked one by one, the
+    other bin (positive definite) is left as given."""
+    p = tiny_healpix("TQU", nside=2, lmax=6, cut=0.3)
+    lo = np.array([2, 5]); hi = np.array([4, 6])
+    spectra = ("TT", "EE", "BB", "TE", "TB", "EB")
+    # M = 2 u1 u1^T + u2 u2^T - u3 u3^T / 2, in ninths: u_i u_i^T = (outer of the integer vectors) / 9
+    # u1 u1^T*9 = [[4,2,-4],[2,1,-2],[-4,-2,4]];  u2 u2^T*9 = [[4,-4,2],[-4,4,-2],[2,-2,1]]
+    # u3 u3^T*9 = [[1,2,2],[2,4,4],[2,4,4]]
+    # M*9 = [[8+4-0.5, 4-4-1, -8+2-1], [., 2+4-2, -4-2-2], [., ., 8+1-2]] = [[11.5,-1,-7],[-1,4,-8],[-7,-8,7]]
+    TT, EE, BB, TE, TB, EB = 11.5 / 9, 4 / 9, 7 / 9, -1 / 9, -7 / 9, -8 / 9
+    # P*9 = [[12,0,-6],[0,6,-6],[-6,-6,9]]
+    P = {"TT": 12 / 9, "EE": 6 / 9, "BB": 9 / 9, "TE": 0.0, "TB": -6 / 9, "EB": -6 / 9}
+    M = np.array([[TT, TE, TB], [TE, EE, EB], [TB, EB, BB]])
+    assert np.allclose(np.sort(np.linalg.eigvalsh(M)), [-0.5, 1.0, 2.0], atol=1e-14)
+    good = [3.0, 2.0, 1.0, 0.5, 0.1, 0.2]                      # bin 1: positive definite
+    chat = np.array([v for pair in zip([TT, EE, BB, TE, TB, EB], good) for v in pair])
+    new = qml.band_fiducial(p.cl, spectra, lo, hi, chat, p.fields)
+    row = {"TT": 0, "EE": 1, "BB": 2, "TE": 3, "TB": 4, "EB": 5}
+    for name, val in P.items():
+        for l in (2, 3, 4):
+            assert abs(new[row[name], l] - val) <= 1e-14, (name, l, new[row[name], l], val)
+    for k, name in enumerate(spectra):
+        for l in (5, 6):
+            assert new[row[name], l] == good[k], (name, l)
