@@ -159,6 +159,22 @@ int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t npoints,
                      int32_t nmaps, int32_t precision, double* m2lnL, double* chi2,
                      double* logdet, const cf_exec* ex, cf_report* rep);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): cf_loglike_batch with the same arguments, results and errors, that
+ * allocates nothing.  Its workspace is a static device array of 64 MiB per GPU (held from the
+ * library's first use on that GPU until the process ends); it creates no streams, events, graphs or
+ * pinned buffers and runs every launch eagerly, in order, on cf_exec.stream (NULL: the null
+ * stream), returning when the results are written.  It does not autotune (cf_exec.autotune,
+ * no_graph and stage_timing are ignored): the batch of points factorised together is the largest
+ * (at most 16) whose workspace fits the array.  CF_EINVAL when even one point does not fit (for
+ * FP64 with 64 maps, up to about n = 2600; host-memory problems also stage their inputs in it).
+ * Calls on one GPU share the array, which keeps the last call's contents; the library serialises
+ * calls per device and each returns after its work is done, so calls never overlap on it. */
+int cf_loglike_batch_noalloc(const cf_problem* probs, int32_t nprob, int32_t npoints,
+                             const double* cl_points, int32_t lstride, const double* const* maps,
+                             int32_t nmaps, int32_t precision, double* m2lnL, double* chi2,
+                             double* logdet, const cf_exec* ex, cf_report* rep);
+
 /* Iterative QML for one map (Sects. 2.2 and 2.6: the single-step estimate is one Newton step towards
  * the maximum of the pixel likelihood; the paper describes the iteration as re-entering the QML with
  * the previous estimates in place of the fiducial).  Iteration i runs the FP64 QML of cf_qml with

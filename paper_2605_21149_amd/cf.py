@@ -62,7 +62,7 @@ STAGES = ("build", "potrf", "ybuild", "trsm", "syrk", "reduce", "qml", "other")
 
 # Every symbol include/cf.h declares.
 EXPORTS = ("cf_problem_dim", "cf_problem_nmodes", "cf_cov_build", "cf_fisher", "cf_qml",
-           "cf_loglike_batch", "cf_emu_create", "cf_emu_destroy", "cf_emu_param_count", "cf_emu_shape",
+           "cf_loglike_batch", "cf_loglike_batch_noalloc", "cf_emu_create", "cf_emu_destroy", "cf_emu_param_count", "cf_emu_shape",
            "cf_emu_train", "cf_emu_predict", "cf_emu_get_params", "cf_emu_set_params",
            "cf_emu_forward", "cf_emu_gradient", "cf_emu_adam", "cf_emu_save", "cf_emu_load",
            "cf_smw_create", "cf_smw_loglike", "cf_smw_dim", "cf_smw_destroy", "cf_decorrelate", "cf_qml_iterate", "cf_qml_cross",
@@ -117,6 +117,7 @@ def lib():
         L.cf_loglike_batch.argtypes = [C.POINTER(cf_problem), C.c_int32, C.c_int32, _dp, C.c_int32,
                                        C.POINTER(_dp), C.c_int32, C.c_int32, _dp, _dp, _dp,
                                        C.POINTER(cf_exec), C.POINTER(cf_report)]
+        L.cf_loglike_batch_noalloc.argtypes = L.cf_loglike_batch.argtypes
         _fp = C.POINTER(C.c_float)
         L.cf_emu_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
                                     C.POINTER(C.c_void_p)]
@@ -154,7 +155,8 @@ def lib():
         L.cf_smw_dim.restype = C.c_int64
         L.cf_smw_destroy.argtypes = [C.c_void_p]
         L.cf_smw_destroy.restype = None
-        for name in ("cf_cov_build", "cf_fisher", "cf_qml", "cf_loglike_batch", "cf_emu_create",
+        for name in ("cf_cov_build", "cf_fisher", "cf_qml", "cf_loglike_batch", "cf_loglike_batch_noalloc",
+                     "cf_emu_create",
                      "cf_emu_train", "cf_emu_predict", "cf_emu_get_params", "cf_emu_set_params",
                      "cf_emu_forward", "cf_emu_gradient", "cf_emu_adam", "cf_emu_save",
                      "cf_emu_load", "cf_smw_create", "cf_smw_loglike", "cf_decorrelate", "cf_qml_cross",
@@ -371,10 +373,13 @@ def qml_cross(p1, p2, bins, maps1, maps2, device=False, stage_timing=False, repo
 
 
 def loglike_batch(problems: Sequence, cl_points, maps: Sequence, precision=CF_FP64, device=False,
-                  stage_timing=False, report=False, packed=None, no_graph=False, autotune=False, out=None):
+                  stage_timing=False, report=False, packed=None, no_graph=False, autotune=False, out=None,
+                  noalloc=False):
     """-2 ln L over a scan.  cl_points [npoints][nprob][6][lstride]; maps[p] [nmaps][n_p].
     Returns dict(m2lnL [npoints][nprob][nmaps], chi2 (same), logdet [npoints][nprob]); out: optional
-    caller-owned (m2lnL, chi2, logdet) arrays of those shapes to write into."""
+    caller-owned (m2lnL, chi2, logdet) arrays of those shapes to write into.  noalloc: call
+    cf_loglike_batch_noalloc (the library's static scratch array; nothing is allocated by the
+    library, the output arrays are the caller's or allocated here by the binding)."""
     pks = packed or [pack_problem(p, device) for p in problems]
     nprob = len(pks)
     arr = (cf_problem * nprob)(*[pk.struct for pk in pks])
@@ -399,8 +404,9 @@ def loglike_batch(problems: Sequence, cl_points, maps: Sequence, precision=CF_FP
         ld = _alloc((npoints, nprob), device)
     rep = cf_report()
     ex = _exec(_torch_stream() if device else None, stage_timing, no_graph, autotune)
-    st = lib().cf_loglike_batch(arr, nprob, npoints, _ptr(clp), lstride, mptr, nmaps, int(precision),
-                                _ptr(m2), _ptr(x2), _ptr(ld), C.byref(ex), C.byref(rep))
+    fn = lib().cf_loglike_batch_noalloc if noalloc else lib().cf_loglike_batch
+    st = fn(arr, nprob, npoints, _ptr(clp), lstride, mptr, nmaps, int(precision),
+            _ptr(m2), _ptr(x2), _ptr(ld), C.byref(ex), C.byref(rep))
     _check(st, rep)
     out = {"m2lnL": m2, "chi2": x2, "logdet": ld}
     return (out, rep.as_dict()) if report else out

@@ -14,6 +14,13 @@
 #include <string>
 #include <vector>
 
+// Workspace of the entry points that allocate nothing (cf_loglike_batch_noalloc): a file-scope
+// device array of kScratchBytes, one copy per GPU, held until the process ends.  Host code never
+// uses its name as an address (on the host it is only a stand-in): the device address comes from
+// hipGetSymbolAddress, once per device with that device current, and is kept per device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 namespace cf {
 namespace {
 
@@ -423,12 +430,34 @@ int potrf_on(Device& d, Factor& F, double* scratch, hipStream_t s, hipStream_t s
 void release_device_state();
 std::once_flag g_atexit_once;
 
+// Device addresses of the scratch array (declared at file scope above), one per device.
+char* g_scratch[64] = {};
+
 struct CallCtx {
   Device* dev = nullptr;
   hipStream_t s = nullptr;
+  int id = 0;
   std::unique_lock<std::mutex> lock;
+  // For the entry points that allocate nothing: the caller's stream (or the null stream), no
+  // library streams, events or pinned buffers; the scratch array's address is looked up on the
+  // first such call on the device.
+  int begin_plain(const cf_exec* ex) {
+    CF_DEV(hipGetDevice(&id));
+    if (id < 0 || id >= 64) return fail(CF_EDEVICE, "device id %d unsupported", id);
+    std::call_once(g_atexit_once, [] { std::atexit(release_device_state); });
+    dev = &g_dev[id];
+    lock = std::unique_lock<std::mutex>(dev->mu);
+    if (!g_scratch[id]) {
+      void* p = nullptr;
+      hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p)
+        return fail(CF_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+      g_scratch[id] = static_cast<char*>(p);
+    }
+    s = (ex && ex->stream) ? (hipStream_t)ex->stream : nullptr;
+    return CF_OK;
+  }
   int begin(const cf_exec* ex) {
-    int id = 0;
     CF_DEV(hipGetDevice(&id));
     if (id < 0 || id >= 64) return fail(CF_EDEVICE, "device id %d unsupported", id);
     // Registered after the runtime is initialised, so it runs before the runtime's own teardown:
@@ -454,6 +483,16 @@ void report_init(cf_report* rep) {
   if (!rep) return;
   std::memset(rep, 0, sizeof *rep);
   rep->fail_index = -1;
+}
+
+// The same through ordinary host memory (no pinned buffer), for the entry points that allocate nothing.
+int read_flags_plain(CallCtx& c, const int* dflags, int nflags, int* out) {
+  int tmp[8];
+  if (nflags > 8) return fail(CF_EINVAL, "internal: %d flags", nflags);
+  CF_DEV(hipMemcpyAsync(tmp, dflags, sizeof(int) * nflags, hipMemcpyDeviceToHost, c.s));
+  CF_DEV(hipStreamSynchronize(c.s));
+  for (int i = 0; i < nflags; ++i) out[i] = tmp[i];
+  return CF_OK;
 }
 
 // Copy back two device ints (cov flag, pivot failure) and turn them into a status.
@@ -1174,6 +1213,7 @@ struct ScanCtx {
   int* flags;
   double *m2, *chi2, *ld;
   size_t layout;                      // workspace layout signature (bytes carved)
+  bool one_stream = false;            // every launch on c->s, no library streams or events
 };
 
 // One batch of b points starting at i0 (or at *i0p when i0p is given).
@@ -1212,7 +1252,12 @@ int scan_batch(const ScanCtx& x, int64_t i0, int b, int64_t* i0p, Timer* tm) {
   F.fail = x.flags + 1; F.batch = b; F.mode = x.mode;
   F.panel = x.panel; F.tile = x.tile;
   if (!x.mode) F.rows = n + nmaps;
-  if (int st = potrf_on(*c.dev, F, x.pscr, c.s, c.dev->aux[1], c.dev->ev + 8)) return st;
+  if (x.one_stream) {
+    Streams st{c.s, c.s, c.s, nullptr, nullptr, nullptr, nullptr};
+    CF_DEV(potrf_f64(F, x.pscr, st));
+  } else if (int st = potrf_on(*c.dev, F, x.pscr, c.s, c.dev->aux[1], c.dev->ev + 8)) {
+    return st;
+  }
   if (tm) tm->mark(ST_POTRF);
   if (!x.mode) {   // chi^2_j = |u_j|^2 from the rows below C
     CF_DEV(launch_rowsumsq(x.Cb + n * n, nmaps, n, n, slot, b, x.x2, nmaps, c.s));
@@ -1327,10 +1372,16 @@ int scan_replay(ScanCtx& x, int64_t i0, int b, int64_t nb, int64_t* i0p) {
 }  // namespace
 }  // namespace cf
 
-extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t npoints,
-                                const double* cl_points, int32_t lstride, const double* const* maps,
-                                int32_t nmaps, int32_t precision, double* m2lnL, double* chi2,
-                                double* logdet, const cf_exec* ex, cf_report* rep) {
+namespace cf {
+namespace {
+
+// The scan of cf_loglike_batch.  noalloc: the workspace is the library's static device array
+// (no allocation of any kind), every launch goes eagerly onto the caller's stream (no library
+// streams, events or graphs, no autotuning), and the batch is the largest that fits that array.
+int loglike_core(const cf_problem* probs, int32_t nprob, int32_t npoints, const double* cl_points,
+                 int32_t lstride, const double* const* maps, int32_t nmaps, int32_t precision,
+                 double* m2lnL, double* chi2, double* logdet, const cf_exec* ex, cf_report* rep,
+                 bool noalloc) {
   report_init(rep);
   if (!probs || nprob <= 0) return fail(CF_EINVAL, "no problems");
   if (npoints <= 0 || !cl_points) return fail(CF_EINVAL, "no scan points");
@@ -1353,7 +1404,7 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   // host-paced two panels ahead (measured faster for n = 5952 batches of 8 than the replay).
   int nmax_all = 0;
   for (int p = 0; p < nprob; ++p) nmax_all = std::max(nmax_all, H[p].n);
-  const bool use_graph = !(ex && ex->no_graph) && !(ex && ex->stage_timing) && nmax_all < kGraphMaxN;
+  const bool use_graph = !noalloc && !(ex && ex->no_graph) && !(ex && ex->stage_timing) && nmax_all < kGraphMaxN;
   const size_t ncl = (size_t)npoints * nprob * 6 * lstride;
   if (mem == CF_MEM_HOST) {
     if (!finite_all(cl_points, (int64_t)ncl)) return fail(CF_EINVAL, "non-finite scan spectra");
@@ -1361,7 +1412,7 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
       if (!finite_all(maps[p], (int64_t)nmaps * H[p].n)) return fail(CF_EINVAL, "non-finite map value");
   }
   CallCtx c;
-  if (int st = c.begin(ex)) return st;
+  if (int st = noalloc ? c.begin_plain(ex) : c.begin(ex)) return st;
   int nmax = 0;
   for (int p = 0; p < nprob; ++p) nmax = H[p].n > nmax ? H[p].n : nmax;
   // batch of points factorised together: the autotuned size of this shape if known, else the
@@ -1370,43 +1421,61 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   const int bt_cap = (int)std::min<size_t>(16, std::max<size_t>(1, (size_t(6) << 30) / per));
   int Bt = bt_cap;
   TuneEntry tuned_e{};
-  const TuneEntry* tp = nprob == 1 ? tune_get(nmax, nmaps, mode) : nullptr;
+  const TuneEntry* tp = (nprob == 1 && !noalloc) ? tune_get(nmax, nmaps, mode) : nullptr;
   if (tp) tuned_e = *tp;                     // copied: tune_put may grow the table
   const bool tuned = tp != nullptr;
   if (tuned && tuned_e.bt > 0) Bt = std::min(tuned_e.bt, bt_cap);
   if (Bt > npoints) Bt = npoints;
   const int L = lmax_all + 1;
-  Sizer z;
-  for (int p = 0; p < nprob; ++p) size_staging(z, &probs[p], H[p]);
-  if (mem == CF_MEM_HOST) {
-    z.add<double>(ncl);
-    for (int p = 0; p < nprob; ++p) z.add<double>((size_t)nmaps * H[p].n);
-    z.add<double>((size_t)npoints * nprob * nmaps * 2 + (size_t)npoints * nprob);
+  // workspace bytes for batches of up to Bw points
+  auto ws_bytes = [&](int Bw) -> size_t {
+    Sizer z;
+    for (int p = 0; p < nprob; ++p) size_staging(z, &probs[p], H[p]);
+    if (mem == CF_MEM_HOST) {
+      z.add<double>(ncl);
+      for (int p = 0; p < nprob; ++p) z.add<double>((size_t)nmaps * H[p].n);
+      z.add<double>((size_t)npoints * nprob * nmaps * 2 + (size_t)npoints * nprob);
+    }
+    const size_t ncw = (size_t)(Bw + kCovIB - 1) / kCovIB * kCovIB * 6 * L;   // whole chunks
+    z.add<double>(ncw);
+    z.add<double>((size_t)Bw * (nmax + (mode ? 0 : nmaps)) * nmax);
+    z.add<double>((size_t)Bw * ((nmax + kNB - 1) / kNB) * kNB * kNB);
+    z.add<double>((size_t)Bw * (nmax / 256) * 256 * 256);
+    z.add<double>((size_t)potrf_scratch(Bw));
+    z.add<double>((size_t)Bw * ((nmax + kNB - 1) / kNB));
+    z.add<double>((size_t)nmax * nmaps);
+    z.add<double>((size_t)Bw * nmax * nmaps);
+    z.add<double>((size_t)Bw * nmax * nmaps);
+    z.add<double>(mode ? (size_t)Bw * nmax * nmax : 1);
+    z.add<double>(mode ? (size_t)Bw * nmax * nmaps : 1);
+    z.add<double>(mode ? (size_t)Bw * nmax * nmaps : 1);
+    z.add<double>(mode ? (size_t)Bw * nmax * kLdProbes : 1);
+    z.add<double>(mode ? (size_t)Bw * nmax * kLdProbes : 1);
+    z.add<double>(mode ? (size_t)Bw * kLdProbes : 1);
+    z.add<double>(mode ? (size_t)Bw * kLdProbes : 1);
+    z.add<double>((size_t)Bw * nmaps);
+    z.add<double>((size_t)Bw);
+    z.add<int64_t>(1);
+    z.add<int>(8);
+    return z.off;
+  };
+  int Bw = bt_cap;   // workspace sized for the largest batch the tuner may pick
+  char* wsbase = nullptr;
+  if (noalloc) {
+    Bw = std::min(bt_cap, (int)std::max<int64_t>(1, npoints));
+    while (Bw > 1 && ws_bytes(Bw) > kScratchBytes) --Bw;
+    const size_t need = ws_bytes(Bw);
+    if (need > kScratchBytes)
+      return fail(CF_EINVAL, "cf_loglike_batch_noalloc: %zu bytes of workspace needed for one point, above the "
+                  "%zu-byte static scratch array", need, kScratchBytes);
+    Bt = Bw;
+    wsbase = g_scratch[c.id];
+  } else {
+    if (int st = ensure_ws(*c.dev, ws_bytes(Bw))) return st;
+    wsbase = c.dev->ws;
   }
-  const int Bw = bt_cap;   // workspace sized for the largest batch the tuner may pick
   const size_t ncw = (size_t)(Bw + kCovIB - 1) / kCovIB * kCovIB * 6 * L;   // whole chunks
-  z.add<double>(ncw);
-  z.add<double>((size_t)Bw * (nmax + (mode ? 0 : nmaps)) * nmax);
-  z.add<double>((size_t)Bw * ((nmax + kNB - 1) / kNB) * kNB * kNB);
-  z.add<double>((size_t)Bw * (nmax / 256) * 256 * 256);
-  z.add<double>((size_t)potrf_scratch(Bw));
-  z.add<double>((size_t)Bw * ((nmax + kNB - 1) / kNB));
-  z.add<double>((size_t)nmax * nmaps);
-  z.add<double>((size_t)Bw * nmax * nmaps);
-  z.add<double>((size_t)Bw * nmax * nmaps);
-  z.add<double>(mode ? (size_t)Bw * nmax * nmax : 1);
-  z.add<double>(mode ? (size_t)Bw * nmax * nmaps : 1);
-  z.add<double>(mode ? (size_t)Bw * nmax * nmaps : 1);
-  z.add<double>(mode ? (size_t)Bw * nmax * kLdProbes : 1);
-  z.add<double>(mode ? (size_t)Bw * nmax * kLdProbes : 1);
-  z.add<double>(mode ? (size_t)Bw * kLdProbes : 1);
-  z.add<double>(mode ? (size_t)Bw * kLdProbes : 1);
-  z.add<double>((size_t)Bw * nmaps);
-  z.add<double>((size_t)Bw);
-  z.add<int64_t>(1);
-  z.add<int>(8);
-  if (int st = ensure_ws(*c.dev, z.off)) return st;
-  Bump bp(c.dev->ws);
+  Bump bp(wsbase);
   std::vector<Staged> S(nprob);
   for (int p = 0; p < nprob; ++p)
     if (int st = stage(bp, &probs[p], H[p], nullptr, c.s, S[p])) return st;
@@ -1452,10 +1521,11 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   x.flags = bp.take<int>(8);
   x.m2 = m2_dev; x.chi2 = chi2_dev; x.ld = ld_dev;
   x.layout = bp.off;
+  x.one_stream = noalloc;
   CF_DEV(launch_fill_int(x.flags, 1, 0, c.s));
   CF_DEV(launch_fill_int(x.flags + 1, 1, INT_MAX, c.s));
   Timer tm;
-  tm.begin(ex && ex->stage_timing, c.s);
+  tm.begin(ex && ex->stage_timing && !noalloc, c.s);
   double flops = 0.0;
   for (int p = 0; p < nprob; ++p) {
     const HostProblem& h = H[p];
@@ -1471,7 +1541,7 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
     // (points per batch; then outer panel width and GEMM tile together), keeping the best rate.
     // Trials run the first points of the scan (best of two timings each); the scan itself then
     // runs in full with the chosen shape, so every output comes from one configuration.
-    if (ex && ex->autotune && nprob == 1 && !tuned && npoints >= 2) {
+    if (ex && ex->autotune && nprob == 1 && !tuned && npoints >= 2 && !noalloc) {
       double best_rate = 0.0;
       TuneEntry best{h.n, nmaps, mode, Bt, 0, 0};
       const bool verbose = getenv("CF_TUNE_VERBOSE") != nullptr;
@@ -1529,7 +1599,7 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
     flops += (double)npoints * (nd * nd * nd / 3.0 + nd * nd * nmaps);
   }
   int fl[2];
-  if (int st = read_flags(c, x.flags, 2, fl)) return st;
+  if (int st = noalloc ? read_flags_plain(c, x.flags, 2, fl) : read_flags(c, x.flags, 2, fl)) return st;
   if (fl[0]) return fail(CF_EINVAL, "non-finite covariance entry (check noise and scan spectra)");
   if (fl[1] != INT_MAX) {
     if (rep) rep->fail_index = fl[1];
@@ -1545,6 +1615,25 @@ extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t 
   tm.finish(rep);
   if (rep) { rep->flops = flops; rep->n = H[0].n; rep->ir_iters = mode ? refine : 0; rep->n_fallback = Bt; }
   return CF_OK;
+}
+
+}  // namespace
+}  // namespace cf
+
+extern "C" int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t npoints,
+                                const double* cl_points, int32_t lstride, const double* const* maps,
+                                int32_t nmaps, int32_t precision, double* m2lnL, double* chi2,
+                                double* logdet, const cf_exec* ex, cf_report* rep) {
+  return cf::loglike_core(probs, nprob, npoints, cl_points, lstride, maps, nmaps, precision, m2lnL, chi2,
+                          logdet, ex, rep, false);
+}
+
+extern "C" int cf_loglike_batch_noalloc(const cf_problem* probs, int32_t nprob, int32_t npoints,
+                                        const double* cl_points, int32_t lstride, const double* const* maps,
+                                        int32_t nmaps, int32_t precision, double* m2lnL, double* chi2,
+                                        double* logdet, const cf_exec* ex, cf_report* rep) {
+  return cf::loglike_core(probs, nprob, npoints, cl_points, lstride, maps, nmaps, precision, m2lnL, chi2,
+                          logdet, ex, rep, true);
 }
 
 // ------------------------------------------------------------------------------- SMW likelihood

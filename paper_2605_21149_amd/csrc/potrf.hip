@@ -297,6 +297,11 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
   if (n <= 0) return hipSuccess;
   const unsigned nb = F.batch > 0 ? F.batch : 1;
   hipStream_t s = st.s;
+  // All three roles on one stream (a caller that creates no streams or events): stream order
+  // already serialises everything, so no event is recorded or waited on.
+  const bool one = st.s1 == s && st.s2 == s;
+  auto erec = [&](hipEvent_t e, hipStream_t on) { return one ? hipSuccess : hipEventRecord(e, on); };
+  auto ewait = [&](hipStream_t on, hipEvent_t e) { return one ? hipSuccess : hipStreamWaitEvent(on, e, 0); };
   bool pending_b = false, pending_i = false;
   int64_t px = 0;                            // first panel column whose extra-row update is pending
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -356,7 +361,7 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     const int64_t pe = (c + W < n) ? c + W : n;
     // ---- critical path: the diagonal blocks and panels of this outer panel (rows of C only)
     CF_HIP_TRY(rec ? panel_rec(c, pe) : panel_right(c, pe));
-    CF_HIP_TRY(hipEventRecord(st.eL, s));
+    CF_HIP_TRY(erec(st.eL, s));
     // ---- keep the host at most two panels ahead of the device.  Measured: with every panel of
     //      every stream queued up front, the device dispatches the critical chain markedly later
     //      (a single n = 5952 factorisation with its solves: 12.0 ms unthrottled, 10.0 ms here).
@@ -368,7 +373,7 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     }
     // ---- 256-block inverse for the solves (side stream)
     if (F.Li256 && pe - c >= OUTER) {
-      CF_HIP_TRY(hipStreamWaitEvent(st.s2, st.eL, 0));
+      CF_HIP_TRY(ewait(st.s2, st.eL));
       for (int64_t q = c; q + OUTER <= pe; q += OUTER) CF_HIP_TRY(tri256(F, (int)(q / OUTER), scratch, st.s2));
       pending_i = true;
     }
@@ -379,7 +384,7 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     const int64_t rx = rows_for(pe) - n;
     const int64_t pn = (pe + W < n) ? pe + W : n;    // end of the next panel
     if (rx > 0) {
-      CF_HIP_TRY(hipStreamWaitEvent(st.s2, st.eL, 0));
+      CF_HIP_TRY(ewait(st.s2, st.eL));
       for (int64_t q = c; q < pe; q += NB) {
         const int b = (int)((n - q) < NB ? (n - q) : NB);
         GemmDesc g{};                                          // X_q <- X_q L_qq^-T (in place)
@@ -406,26 +411,26 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     // ---- lookahead: the next panel's columns on the critical path, after the previous bulk update
     if (st.eA) {
       // on the bulk CUs, after the previous trailing update (stream order) and this panel's chain
-      CF_HIP_TRY(hipStreamWaitEvent(st.s1, st.eL, 0));
+      CF_HIP_TRY(ewait(st.s1, st.eL));
       CF_HIP_TRY(gemm_f64(upd(F, pe, pe, n - pe, pn - pe, c, pe - c), st.s1));
-      CF_HIP_TRY(hipEventRecord(st.eA, st.s1));
-      CF_HIP_TRY(hipStreamWaitEvent(s, st.eA, 0));
+      CF_HIP_TRY(erec(st.eA, st.s1));
+      CF_HIP_TRY(ewait(s, st.eA));
     } else {
-      if (pending_b) CF_HIP_TRY(hipStreamWaitEvent(s, st.eB, 0));
+      if (pending_b) CF_HIP_TRY(ewait(s, st.eB));
       CF_HIP_TRY(gemm_f64(upd(F, pe, pe, n - pe, pn - pe, c, pe - c), s));
     }
     // ---- bulk trailing update beyond the next panel (side stream, overlaps the next panel)
     if (pn < n) {
-      CF_HIP_TRY(hipStreamWaitEvent(st.s1, st.eL, 0));
+      CF_HIP_TRY(ewait(st.s1, st.eL));
       CF_HIP_TRY(gemm_f64(upd(F, pn, pn, n - pn, n - pn, c, pe - c), st.s1));
-      CF_HIP_TRY(hipEventRecord(st.eB, st.s1));
+      CF_HIP_TRY(erec(st.eB, st.s1));
       pending_b = true;
     }
   }
-  if (pending_b) CF_HIP_TRY(hipStreamWaitEvent(s, st.eB, 0));
+  if (pending_b) CF_HIP_TRY(ewait(s, st.eB));
   if (pending_i) {
-    CF_HIP_TRY(hipEventRecord(st.eI, st.s2));
-    CF_HIP_TRY(hipStreamWaitEvent(s, st.eI, 0));
+    CF_HIP_TRY(erec(st.eI, st.s2));
+    CF_HIP_TRY(ewait(s, st.eI));
   }
   return hipSuccess;
 }
