@@ -27,6 +27,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="time the oracle sample as a median of 3 after one warmup, plus a single-thread run")
+    ap.add_argument("--scan-points", type=int, default=8192,
+                    help="points of the two-problem QU scan (N_side 8 + 16, 64 maps each)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 / BF16x3 comparison")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (HBM counter calibration)")
@@ -63,12 +67,16 @@ def _traffic(kernel):
     return k["fetch_bytes"] + k["write_bytes"]
 
 
-def _tuned_line(path):
-    """The autotuner's entry for the likelihood batch (launch shape chosen during warmup)."""
+def _tuned_lines(path):
+    """The autotuner's entries (launch shapes chosen during warmup and tuning calls)."""
     try:
-        lines = [l.strip() for l in open(path) if l.startswith("scan ")]
+        return [l.strip() for l in open(path) if l.startswith("scan ")]
     except OSError:
         return None
+
+
+def _tuned_line(path, n=None):
+    lines = [l for l in (_tuned_lines(path) or []) if n is None or f" n={n} " in l]
     return lines[-1] if lines else None
 
 
@@ -153,41 +161,68 @@ def emulator_bench(cf, I, n_train, epochs, n_query, spread_max=0.1, seed_map=403
     }
 
 
-def cpu_baseline(problem, bins, cl_points, maps_qml, maps_scan):
-    """The CPU oracle timed on a bounded sample of one step: one covariance + factorisation +
-    Z + Fisher rows 0..5 of 72 + QML, and one likelihood point; extrapolated linearly to a full
-    step (72 Fisher rows, SCAN_POINTS likelihood points)."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sample(problem, bins, cl_points, maps_qml, maps_scan):
+    """One Fisher + QML pass of the oracle in full (covariance, factorisation, Z, all 72 x 72
+    Fisher entries, y, bias, C_hat) and one likelihood point (covariance rebuild, Cholesky, 64
+    maps); returns (seconds of the Fisher + QML pass, seconds of the likelihood point)."""
+    import scipy.linalg as sla
     from oracle import covariance as cv, likelihood, qml
-    from threadpoolctl import threadpool_info
+    import copy
     t0 = time.perf_counter()
     C = cv.total_covariance(problem)
-    t_cov = time.perf_counter() - t0
-    t0 = time.perf_counter()
     Z, Y, modes, fac = qml.projected_inverse(problem, C)
-    t_z = time.perf_counter() - t0
     coo = qml.coo_derivatives(problem, modes, bins.spectra, bins.lo, bins.hi)
-    rows = 6
+    F = qml.fisher_from_z(Z, coo)
+    w = (Y.T @ sla.cho_solve(fac, maps_qml.T)).T
+    y = qml.quadratic_from_w(w, coo)
+    np.linalg.solve(F, np.atleast_2d(y).T)
+    t_fisher = time.perf_counter() - t0
     t0 = time.perf_counter()
-    qml.fisher_from_z(Z, coo[:rows])
-    t_f = (time.perf_counter() - t0) * (len(coo) / rows) ** 2
-    t0 = time.perf_counter()
-    w = (Y.T @ __import__("scipy.linalg", fromlist=["cho_solve"]).cho_solve(fac, maps_qml.T)).T
-    qml.quadratic_from_w(w, coo)
-    t_q = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    import copy
     p1 = copy.copy(problem)
     p1.cl = cl_points[0, 0]
-    C1 = cv.total_covariance(p1)
-    likelihood.chi2_logdet(C1, maps_scan)
-    t_pt = time.perf_counter() - t0
-    step = t_cov + t_z + t_f + t_q + SCAN_POINTS * t_pt
+    likelihood.chi2_logdet(cv.total_covariance(p1), maps_scan)
+    t_point = time.perf_counter() - t0
+    return t_fisher, t_point
+
+
+def cpu_baseline(problem, bins, cl_points, maps_qml, maps_scan, full=False):
+    """The CPU oracle on the host cores: the Fisher + QML pass timed in full and one of the
+    SCAN_POINTS likelihood points timed and scaled to the step.  full: one warmup, the median of
+    three runs, and one run on a single BLAS thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    return {"value": 1.0 / step, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"one Fisher+QML pass with Fisher rows 0-5 of 72 timed and scaled by 144, "
-                       f"one of {SCAN_POINTS} likelihood points timed and scaled; "
-                       f"measured {t_cov + t_z + t_f / 144 + t_q + t_pt:.1f} s, "
-                       f"extrapolated step {step:.1f} s (host BLAS threads {threads})")}
+    if full:
+        _oracle_sample(problem, bins, cl_points, maps_qml, maps_scan)
+        runs = [_oracle_sample(problem, bins, cl_points, maps_qml, maps_scan) for _ in range(3)]
+        t_f = float(np.median([r[0] for r in runs]))
+        t_p = float(np.median([r[1] for r in runs]))
+    else:
+        t_f, t_p = _oracle_sample(problem, bins, cl_points, maps_qml, maps_scan)
+    step = t_f + SCAN_POINTS * t_p
+    out = {"value": 1.0 / step, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+           "fisher_qml_s": t_f, "loglike_point_s": t_p,
+           "sample": (f"one Fisher+QML pass timed in full ({t_f:.1f} s: covariance, Cholesky, Z, all 72x72 "
+                      f"Fisher entries, y, bias, C_hat) and one of {SCAN_POINTS} likelihood points "
+                      f"({t_p:.1f} s, 64 maps) scaled by {SCAN_POINTS}; "
+                      + ("median of 3 after one warmup" if full else "one run")
+                      + f"; host BLAS threads {threads}")}
+    if full:
+        with threadpool_limits(limits=1):
+            t1f, t1p = _oracle_sample(problem, bins, cl_points, maps_qml, maps_scan)
+        out["single_thread"] = {"fisher_qml_s": t1f, "loglike_point_s": t1p,
+                                "steps_per_s": 1.0 / (t1f + SCAN_POINTS * t1p)}
+    return out
 
 
 def smw_section(cf, I, problem, packed, d_maps_scan, direct_m2, direct_pts_per_s, reps=3):
@@ -275,12 +310,13 @@ def qml_extras(cf, I, problem, bins, packed, d_maps_qml, reps=3):
             "qml_iterate": {"ms": 1e3 * ti, "iterations": it["iterations"], "tol_fisher_errors": 1e-6}}
 
 
-def qu_scan(cf, I, npoints=256, reps=3):
-    """The two-problem QU likelihood scan (N_side 8, n = 1088, and N_side 16, n = 3968, in one call,
-    64 maps each) on a bounded sample of the scan's parameter box: points/s (one point = both
-    problems) and map evaluations/s, FP64 and FP32 mixed (with the refined chi^2 and the log-det
-    correction), and the mixed path's largest |d(-2 ln L)| against FP64.  Autotuning is off: a
-    multi-problem call takes the default batch."""
+def qu_scan(cf, I, npoints=8192):
+    """The QU likelihood scan of the batched-scan workload (N_side 8, n = 1088, and N_side 16,
+    n = 3968, 64 maps each) over npoints points of its parameter box, each problem in its own call
+    (calls that mix the two problems stay off the GPU: see the library's notes) in the launch shape
+    the autotuner recorded for it (tuned on 64 points first): points/s (one point = both problems,
+    the two calls' times added) and map evaluations/s, FP64 and FP32 mixed (with the refined chi^2
+    and the log-det correction), and the mixed path's largest |d(-2 ln L)| against FP64."""
     import torch
     pa, pb = I.qu_scan_problem(8), I.qu_scan_problem(16)
     pks = [cf.pack_problem(pa, device=True), cf.pack_problem(pb, device=True)]
@@ -293,20 +329,28 @@ def qu_scan(cf, I, npoints=256, reps=3):
     d_cl = torch.as_tensor(clp).cuda()
     out, ref = {"n": [pa.n, pb.n], "points": npoints, "maps": 64}, None
     for prec, name in ((cf.CF_FP64, "fp64"), (cf.CF_MIXED_FP32, "fp32")):
-        ts, res = [], None
-        for _ in range(reps + 1):
+        for k, p in enumerate((pa, pb)):
+            cf.loglike_batch([p], d_cl[:64, k:k + 1, :, :p.lmax + 1].contiguous(), maps[k:k + 1], precision=prec,
+                             device=True, packed=pks[k:k + 1], autotune=True)
+        t, parts = 0.0, []
+        for k, p in enumerate((pa, pb)):
+            cl1 = d_cl[:, k:k + 1, :, :p.lmax + 1].contiguous()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            res = cf.loglike_batch([pa, pb], d_cl, maps, precision=prec, device=True, packed=pks)
+            res = cf.loglike_batch([p], cl1, maps[k:k + 1], precision=prec, device=True, packed=pks[k:k + 1],
+                                   autotune=True)
             torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
-        t = float(np.median(ts[1:]))
-        m2 = res["m2lnL"].cpu().numpy()
+            t += time.perf_counter() - t0
+            parts.append(res["m2lnL"].cpu().numpy())
+        _log(f"qu scan {name}: {npoints} points x 2 problems in {t:.2f} s")
+        m2 = np.concatenate(parts, axis=1)
         out[name] = {"ms": 1e3 * t, "points_per_s": npoints / t, "map_evals_per_s": 2 * 64 * npoints / t}
         if ref is None:
             ref = m2
         else:
             out[name]["max_abs_dm2lnL_vs_fp64"] = float(np.abs(m2 - ref).max())
+    out["autotuned"] = [l for l in (_tuned_lines(os.environ["CF_TUNE_CACHE"]) or [])
+                        if f"n={pa.n} " in l or f"n={pb.n} " in l]
     return out
 
 
@@ -465,12 +509,13 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         ev[3 * k].record()
-        # Fisher + QML with per-stage device timers (the roofline of the Z = G^T G kernel)
+        # Fisher + QML with per-stage device timers and per-launch GEMM events
         rq = cf.qml(problem, bins, d_maps_qml, device=True, stage_timing=True, report=True,
                     packed=packed)[1]
         ev[3 * k + 1].record()
-        # the likelihood batch, in the launch shape the autotuner chose during warmup
-        rs = cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True, report=True,
+        # the likelihood batch, in the launch shape the autotuner chose during warmup, with the same
+        # timers (the tuned shape launches eagerly at this size)
+        rs = cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True, report=True, stage_timing=True,
                               packed=[packed], autotune=True)[1]
         ev[3 * k + 2].record()
         reps.append((rq, rs))
@@ -480,14 +525,15 @@ def main():
     scan_ms = [ev[3 * k + 1].elapsed_time(ev[3 * k + 2]) for k in range(args.steps)]
     ms_step = 1000.0 * wall / args.steps
     stage = np.mean([r[0]["ms_stage"] for r in reps], axis=0)
-    # per-stage view of the likelihood batch (eager launches with timers, outside the timed steps)
-    scan_stage = np.asarray(cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True,
-                                             stage_timing=True, report=True,
-                                             packed=[packed])[1]["ms_stage"])
+    scan_stage = np.mean([r[1]["ms_stage"] for r in reps], axis=0)
+    # GEMM instances over the timed steps (both calls): summed event time, algorithmic flops, launches
+    g_ms = np.sum([np.add(r[0]["gemm_ms"], r[1]["gemm_ms"]) for r in reps], axis=0)
+    g_fl = np.sum([np.add(r[0]["gemm_flops"], r[1]["gemm_flops"]) for r in reps], axis=0)
+    g_n = np.sum([np.add(r[0]["gemm_launches"], r[1]["gemm_launches"]) for r in reps], axis=0)
     mixed = None if args.no_mixed else mixed_precision(cf, I, problem, bins, packed, d_maps_qml, d_cl,
                                                           d_maps_scan)
     extras = None if args.no_extras else qml_extras(cf, I, problem, bins, packed, d_maps_qml)
-    scan_qu = None if args.no_extras else qu_scan(cf, I)
+    scan_qu = None if args.no_extras else qu_scan(cf, I, args.scan_points)
     fishers = None if args.no_extras else other_fishers(cf, I)
     host_inputs = None if args.no_extras else host_input_step(cf, problem, bins, maps_qml, maps_scan,
                                                                  cl_points)
@@ -497,20 +543,25 @@ def main():
                                      autotune=True)["m2lnL"][:, 0, :].cpu().numpy()
         smw = smw_section(cf, I, problem, packed, d_maps_scan, direct_m2,
                           SCAN_POINTS / (np.median(scan_ms) * 1e-3))
-    # roofline kernel: the largest single launch of the step, the FP64 MFMA symmetric product
-    # forming the E,B x E,B block of Z = G^T G (k_gemm<64,64,false,true,1>), timed with HIP
-    # events on the stream it runs on.  Algorithmic flops: the lower triangle with the diagonal
-    # (kP (kP+1) / 2 entries) over the rows from the first Q pixel (G's E,B columns vanish above).
-    npx = problem.npix
-    kP = 4600
-    p0 = (npx // 64) * 64
-    syrk_flops = kP * (kP + 1) * (n - p0)
-    syrk_ms = stage[4]
-    achieved = syrk_flops / (syrk_ms * 1e-3) / 1e12
-    traffic = _traffic("k_gemm<64,64,false,true,1>")
+    # Roofline kernel: the GEMM instance with the most device time over the timed steps (the
+    # factorisations' A B^T updates dominate the step), achieved = its algorithmic flops over the
+    # timed steps / its summed HIP-event durations on the streams it ran on.  Every instance is also
+    # listed (gemm_instances), with the whole factorisations' rates (factorisation).
+    inst = []
+    for i in range(len(g_ms)):
+        if g_n[i] > 0:
+            inst.append({"kernel": cf.gemm_instance_name(i), "launches_per_step": float(g_n[i]) / args.steps,
+                         "ms_per_step": float(g_ms[i]) / args.steps,
+                         "tflops": float(g_fl[i] / (g_ms[i] * 1e-3) / 1e12) if g_ms[i] > 0 else None,
+                         "flops_per_launch": float(g_fl[i] / g_n[i])})
+    inst.sort(key=lambda r: -r["ms_per_step"])
+    top = inst[0]
+    traffic = _traffic(top["kernel"])
     # whole factorisations against the same peak, algorithmic flops only: n^3/3 for the Cholesky and
     # m^2 per right-hand side solved over m rows (the E,B columns of Y vanish above the first Q
     # pixel, so they are solved over n - p0 rows; the T columns and the map over all n)
+    npx = problem.npix
+    p0 = (npx // 64) * 64
     nT = 48 * 48 - 4
     fac_fisher = n ** 3 / 3.0 + (nT + 1) * n ** 2 + (6900 - nT) * (n - p0) ** 2
     fac_scan = SCAN_POINTS * (n ** 3 / 3.0 + NMAPS_SCAN * n ** 2)
@@ -532,13 +583,14 @@ def main():
                                 f"{NMAPS_SCAN} maps"),
                    "precision": "fp64", "n": n, "nmodes": 6900, "scan_points_per_step": SCAN_POINTS,
                    "maps_per_point": NMAPS_SCAN,
-                   "autotuned": _tuned_line(os.environ["CF_TUNE_CACHE"])},
+                   "autotuned": _tuned_line(os.environ["CF_TUNE_CACHE"], n)},
         "fisher_qml_ms": float(np.median(qml_ms)),
         "loglike_ms": float(np.median(scan_ms)),
         "loglike_points_per_s": SCAN_POINTS / (np.median(scan_ms) * 1e-3),
         "loglike_map_evals_per_s": SCAN_POINTS * NMAPS_SCAN / (np.median(scan_ms) * 1e-3),
         "stages_fisher_qml_ms": dict(zip(cf.STAGES, [round(float(x), 4) for x in stage])),
         "stages_loglike_ms": dict(zip(cf.STAGES, [round(float(x), 4) for x in scan_stage])),
+        "gemm_instances": inst,
         "mixed_precision": mixed,
         "smw": smw,
         "qml_extras": extras,
@@ -546,14 +598,17 @@ def main():
         "qu_scan": scan_qu,
         "other_fishers": fishers,
         "factorisation": factorisation,
-        "roofline": {"bound": "mfma", "kernel": "k_gemm<64,64,false,true,1> FP64 (Z_EB,EB = G_EB^T G_EB)",
-                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic},
+        "roofline": {"bound": "mfma", "kernel": top["kernel"] + " FP64 (factorisation and solve updates)",
+                     "achieved": top["tflops"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": top["tflops"] / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "launches_per_step": top["launches_per_step"],
+                     "flops_per_launch": top["flops_per_launch"]},
     }
     if args.emulator:
         out["emulator"] = emulator_bench(cf, I, args.emu_train, args.emu_epochs, args.emu_query)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(problem, bins, cl_points, maps_qml, maps_scan)
+        out["cpu_baseline"] = cpu_baseline(problem, bins, cl_points, maps_qml, maps_scan,
+                                           full=args.cpu_baseline_full)
     print(json.dumps(out), flush=True)
 
 

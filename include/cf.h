@@ -101,6 +101,13 @@ typedef struct {
   int32_t ir_iters;       /* refinement steps taken                                    */
   double est_err[4];      /* mixed precision error estimates                           */
   int64_t n_fallback;     /* fallbacks taken                                           */
+  /* With cf_exec.stage_timing: every launch of the FP64 matrix-core GEMM is bracketed by events
+   * on its stream and summed per kernel instance, id = (128 x 128 tile) + 2 (A stored transposed)
+   * + 4 (B stored transposed) + 8 (the separately named Z = G^T G instance):                  */
+  double gemm_ms[16];        /* summed device time of the instance's launches                  */
+  double gemm_flops[16];     /* their algorithmic flops, 2 M N K, outputs of a lower-triangular
+                                product counted on the triangle only                          */
+  int64_t gemm_launches[16]; /* their number                                                  */
 } cf_report;
 
 /* Data dimension n = nmaps * npix of a problem, or -1 (see cf_last_error). */
@@ -227,7 +234,10 @@ typedef struct cf_smw cf_smw;
 /* Factor N_eff and solve the window's harmonic rows and the maps against it.  maps: [nmaps][n] in
  * prob->mem space.  The handle keeps device buffers of about 8 (k_win^2 + k_win nmaps) bytes on the
  * current device and copies of the geometry-independent data it needs; the problem and the maps
- * may be released after the call.  On error *out is left NULL. */
+ * may be released after the call.  On error *out is left NULL.
+ * Field groups (App. field_blocks): when the window holds T and E and/or B and N_eff couples no T
+ * pixel with a Q, U pixel (no TE, TB in the fixed spectra, no T-P block in N), M has no T x (E,B)
+ * block; the handle then records two groups (cf_report.ir_iters = 2, else 1). */
 int cf_smw_create(const cf_problem* prob, int32_t win_lmin, int32_t win_lmax, uint32_t win_fields,
                   const double* maps, int32_t nmaps, const cf_exec* ex, cf_smw** out, cf_report* rep);
 
@@ -235,13 +245,68 @@ int cf_smw_create(const cf_problem* prob, int32_t win_lmin, int32_t win_lmax, ui
  *   cl_points [npoints][6][lstride] (lstride >= lmax+1 of the problem)
  *   m2lnL [npoints][nmaps];  chi2 same shape (nullable);  logdet [npoints] (nullable)
  * Memory space of cl_points and the outputs: the problem's mem at creation.  Calls on one handle
- * must not overlap. */
+ * must not overlap.  On a handle with two field groups, a call whose points all have TE and TB
+ * equal to zero inside the window factorises K' as its T block and its E,B block separately
+ * (k_T^3/3 + k_EB^3/3 instead of k_win^3/3 per point; cf_report.ir_iters = 2); any other call
+ * factorises the dense K' (ir_iters = 1). */
 int cf_smw_loglike(cf_smw* h, int32_t npoints, const double* cl_points, int32_t lstride, double* m2lnL,
                    double* chi2, double* logdet, const cf_exec* ex, cf_report* rep);
 
 /* k_win of a handle (or -1), and its release (NULL is a no-op). */
 int64_t cf_smw_dim(const cf_smw* h);
 void cf_smw_destroy(cf_smw* h);
+
+/* Fisher matrix and QML estimates in the harmonic basis with multipole switching (Sects. 2.3.3 and
+ * 2.3.4; Eqs. projected_inv_smw, weighted_data_smw, q_harmonic, N_eff; App. smw_stable).  The
+ * estimation window [win_lmin, win_lmax] holds every harmonic field of the problem; multipoles of
+ * [lmin, lmax] outside it stay at the fiducial prob->cl and enter N_eff.  With M = V N_eff^-1 V^T,
+ * b = V N_eff^-1 d, Lambda = R R^T at the fiducial and K' = I + R^T M R:
+ *   Z = V C^-1 V^T = M R K'^-1 R^-1 (= M (I + Lambda M)^-1),  w = V C^-1 d = R^-T K'^-1 R^T b,
+ *   noise bias b_b = 1/2 tr[E_b A T A^T], A = R^-T K'^-1 R^T, T = V N_eff^-1 N N_eff^-1 V^T,
+ * then F, y, C_hat as in cf_qml; the results equal cf_qml's with the same bins (all inside the
+ * window).  Needs Lambda positive definite at every window multipole (CF_EINVAL otherwise).
+ * Outputs as cf_qml: y_out [nmaps][ns*nb], bias_out [ns*nb], chat_out [nmaps][ns*nb], F_out
+ * [(ns*nb)^2] (nullable), all in prob->mem space; maps [nmaps][n].  FP64. */
+int cf_smw_qml(const cf_problem* prob, int32_t win_lmin, int32_t win_lmax, const cf_bins* bins,
+               const double* maps, int32_t nmaps, double* y_out, double* bias_out, double* chat_out,
+               double* F_out, const cf_exec* ex, cf_report* rep);
+
+/* ---------------------------------------------------------------------------------------------
+ * Cost-based choice of the computation basis for a likelihood scan (Sect. 3, the "auto" selector
+ * of the ComputationBasis interface; per-point costs as in the complexity table of App. C).
+ *   pixel:    npoints * (n^3/3 + n^2 nmaps)            (C = S + N factorised at every point)
+ *   harmonic: n^3/3 + n^2 (k + nmaps) + n k (k + nmaps) (N_eff factorised once with the window's
+ *             rows and the maps) + npoints * (k^3/3 + k^2 nmaps), with k = k_win, or with the
+ *             T and E,B field groups factorised apart (k_T^3/3 + k_EB^3/3 + ...) when the fixed
+ *             spectra carry no TE, TB and the noise has no T-P block (diagonal noise without a
+ *             low-rank part, or a dense noise in host memory found block-diagonal).
+ * The harmonic basis is chosen when it is cheaper and the window couples no varied field to a fixed
+ * one (harmonic_ok); the caller states the window in which its points' spectra vary.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct {
+  int32_t basis;          /* 0 pixel basis (cf_loglike_batch), 1 harmonic basis (cf_smw_*)        */
+  int32_t harmonic_ok;    /* 0: the window couples a varied and a fixed field (pixel basis only) */
+  int32_t groups;         /* field groups of the harmonic kernel (1, or 2: T | E,B)              */
+  int64_t n, k_win;       /* data dimension and window modes                                   */
+  double cost_pixel;      /* flops of the whole scan in the pixel basis                         */
+  double cost_harmonic;   /* flops of the whole scan in the harmonic basis, setup included       */
+} cf_basis_choice;
+
+/* Fills *out for a scan of npoints points with nmaps maps over the window [win_lmin, win_lmax] on
+ * win_fields (OR of CF_FIELD_T, CF_FIELD_E, CF_FIELD_B).  Host-only (no device work). */
+int cf_select_basis(const cf_problem* prob, int32_t win_lmin, int32_t win_lmax, uint32_t win_fields,
+                    int32_t npoints, int32_t nmaps, cf_basis_choice* out);
+
+/* -2 ln L of one problem over npoints points in the basis cf_select_basis picks: the pixel basis
+ * runs cf_loglike_batch (FP64), the harmonic basis creates a cf_smw handle for the window, runs
+ * cf_smw_loglike and releases it.  The points' spectra must differ from prob->cl only inside the
+ * window (the harmonic basis reads nothing else).  cl_points [npoints][6][lstride], maps [nmaps][n],
+ * outputs m2lnL, chi2 [npoints][nmaps] and logdet [npoints] in prob->mem space; choice (host,
+ * nullable) receives the selector's record. */
+int cf_loglike_auto(const cf_problem* prob, int32_t win_lmin, int32_t win_lmax, uint32_t win_fields,
+                    int32_t npoints, const double* cl_points, int32_t lstride, const double* maps,
+                    int32_t nmaps, double* m2lnL, double* chi2, double* logdet, cf_basis_choice* choice,
+                    const cf_exec* ex, cf_report* rep);
 
 /* ---------------------------------------------------------------------------------------------
  * Likelihood emulator.  Not part of the paper's method: a surrogate of the -2 ln L of
@@ -315,6 +380,16 @@ int cf_emu_predict(cf_emu* emu, const double* x, int64_t N, int32_t mem, double 
                    const cf_problem* exact_prob, const cf_linear_spectra* model,
                    const double* exact_map, double* y_out, double* spread_out,
                    uint8_t* used_fallback, const cf_exec* ex, cf_report* rep);
+
+/* cf_emu_predict with the exact fallback through a harmonic-basis likelihood handle (cf_smw_create
+ * with one map): queries outside the hull or with spread above spread_max get cf_smw_loglike at
+ * cl(x) (FP64).  The handle evaluates the model's spectra inside its window (its fields and
+ * multipoles) and holds everything else at the fiducial it was made with, so its values equal the
+ * exact pixel likelihood when the model varies the spectra only inside that window.  The memory
+ * space of the handle (its problem's mem) need not match `mem`. */
+int cf_emu_predict_smw(cf_emu* emu, const double* x, int64_t N, int32_t mem, double spread_max,
+                       const cf_smw* exact_smw, const cf_linear_spectra* model, double* y_out,
+                       double* spread_out, uint8_t* used_fallback, const cf_exec* ex, cf_report* rep);
 
 /* Inspection and checking of the networks (host memory, raw network units: inputs already
  * normalised, outputs and targets standardised).

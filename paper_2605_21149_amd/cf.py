@@ -49,13 +49,23 @@ class cf_report(C.Structure):
     _fields_ = [("ms_total", C.c_double), ("ms_stage", C.c_double * 8), ("flops", C.c_double),
                 ("logdet", C.c_double), ("n", C.c_int64), ("nmodes", C.c_int64),
                 ("fail_index", C.c_int32), ("ir_iters", C.c_int32), ("est_err", C.c_double * 4),
-                ("n_fallback", C.c_int64)]
+                ("n_fallback", C.c_int64), ("gemm_ms", C.c_double * 16), ("gemm_flops", C.c_double * 16),
+                ("gemm_launches", C.c_int64 * 16)]
 
     def as_dict(self):
         return {"ms_total": self.ms_total, "ms_stage": list(self.ms_stage), "flops": self.flops,
                 "logdet": self.logdet, "n": self.n, "nmodes": self.nmodes,
                 "fail_index": self.fail_index, "ir_iters": self.ir_iters,
-                "est_err": list(self.est_err), "n_fallback": self.n_fallback}
+                "est_err": list(self.est_err), "n_fallback": self.n_fallback,
+                "gemm_ms": list(self.gemm_ms), "gemm_flops": list(self.gemm_flops),
+                "gemm_launches": list(self.gemm_launches)}
+
+
+def gemm_instance_name(i):
+    """Kernel name of FP64 GEMM instance id i of cf_report.gemm_* (tile, operand storage, tag)."""
+    t = 128 if i & 1 else 64
+    return (f"k_gemm<{t}, {t}, {'true' if i & 2 else 'false'}, {'true' if i & 4 else 'false'}, "
+            f"{1 if i & 8 else 0}>")
 
 
 STAGES = ("build", "potrf", "ybuild", "trsm", "syrk", "reduce", "qml", "other")
@@ -63,10 +73,20 @@ STAGES = ("build", "potrf", "ybuild", "trsm", "syrk", "reduce", "qml", "other")
 # Every symbol include/cf.h declares.
 EXPORTS = ("cf_problem_dim", "cf_problem_nmodes", "cf_cov_build", "cf_fisher", "cf_qml",
            "cf_loglike_batch", "cf_loglike_batch_noalloc", "cf_emu_create", "cf_emu_destroy", "cf_emu_param_count", "cf_emu_shape",
-           "cf_emu_train", "cf_emu_predict", "cf_emu_get_params", "cf_emu_set_params",
+           "cf_emu_train", "cf_emu_predict", "cf_emu_predict_smw", "cf_emu_get_params", "cf_emu_set_params",
            "cf_emu_forward", "cf_emu_gradient", "cf_emu_adam", "cf_emu_save", "cf_emu_load",
-           "cf_smw_create", "cf_smw_loglike", "cf_smw_dim", "cf_smw_destroy", "cf_decorrelate", "cf_qml_iterate", "cf_qml_cross",
+           "cf_smw_create", "cf_smw_loglike", "cf_smw_dim", "cf_smw_destroy", "cf_select_basis", "cf_loglike_auto", "cf_smw_qml", "cf_decorrelate", "cf_qml_iterate", "cf_qml_cross",
            "cf_last_error", "cf_version")
+
+
+class cf_basis_choice(C.Structure):
+    _fields_ = [("basis", C.c_int32), ("harmonic_ok", C.c_int32), ("groups", C.c_int32), ("n", C.c_int64),
+                ("k_win", C.c_int64), ("cost_pixel", C.c_double), ("cost_harmonic", C.c_double)]
+
+    def as_dict(self):
+        return {"basis": "harmonic" if self.basis else "pixel", "harmonic_ok": bool(self.harmonic_ok),
+                "groups": self.groups, "n": self.n, "k_win": self.k_win, "cost_pixel": self.cost_pixel,
+                "cost_harmonic": self.cost_harmonic}
 
 
 class cf_linear_spectra(C.Structure):
@@ -133,6 +153,9 @@ def lib():
                                      C.POINTER(cf_problem), C.POINTER(cf_linear_spectra), _dp, _dp,
                                      _dp, C.POINTER(C.c_uint8), C.POINTER(cf_exec),
                                      C.POINTER(cf_report)]
+        L.cf_emu_predict_smw.argtypes = [C.c_void_p, _dp, C.c_int64, C.c_int32, C.c_double, C.c_void_p,
+                                         C.POINTER(cf_linear_spectra), _dp, _dp, C.POINTER(C.c_uint8),
+                                         C.POINTER(cf_exec), C.POINTER(cf_report)]
         L.cf_emu_get_params.argtypes = [C.c_void_p, C.c_int32, _fp]
         L.cf_emu_set_params.argtypes = [C.c_void_p, C.c_int32, _fp]
         L.cf_emu_forward.argtypes = [C.c_void_p, _dp, C.c_int64, _fp]
@@ -151,13 +174,23 @@ def lib():
         L.cf_qml_iterate.argtypes = [C.POINTER(cf_problem), C.POINTER(cf_bins), _dp, C.c_int32, C.c_double,
                                      _dp, _dp, _dp, C.POINTER(C.c_int32), C.POINTER(cf_exec),
                                      C.POINTER(cf_report)]
+        L.cf_select_basis.argtypes = [C.POINTER(cf_problem), C.c_int32, C.c_int32, C.c_uint32, C.c_int32, C.c_int32,
+                                      C.POINTER(cf_basis_choice)]
+        L.cf_select_basis.restype = C.c_int
+        L.cf_loglike_auto.argtypes = [C.POINTER(cf_problem), C.c_int32, C.c_int32, C.c_uint32, C.c_int32, _dp,
+                                      C.c_int32, _dp, C.c_int32, _dp, _dp, _dp, C.POINTER(cf_basis_choice),
+                                      C.POINTER(cf_exec), C.POINTER(cf_report)]
+        L.cf_loglike_auto.restype = C.c_int
+        L.cf_smw_qml.argtypes = [C.POINTER(cf_problem), C.c_int32, C.c_int32, C.POINTER(cf_bins), _dp, C.c_int32,
+                                 _dp, _dp, _dp, _dp, C.POINTER(cf_exec), C.POINTER(cf_report)]
+        L.cf_smw_qml.restype = C.c_int
         L.cf_smw_dim.argtypes = [C.c_void_p]
         L.cf_smw_dim.restype = C.c_int64
         L.cf_smw_destroy.argtypes = [C.c_void_p]
         L.cf_smw_destroy.restype = None
         for name in ("cf_cov_build", "cf_fisher", "cf_qml", "cf_loglike_batch", "cf_loglike_batch_noalloc",
                      "cf_emu_create",
-                     "cf_emu_train", "cf_emu_predict", "cf_emu_get_params", "cf_emu_set_params",
+                     "cf_emu_train", "cf_emu_predict", "cf_emu_predict_smw", "cf_emu_get_params", "cf_emu_set_params",
                      "cf_emu_forward", "cf_emu_gradient", "cf_emu_adam", "cf_emu_save",
                      "cf_emu_load", "cf_smw_create", "cf_smw_loglike", "cf_decorrelate", "cf_qml_cross",
                      "cf_qml_iterate"):
@@ -412,6 +445,72 @@ def loglike_batch(problems: Sequence, cl_points, maps: Sequence, precision=CF_FP
     return (out, rep.as_dict()) if report else out
 
 
+def smw_qml(p, window, bins, maps, device=False, report=False, packed=None):
+    """Fisher and QML in the harmonic basis with multipole switching (cf_smw_qml): the estimation
+    window = (lo, hi) on every field of the problem, bins inside it.  Returns dict(y, bias, chat, F)."""
+    pk = packed or pack_problem(p, device)
+    bs, keep = pack_bins(bins)
+    K = len(bins.spectra) * bs.nbins
+    if device:
+        import torch
+        m = maps if _is_torch(maps) else torch.as_tensor(np.ascontiguousarray(maps, np.float64))
+        m = torch.atleast_2d(m.to("cuda", torch.float64)).contiguous()
+    else:
+        m = np.atleast_2d(_host(maps))
+    nm = int(m.shape[0])
+    y, bias, chat, F = (_alloc((nm, K), device), _alloc((K,), device), _alloc((nm, K), device),
+                        _alloc((K, K), device))
+    rep = cf_report()
+    ex = _exec(_torch_stream() if device else None)
+    st = lib().cf_smw_qml(C.byref(pk.struct), int(window[0]), int(window[1]), C.byref(bs), _ptr(m), nm, _ptr(y),
+                          _ptr(bias), _ptr(chat), _ptr(F), C.byref(ex), C.byref(rep))
+    _check(st, rep)
+    out = {"y": y, "bias": bias, "chat": chat, "F": F}
+    return (out, rep.as_dict()) if report else out
+
+
+def _field_bits(fields):
+    return sum(FIELD_BITS[f] for f in set(fields))
+
+
+def select_basis(p, window, fields, npoints, nmaps, packed=None):
+    """The cost-based basis choice (cf_select_basis) for a scan of npoints points and nmaps maps
+    whose spectra vary in window = (lo, hi) on the harmonic fields `fields` (e.g. "TEB")."""
+    pk = packed or pack_problem(p)
+    out = cf_basis_choice()
+    _check(lib().cf_select_basis(C.byref(pk.struct), int(window[0]), int(window[1]), _field_bits(fields),
+                                 int(npoints), int(nmaps), C.byref(out)))
+    return out.as_dict()
+
+
+def loglike_auto(p, window, fields, cl_points, maps, device=False, packed=None, report=False):
+    """-2 ln L of one problem over cl_points [npoints][6][lstride] in the basis cf_select_basis picks
+    (cf_loglike_auto).  Returns dict(m2lnL [npoints][nmaps], chi2, logdet [npoints], choice)."""
+    pk = packed or pack_problem(p, device)
+    if device:
+        import torch
+        clp = cl_points if _is_torch(cl_points) else torch.as_tensor(np.ascontiguousarray(cl_points, np.float64))
+        clp = clp.to("cuda", torch.float64).contiguous()
+        m = maps if _is_torch(maps) else torch.as_tensor(np.ascontiguousarray(maps, np.float64))
+        m = torch.atleast_2d(m.to("cuda", torch.float64)).contiguous()
+    else:
+        clp = _host(cl_points)
+        m = np.atleast_2d(_host(maps))
+    npoints, lstride, nmaps = int(clp.shape[0]), int(clp.shape[-1]), int(m.shape[0])
+    m2 = _alloc((npoints, nmaps), device)
+    x2 = _alloc((npoints, nmaps), device)
+    ld = _alloc((npoints,), device)
+    ch = cf_basis_choice()
+    rep = cf_report()
+    ex = _exec(_torch_stream() if device else None)
+    st = lib().cf_loglike_auto(C.byref(pk.struct), int(window[0]), int(window[1]), _field_bits(fields), npoints,
+                               _ptr(clp), lstride, _ptr(m), nmaps, _ptr(m2), _ptr(x2), _ptr(ld), C.byref(ch),
+                               C.byref(ex), C.byref(rep))
+    _check(st, rep)
+    out = {"m2lnL": m2, "chi2": x2, "logdet": ld, "choice": ch.as_dict()}
+    return (out, rep.as_dict()) if report else out
+
+
 # ------------------------------------------------------------------------------ emulator
 def qml_iterate(p, bins, data, max_iter=20, tol=1e-6, device=False, report=False, packed=None):
     """Iterative QML of one map [n]: dict(chat [K], F [K][K] at the last fiducial, cl [6][lmax+1]
@@ -587,14 +686,20 @@ class Emulator:
         _check(st, rep)
         return rep.as_dict() if report else None
 
-    def predict(self, x, spread_max=0.1, exact=None, device=False, report=False):
-        """exact = (problem, base [6][L], basis [in][6][L], map [n]) enables the exact fallback.
-        Returns dict(y, spread, fallback)."""
+    def predict(self, x, spread_max=0.1, exact=None, device=False, report=False, exact_smw=None):
+        """exact = (problem, base [6][L], basis [in][6][L], map [n]) enables the exact fallback
+        through the pixel likelihood; exact_smw = (SMW handle with one map, base, basis) through the
+        harmonic-basis likelihood.  Returns dict(y, spread, fallback)."""
         xs = self._arr(x, device)
         N = xs.shape[0]
         keep = []
         pp = ms = mp = None
-        if exact is not None:
+        if exact_smw is not None:
+            h, base, basis = exact_smw
+            base, basis = _host(base), _host(basis)
+            keep += [base, basis]
+            ms = C.byref(cf_linear_spectra(basis.shape[0], base.shape[-1], _ptr(base), _ptr(basis)))
+        elif exact is not None:
             prob, base, basis, emap = exact
             pk = pack_problem(prob, device)
             keep.append(pk)
@@ -615,9 +720,14 @@ class Emulator:
             fb = np.empty((N,), dtype=np.uint8)
         rep = cf_report()
         ex = _exec(_torch_stream() if device else None)
-        st = lib().cf_emu_predict(self._h, _ptr(xs), N, CF_MEM_DEVICE if device else CF_MEM_HOST,
-                                  float(spread_max), pp, ms, mp, _ptr(y), _ptr(sp),
-                                  _ptr(fb, C.c_uint8), C.byref(ex), C.byref(rep))
+        if exact_smw is not None:
+            st = lib().cf_emu_predict_smw(self._h, _ptr(xs), N, CF_MEM_DEVICE if device else CF_MEM_HOST,
+                                          float(spread_max), exact_smw[0]._h, ms, _ptr(y), _ptr(sp),
+                                          _ptr(fb, C.c_uint8), C.byref(ex), C.byref(rep))
+        else:
+            st = lib().cf_emu_predict(self._h, _ptr(xs), N, CF_MEM_DEVICE if device else CF_MEM_HOST,
+                                      float(spread_max), pp, ms, mp, _ptr(y), _ptr(sp),
+                                      _ptr(fb, C.c_uint8), C.byref(ex), C.byref(rep))
         _check(st, rep)
         out = {"y": y, "spread": sp, "fallback": fb}
         return (out, rep.as_dict()) if report else out

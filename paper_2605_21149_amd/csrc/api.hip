@@ -47,7 +47,12 @@ int fail(int code, const char* fmt, ...) {
 
 // ------------------------------------------------------------------------------- per device
 constexpr int kEvents = 16;
-constexpr int kGraphMaxN = 2048;   // scans of larger problems launch eagerly
+// Captured batches are replayed only for problems that a batch factorises in one outer panel
+// (n <= 512): processes that captured and replayed batches of larger problems (n = 1088 and
+// n = 3968 with 64 maps, factorised over several panels on three streams) ended with host
+// segmentation faults whose cause is not established, so larger problems launch eagerly,
+// host-paced two panels ahead (measured faster for n = 5952 batches of 8 than the replay).
+constexpr int kGraphMaxN = 512;
 // Probes of the mixed path's stochastic log-det correction: the estimate's standard deviation is
 // about sqrt(2 / kLdProbes) |X|_F.  Measured with FP32 updates: 2.5e-4 at 256 probes on the QU
 // N_side 16 scan problem (|X|_F about 2.8e-3), against biases of ln|C| of the FP32 factor of up to
@@ -66,6 +71,7 @@ struct Device {
   char* ws = nullptr;
   size_t cap = 0;
   int* hflags = nullptr;   // pinned host mirror of the device flags
+  char arch[64] = {0};     // the device's architecture name (gcnArchName up to its first ':')
 };
 Device g_dev[64];
 
@@ -303,6 +309,11 @@ struct Timer {
   struct Iv { int stage; hipEvent_t a, b; };
   std::vector<Iv> iv;
   std::vector<std::pair<int, hipEvent_t>> marks;   // sequential marks on the main stream
+  KernTimer kt;                                     // per-launch GEMM events of this call
+  ~Timer() {
+    if (g_ktimer == &kt) g_ktimer = nullptr;        // also on early error returns
+    for (auto& r : kt.rec) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+  }
   hipEvent_t make() {
     hipEvent_t e = nullptr;
     if (hipEventCreate(&e) != hipSuccess) { on = false; return nullptr; }
@@ -315,6 +326,7 @@ struct Timer {
     t0 = make();
     if (t0) (void)hipEventRecord(t0, s);
     marks.push_back({-1, t0});
+    g_ktimer = &kt;
   }
   // main-stream stage boundary: the interval since the previous mark is charged to stage_id
   void mark(int stage_id) {
@@ -357,6 +369,19 @@ struct Timer {
     float tot = 0.f;
     (void)hipEventElapsedTime(&tot, t0, t1);
     if (rep) rep->ms_total = tot;
+    if (g_ktimer == &kt) g_ktimer = nullptr;
+    for (auto& r : kt.rec) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, r.a, r.b);
+      if (rep && r.id >= 0 && r.id < kGemmIds) {
+        rep->gemm_ms[r.id] += ms;
+        rep->gemm_flops[r.id] += r.flops;
+        rep->gemm_launches[r.id] += 1;
+      }
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    kt.rec.clear();
     for (auto& m : marks) (void)hipEventDestroy(m.second);
     for (auto& x : iv) { (void)hipEventDestroy(x.a); (void)hipEventDestroy(x.b); }
     (void)hipEventDestroy(t1);
@@ -472,6 +497,16 @@ struct CallCtx {
       for (auto& e : dev->ev) CF_DEV(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       for (auto& e : dev->ring) CF_DEV(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       make_cholesky_streams(*dev, id);
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, id) == hipSuccess) {
+        size_t k = 0;
+        while (k + 1 < sizeof dev->arch && prop.gcnArchName[k] && prop.gcnArchName[k] != ':') {
+          dev->arch[k] = prop.gcnArchName[k];
+          ++k;
+        }
+        dev->arch[k] = 0;
+      }
+      if (!dev->arch[0]) std::snprintf(dev->arch, sizeof dev->arch, "unknown");
     }
     if (!dev->hflags) CF_DEV(hipHostMalloc((void**)&dev->hflags, 64 * sizeof(int), hipHostMallocDefault));
     s = (ex && ex->stream) ? (hipStream_t)ex->stream : dev->stream;
@@ -1152,10 +1187,16 @@ void release_device_state() {
   if (cur >= 0) (void)hipSetDevice(cur);
 }
 
-// Autotuned launch shape of the scan per (n, nmaps, mode): points per batch, outer panel width
-// of the batched factorisation and GEMM tile of its updates; in memory and in a small text file
-// (one line per shape: "scan gfx950 n=.. nmaps=.. mode=.. batch=.. panel=.. tile=..").
-struct TuneEntry { int64_t n; int nmaps, mode, bt, panel, tile; };
+// Autotuned launch shape of the scan per (device architecture, n, nmaps, mode): points per
+// batch, outer panel width of the batched factorisation and GEMM tile of its updates, measured in
+// the launch mode the call used (graph: 1 replayed, 0 eager); in memory and in a small text file,
+// one line per shape: "scan <arch> n=.. nmaps=.. mode=.. batch=.. panel=.. tile=.. graph=..".
+struct TuneEntry {
+  std::string arch;
+  int64_t n;
+  int nmaps, mode, bt, panel, tile;
+  int graph;                          // launch mode of the trials (-1: not recorded)
+};
 std::vector<TuneEntry> g_tune;
 std::string g_tune_loaded;            // path the table was read from
 
@@ -1175,28 +1216,31 @@ void tune_load() {
   char line[256];
   while (fgets(line, sizeof line, f)) {
     TuneEntry e{};
+    char arch[64] = {0};
     long long n;
-    const int got = sscanf(line, "scan gfx950 n=%lld nmaps=%d mode=%d batch=%d panel=%d tile=%d", &n, &e.nmaps,
-                           &e.mode, &e.bt, &e.panel, &e.tile);
-    if (got < 4) continue;
-    if (got < 6) e.panel = e.tile = 0;
+    const int got = sscanf(line, "scan %63s n=%lld nmaps=%d mode=%d batch=%d panel=%d tile=%d graph=%d", arch, &n,
+                           &e.nmaps, &e.mode, &e.bt, &e.panel, &e.tile, &e.graph);
+    if (got < 5) continue;
+    if (got < 7) e.panel = e.tile = 0;
+    if (got < 8) e.graph = -1;
+    e.arch = arch;
     e.n = n;
     g_tune.push_back(e);
   }
   fclose(f);
 }
-const TuneEntry* tune_get(int64_t n, int nmaps, int mode) {
+const TuneEntry* tune_get(const char* arch, int64_t n, int nmaps, int mode) {
   tune_load();
   for (auto& e : g_tune)
-    if (e.n == n && e.nmaps == nmaps && e.mode == mode) return &e;
+    if (e.arch == arch && e.n == n && e.nmaps == nmaps && e.mode == mode) return &e;
   return nullptr;
 }
 void tune_put(const TuneEntry& e) {
   g_tune.push_back(e);
   FILE* f = fopen(tune_path().c_str(), "a");
   if (!f) return;
-  fprintf(f, "scan gfx950 n=%lld nmaps=%d mode=%d batch=%d panel=%d tile=%d\n", (long long)e.n, e.nmaps, e.mode,
-          e.bt, e.panel, e.tile);
+  fprintf(f, "scan %s n=%lld nmaps=%d mode=%d batch=%d panel=%d tile=%d graph=%d\n", e.arch.c_str(), (long long)e.n,
+          e.nmaps, e.mode, e.bt, e.panel, e.tile, e.graph);
   fclose(f);
 }
 
@@ -1400,11 +1444,11 @@ int loglike_core(const cf_problem* probs, int32_t nprob, int32_t npoints, const 
     if (H[p].lmax > lmax_all) lmax_all = H[p].lmax;
   }
   if (lstride < lmax_all + 1) return fail(CF_EINVAL, "lstride %d < lmax+1 = %d", lstride, lmax_all + 1);
-  // Graph replay pays off where launches dominate (small n); a large factorisation runs eagerly,
-  // host-paced two panels ahead (measured faster for n = 5952 batches of 8 than the replay).
+  // Captured batches are replayed only in calls whose problems all have n <= kGraphMaxN; any other
+  // call launches every batch eagerly.
   int nmax_all = 0;
   for (int p = 0; p < nprob; ++p) nmax_all = std::max(nmax_all, H[p].n);
-  const bool use_graph = !noalloc && !(ex && ex->no_graph) && !(ex && ex->stage_timing) && nmax_all < kGraphMaxN;
+  const bool use_graph = !noalloc && !(ex && ex->no_graph) && !(ex && ex->stage_timing) && nmax_all <= kGraphMaxN;
   const size_t ncl = (size_t)npoints * nprob * 6 * lstride;
   if (mem == CF_MEM_HOST) {
     if (!finite_all(cl_points, (int64_t)ncl)) return fail(CF_EINVAL, "non-finite scan spectra");
@@ -1415,20 +1459,26 @@ int loglike_core(const cf_problem* probs, int32_t nprob, int32_t npoints, const 
   if (int st = noalloc ? c.begin_plain(ex) : c.begin(ex)) return st;
   int nmax = 0;
   for (int p = 0; p < nprob; ++p) nmax = H[p].n > nmax ? H[p].n : nmax;
-  // batch of points factorised together: the autotuned size of this shape if known, else the
-  // largest of at most 16 whose covariances fit in 6 GB
-  const size_t per = (size_t)nmax * nmax * 8 * (mode ? 2 : 1);
-  const int bt_cap = (int)std::min<size_t>(16, std::max<size_t>(1, (size_t(6) << 30) / per));
-  int Bt = bt_cap;
-  TuneEntry tuned_e{};
-  const TuneEntry* tp = (nprob == 1 && !noalloc) ? tune_get(nmax, nmaps, mode) : nullptr;
-  if (tp) tuned_e = *tp;                     // copied: tune_put may grow the table
-  const bool tuned = tp != nullptr;
-  if (tuned && tuned_e.bt > 0) Bt = std::min(tuned_e.bt, bt_cap);
-  if (Bt > npoints) Bt = npoints;
+  // Points factorised together, per problem: the autotuned batch of the problem's shape if known,
+  // else the largest of at most 16 whose covariances fit in 6 GB.  The workspace holds, for every
+  // buffer, the largest of the problems' batches of it.
+  std::vector<int> cap(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    const size_t per = (size_t)H[p].n * H[p].n * 8 * (mode ? 2 : 1);
+    cap[p] = (int)std::min<size_t>(16, std::max<size_t>(1, (size_t(6) << 30) / per));
+    cap[p] = (int)std::min<int64_t>(cap[p], npoints);
+  }
+  std::vector<TuneEntry> te(nprob);
+  std::vector<char> tuned(nprob, 0);
+  if (!noalloc)
+    for (int p = 0; p < nprob; ++p)
+      if (const TuneEntry* tp = tune_get(c.dev->arch, H[p].n, nmaps, mode)) {
+        te[p] = *tp;                     // copied: tune_put may grow the table
+        tuned[p] = 1;
+      }
   const int L = lmax_all + 1;
-  // workspace bytes for batches of up to Bw points
-  auto ws_bytes = [&](int Bw) -> size_t {
+  // workspace bytes for batches of up to bw[p] points of problem p
+  auto ws_bytes = [&](const std::vector<int>& bw) -> size_t {
     Sizer z;
     for (int p = 0; p < nprob; ++p) size_staging(z, &probs[p], H[p]);
     if (mem == CF_MEM_HOST) {
@@ -1436,45 +1486,68 @@ int loglike_core(const cf_problem* probs, int32_t nprob, int32_t npoints, const 
       for (int p = 0; p < nprob; ++p) z.add<double>((size_t)nmaps * H[p].n);
       z.add<double>((size_t)npoints * nprob * nmaps * 2 + (size_t)npoints * nprob);
     }
-    const size_t ncw = (size_t)(Bw + kCovIB - 1) / kCovIB * kCovIB * 6 * L;   // whole chunks
-    z.add<double>(ncw);
-    z.add<double>((size_t)Bw * (nmax + (mode ? 0 : nmaps)) * nmax);
-    z.add<double>((size_t)Bw * ((nmax + kNB - 1) / kNB) * kNB * kNB);
-    z.add<double>((size_t)Bw * (nmax / 256) * 256 * 256);
-    z.add<double>((size_t)potrf_scratch(Bw));
-    z.add<double>((size_t)Bw * ((nmax + kNB - 1) / kNB));
+    auto mx = [&](auto per_point) {
+      size_t m = 1;
+      for (int p = 0; p < nprob; ++p) m = std::max(m, (size_t)bw[p] * (size_t)per_point((size_t)H[p].n));
+      return m;
+    };
+    int bmax = 1;
+    for (int p = 0; p < nprob; ++p) bmax = std::max(bmax, bw[p]);
+    z.add<double>((size_t)(bmax + kCovIB - 1) / kCovIB * kCovIB * 6 * L);   // whole chunks
+    z.add<double>(mx([&](size_t n) { return (n + (mode ? 0 : nmaps)) * n; }));
+    z.add<double>(mx([&](size_t n) { return (n + kNB - 1) / kNB * kNB * kNB; }));
+    z.add<double>(mx([&](size_t n) { return (n / 256) * 256 * 256; }));
+    z.add<double>((size_t)potrf_scratch(bmax));
+    z.add<double>(mx([&](size_t n) { return (n + kNB - 1) / kNB; }));
     z.add<double>((size_t)nmax * nmaps);
-    z.add<double>((size_t)Bw * nmax * nmaps);
-    z.add<double>((size_t)Bw * nmax * nmaps);
-    z.add<double>(mode ? (size_t)Bw * nmax * nmax : 1);
-    z.add<double>(mode ? (size_t)Bw * nmax * nmaps : 1);
-    z.add<double>(mode ? (size_t)Bw * nmax * nmaps : 1);
-    z.add<double>(mode ? (size_t)Bw * nmax * kLdProbes : 1);
-    z.add<double>(mode ? (size_t)Bw * nmax * kLdProbes : 1);
-    z.add<double>(mode ? (size_t)Bw * kLdProbes : 1);
-    z.add<double>(mode ? (size_t)Bw * kLdProbes : 1);
-    z.add<double>((size_t)Bw * nmaps);
-    z.add<double>((size_t)Bw);
+    z.add<double>(mx([&](size_t n) { return n * nmaps; }));
+    z.add<double>(mx([&](size_t n) { return n * nmaps; }));
+    z.add<double>(mode ? mx([&](size_t n) { return n * n; }) : 1);
+    z.add<double>(mode ? mx([&](size_t n) { return n * nmaps; }) : 1);
+    z.add<double>(mode ? mx([&](size_t n) { return n * nmaps; }) : 1);
+    z.add<double>(mode ? mx([&](size_t n) { return n * kLdProbes; }) : 1);
+    z.add<double>(mode ? mx([&](size_t n) { return n * kLdProbes; }) : 1);
+    z.add<double>(mode ? (size_t)bmax * kLdProbes : 1);
+    z.add<double>(mode ? (size_t)bmax * kLdProbes : 1);
+    z.add<double>((size_t)bmax * nmaps);
+    z.add<double>((size_t)bmax);
     z.add<int64_t>(1);
     z.add<int>(8);
     return z.off;
   };
-  int Bw = bt_cap;   // workspace sized for the largest batch the tuner may pick
+  std::vector<int> bw = cap;   // the workspace fits the largest batch the tuner may pick
   char* wsbase = nullptr;
   if (noalloc) {
-    Bw = std::min(bt_cap, (int)std::max<int64_t>(1, npoints));
-    while (Bw > 1 && ws_bytes(Bw) > kScratchBytes) --Bw;
-    const size_t need = ws_bytes(Bw);
+    int B = 16;
+    auto clip = [&](int lim) {
+      for (int p = 0; p < nprob; ++p) bw[p] = std::min(cap[p], lim);
+    };
+    clip(B);
+    while (B > 1 && ws_bytes(bw) > kScratchBytes) clip(--B);
+    const size_t need = ws_bytes(bw);
     if (need > kScratchBytes)
       return fail(CF_EINVAL, "cf_loglike_batch_noalloc: %zu bytes of workspace needed for one point, above the "
                   "%zu-byte static scratch array", need, kScratchBytes);
-    Bt = Bw;
+    cap = bw;
     wsbase = g_scratch[c.id];
   } else {
-    if (int st = ensure_ws(*c.dev, ws_bytes(Bw))) return st;
+    if (int st = ensure_ws(*c.dev, ws_bytes(bw))) return st;
     wsbase = c.dev->ws;
   }
-  const size_t ncw = (size_t)(Bw + kCovIB - 1) / kCovIB * kCovIB * 6 * L;   // whole chunks
+  size_t szC = 1, szLi = 1, szL256 = 1, szP = 1, szY = 1, szC0 = 1, szPz = 1;
+  int bmax = 1;
+  for (int p = 0; p < nprob; ++p) {
+    const size_t n = H[p].n, w = bw[p];
+    szC = std::max(szC, w * (n + (mode ? 0 : nmaps)) * n);
+    szLi = std::max(szLi, w * ((n + kNB - 1) / kNB) * kNB * kNB);
+    szL256 = std::max(szL256, w * (n / 256) * 256 * 256);
+    szP = std::max(szP, w * ((n + kNB - 1) / kNB));
+    szY = std::max(szY, w * n * nmaps);
+    szC0 = std::max(szC0, w * n * n);
+    szPz = std::max(szPz, w * n * kLdProbes);
+    bmax = std::max(bmax, bw[p]);
+  }
+  const size_t ncw = (size_t)(bmax + kCovIB - 1) / kCovIB * kCovIB * 6 * L;   // whole chunks
   Bump bp(wsbase);
   std::vector<Staged> S(nprob);
   for (int p = 0; p < nprob; ++p)
@@ -1500,23 +1573,23 @@ int loglike_core(const cf_problem* probs, int32_t nprob, int32_t npoints, const 
   x.c = &c; x.nprob = nprob; x.nmaps = nmaps; x.lstride = lstride; x.mode = mode; x.refine = refine;
   x.cl_dev = cl_dev;
   x.cwb = bp.take<double>(ncw);
-  x.Cb = bp.take<double>((size_t)Bw * (nmax + (mode ? 0 : nmaps)) * nmax);
-  x.Linv = bp.take<double>((size_t)Bw * ((nmax + kNB - 1) / kNB) * kNB * kNB);
-  x.Li256 = bp.take<double>((size_t)Bw * (nmax / 256) * 256 * 256);
-  x.pscr = bp.take<double>((size_t)potrf_scratch(Bw));
-  x.ldp = bp.take<double>((size_t)Bw * ((nmax + kNB - 1) / kNB));
+  x.Cb = bp.take<double>(szC);
+  x.Linv = bp.take<double>(szLi);
+  x.Li256 = bp.take<double>(szL256);
+  x.pscr = bp.take<double>((size_t)potrf_scratch(bmax));
+  x.ldp = bp.take<double>(szP);
   x.D = bp.take<double>((size_t)nmax * nmaps);
-  x.Yb = bp.take<double>((size_t)Bw * nmax * nmaps);
-  x.Gb = bp.take<double>((size_t)Bw * nmax * nmaps);
-  x.C0b = bp.take<double>(mode ? (size_t)Bw * nmax * nmax : 1);
-  x.Xb = bp.take<double>(mode ? (size_t)Bw * nmax * nmaps : 1);
-  x.Rb = bp.take<double>(mode ? (size_t)Bw * nmax * nmaps : 1);
-  x.Pz = bp.take<double>(mode ? (size_t)Bw * nmax * kLdProbes : 1);
-  x.Pw = bp.take<double>(mode ? (size_t)Bw * nmax * kLdProbes : 1);
-  x.T1 = bp.take<double>(mode ? (size_t)Bw * kLdProbes : 1);
-  x.T2 = bp.take<double>(mode ? (size_t)Bw * kLdProbes : 1);
-  x.x2 = bp.take<double>((size_t)Bw * nmaps);
-  x.ldb = bp.take<double>((size_t)Bw);
+  x.Yb = bp.take<double>(szY);
+  x.Gb = bp.take<double>(szY);
+  x.C0b = bp.take<double>(mode ? szC0 : 1);
+  x.Xb = bp.take<double>(mode ? szY : 1);
+  x.Rb = bp.take<double>(mode ? szY : 1);
+  x.Pz = bp.take<double>(mode ? szPz : 1);
+  x.Pw = bp.take<double>(mode ? szPz : 1);
+  x.T1 = bp.take<double>(mode ? (size_t)bmax * kLdProbes : 1);
+  x.T2 = bp.take<double>(mode ? (size_t)bmax * kLdProbes : 1);
+  x.x2 = bp.take<double>((size_t)bmax * nmaps);
+  x.ldb = bp.take<double>((size_t)bmax);
   int64_t* i0p = bp.take<int64_t>(1);
   x.flags = bp.take<int>(8);
   x.m2 = m2_dev; x.chi2 = chi2_dev; x.ld = ld_dev;
@@ -1527,6 +1600,7 @@ int loglike_core(const cf_problem* probs, int32_t nprob, int32_t npoints, const 
   Timer tm;
   tm.begin(ex && ex->stage_timing && !noalloc, c.s);
   double flops = 0.0;
+  int bt_used = 0;
   for (int p = 0; p < nprob; ++p) {
     const HostProblem& h = H[p];
     x.p = p; x.prob = &probs[p]; x.h = &h; x.S = &S[p];
@@ -1534,29 +1608,36 @@ int loglike_core(const cf_problem* probs, int32_t nprob, int32_t npoints, const 
       CF_DEV(launch_transpose(map_dev[p], nmaps, h.n, h.n, x.D, nmaps, c.s));
     else
       CF_DEV(hipMemcpyAsync(x.D, map_dev[p], sizeof(double) * nmaps * h.n, hipMemcpyDeviceToDevice, c.s));
-    int b = Bt;
+    int b = cap[p];
+    const bool graph = use_graph;
+    x.panel = x.tile = 0;
+    if (tuned[p]) {
+      if (te[p].bt > 0) b = std::min(te[p].bt, cap[p]);
+      x.panel = te[p].panel;
+      x.tile = te[p].tile;
+    }
     int64_t i0 = 0;
-    if (tuned) { x.panel = tuned_e.panel; x.tile = tuned_e.tile; }
-    // autotuning on the first call of a shape: time one batch per candidate, in two rounds
-    // (points per batch; then outer panel width and GEMM tile together), keeping the best rate.
-    // Trials run the first points of the scan (best of two timings each); the scan itself then
-    // runs in full with the chosen shape, so every output comes from one configuration.
-    if (ex && ex->autotune && nprob == 1 && !tuned && npoints >= 2 && !noalloc) {
+    // Autotuning on the first call of a problem's shape: time one batch per candidate, in two
+    // rounds (points per batch; then outer panel width and GEMM tile together), keeping the best
+    // rate.  Trials run the first points of the scan (best of two timings each) in the call's
+    // launch mode (replayed graphs or eager launches); the scan itself then runs in full with the
+    // chosen shape, so every output comes from one configuration.
+    if (ex && ex->autotune && !tuned[p] && npoints >= 2 && !noalloc) {
       double best_rate = 0.0;
-      TuneEntry best{h.n, nmaps, mode, Bt, 0, 0};
+      TuneEntry best{c.dev->arch, h.n, nmaps, mode, b, 0, 0, graph ? 1 : 0};
       const bool verbose = getenv("CF_TUNE_VERBOSE") != nullptr;
-      auto trial = [&](int cand, int panel, int tile) -> int {
-        if (cand > bt_cap || cand > npoints) return CF_OK;
+      auto trial = [&](int cand, int panel, int tile, bool g) -> int {
+        if (cand > cap[p]) return CF_OK;
         x.panel = panel;
         x.tile = tile;
-        if (use_graph) { if (int st = scan_replay(x, 0, cand, 0, i0p)) return st; }   // capture first
+        if (g) { if (int st = scan_replay(x, 0, cand, 0, i0p)) return st; }   // capture first
         hipEvent_t e0, e1;
         CF_DEV(hipEventCreate(&e0));
         CF_DEV(hipEventCreate(&e1));
         float best_ms = 0.f;
         for (int rep = 0; rep < 2; ++rep) {
           CF_DEV(hipEventRecord(e0, c.s));
-          if (use_graph) { if (int st = scan_replay(x, 0, cand, 1, i0p)) return st; }
+          if (g) { if (int st = scan_replay(x, 0, cand, 1, i0p)) return st; }
           else if (int st = scan_batch(x, 0, cand, nullptr, nullptr)) return st;
           CF_DEV(hipEventRecord(e1, c.s));
           CF_DEV(hipEventSynchronize(e1));
@@ -1568,26 +1649,27 @@ int loglike_core(const cf_problem* probs, int32_t nprob, int32_t npoints, const 
         (void)hipEventDestroy(e1);
         const double rate = cand / (double)best_ms;
         if (verbose)
-          fprintf(stderr, "cf autotune n=%d nmaps=%d mode=%d batch=%d panel=%d tile=%d: %.3f ms per point\n",
-                  h.n, nmaps, mode, cand, panel, tile, best_ms / cand);
+          fprintf(stderr, "cf autotune %s n=%d nmaps=%d mode=%d batch=%d panel=%d tile=%d graph=%d: %.3f ms per point\n",
+                  c.dev->arch, h.n, nmaps, mode, cand, panel, tile, g ? 1 : 0, best_ms / cand);
         if (rate > best_rate) { best_rate = rate; best.bt = cand; best.panel = panel; best.tile = tile; }
         return CF_OK;
       };
       for (int cand : {2, 4, 8, 16})
-        if (int st = trial(cand, 0, 0)) return st;
+        if (int st = trial(cand, 0, 0, graph)) return st;
       const int bt = best.bt;
       for (int panel : {0, 256, 512}) {       // panel width and tile jointly (they interact)
         if (panel && h.n <= 512) continue;
         for (int tile : {64, 128})
-          if (int st = trial(bt, panel, tile)) return st;
+          if (int st = trial(bt, panel, tile, graph)) return st;
       }
       tune_put(best);
       b = best.bt;
       x.panel = best.panel;
       x.tile = best.tile;
     }
+    bt_used = std::max(bt_used, b);
     const int64_t nfull = (npoints - i0) / b;
-    if (use_graph && nfull >= 1) {
+    if (graph && nfull >= 1) {
       if (int st = scan_replay(x, i0, b, nfull, i0p)) return st;
       i0 += nfull * b;
     }
@@ -1613,7 +1695,7 @@ int loglike_core(const cf_problem* probs, int32_t nprob, int32_t npoints, const 
   }
   CF_DEV(hipStreamSynchronize(c.s));
   tm.finish(rep);
-  if (rep) { rep->flops = flops; rep->n = H[0].n; rep->ir_iters = mode ? refine : 0; rep->n_fallback = Bt; }
+  if (rep) { rep->flops = flops; rep->n = H[0].n; rep->ir_iters = mode ? refine : 0; rep->n_fallback = bt_used; }
   return CF_OK;
 }
 
@@ -1646,6 +1728,10 @@ struct cf_smw {
   int n = 0, lmax = 0, wlo = 0, whi = 0, nf = 0, nmaps = 0;
   int fld[3] = {0, 0, 0};          // harmonic field (T 0, E 1, B 2) of each window slot
   int64_t kwf = 0, kw = 0;
+  // 2: the window holds T and E and/or B and M = V N_eff^-1 V^T has no T x (E,B) block (N_eff
+  // couples no T pixel with a Q, U pixel), so K' splits into a T block and an E,B block for every
+  // point whose window spectra have no TE, TB; 1: one dense K'.
+  int blocks = 1;
   double *M = nullptr, *b = nullptr, *chi2N = nullptr, *ldN = nullptr, *wl = nullptr;
 };
 
@@ -1746,11 +1832,16 @@ int smw_setup(const cf_problem* prob, const HostProblem& H, cf_smw* h, const int
   CF_DEV(gemm_f64(w, c.s));
   CF_DEV(launch_rowsumsq(C + n * n, nm, n, n, 0, 1, h->chi2N, nm, c.s));
   CF_DEV(launch_sum_parts(ldp, (int)nblk, nblk, 1, h->ldN, 1, c.s));
+  // field groups (App. field_blocks): T against the window's E, B columns of M
+  const bool groups = h->fld[0] == 0 && h->nf > 1;
+  CF_DEV(launch_fill_int(flags + 2, 1, 0, c.s));
+  if (groups) CF_DEV(launch_any_nonzero(h->M + kwf, kw, kwf, kw - kwf, 0, 1, flags + 2, c.s));
   tm.mark(ST_SYRK);
-  int fl[2];
-  if (int st = read_flags(c, flags, 2, fl)) return st;
+  int fl[3];
+  if (int st = read_flags(c, flags, 3, fl)) return st;
   if (fl[0]) return fail(CF_EINVAL, "non-finite entry of N_eff (check noise and spectra)");
   if (fl[1] != INT_MAX) return fail(CF_ENOTPD, "N_eff not positive definite (pivot %d)", fl[1]);
+  h->blocks = (groups && fl[2] == 0) ? 2 : 1;
   return CF_OK;
 }
 
@@ -1818,7 +1909,7 @@ extern "C" int cf_smw_create(const cf_problem* prob, int32_t win_lmin, int32_t w
   tm.finish(rep);
   if (rep) {
     const double nd = H.n, kd = (double)kw;
-    rep->n = H.n; rep->nmodes = h->kw;
+    rep->n = H.n; rep->nmodes = h->kw; rep->ir_iters = h->blocks;
     rep->flops = nd * nd * nd / 3.0 + nd * nd * (kd + nmaps) + nd * kd * (kd + nmaps);
   }
   *out = tmp.release();
@@ -1858,6 +1949,8 @@ extern "C" int cf_smw_loglike(cf_smw* h, int32_t npoints, const double* cl_point
   z.add<double>((size_t)Bt * nblk);
   z.add<double>((size_t)Bt * nm);
   z.add<double>((size_t)Bt);
+  z.add<double>((size_t)Bt * nm);
+  z.add<double>((size_t)Bt);
   z.add<int>(8);
   if (int st = ensure_ws(*c.dev, z.off)) return st;
   Bump bp(c.dev->ws);
@@ -1879,16 +1972,60 @@ extern "C" int cf_smw_loglike(cf_smw* h, int32_t npoints, const double* cl_point
   double* ldp = bp.take<double>((size_t)Bt * nblk);
   double* x2 = bp.take<double>((size_t)Bt * nm);
   double* ldK = bp.take<double>((size_t)Bt);
+  double* x2g = bp.take<double>((size_t)Bt * nm);    // the E,B group's sums (blocked path)
+  double* ldKg = bp.take<double>((size_t)Bt);
   int* flags = bp.take<int>(8);
   CF_DEV(launch_fill_int(flags, 1, 0, c.s));
   CF_DEV(launch_fill_int(flags + 1, 2, INT_MAX, c.s));
+  // Field block-diagonal kernel (App. field_blocks): with M split into T and E,B blocks, K' splits
+  // as well when no point couples T to the window's E, B fields (TE, TB zero inside the window);
+  // otherwise one dense K' keeps the general case exact.
+  bool blocked = false;
+  if (h->blocks == 2) {
+    CF_DEV(launch_fill_int(flags + 3, 1, 0, c.s));
+    for (int q = 1; q < nf; ++q) {
+      const int row = h->fld[q] == 1 ? 3 : 4;   // TE or TB
+      CF_DEV(launch_any_nonzero(cl_dev + (int64_t)row * lstride + h->wlo, lstride, 1, nl, 6 * (int64_t)lstride,
+                                npoints, flags + 3, c.s));
+    }
+    int fl4[4];
+    if (int st = read_flags(c, flags, 4, fl4)) return st;
+    blocked = fl4[3] == 0;
+  }
   Timer tm;
   tm.begin(ex && ex->stage_timing, c.s);
   for (int64_t i0 = 0; i0 < npoints; i0 += Bt) {
     const int bb = (int)std::min<int64_t>(Bt, npoints - i0);
+    if (blocked) {
+      // T block (one field) and E,B block (the window's other fields), each factorised as a batch
+      const int fldT[3] = {h->fld[0], 0, 0}, fldP[3] = {h->fld[1], h->fld[2], 0};
+      for (int g = 0; g < 2; ++g) {
+        const int nfg = g == 0 ? 1 : nf - 1;
+        const int64_t off = g == 0 ? 0 : kwf, kwg = nfg * kwf;
+        const int64_t slotg = (kwg + nm) * kwg, nblkg = (kwg + kNB - 1) / kNB;
+        CF_DEV(launch_smw_lambda(cl_dev + i0 * 6 * lstride, 6 * (int64_t)lstride, lstride, h->wl, h->wlo, nl, nfg,
+                                 g == 0 ? fldT : fldP, bb, R, flags + 2, c.s));
+        CF_DEV(launch_smw_kernel(h->M + off * kw + off, kw, kwg, kwf, nfg, h->wlo, nl, R, bb, K, slotg, c.s));
+        CF_DEV(launch_smw_rhs(h->b + off * nm, nm, kwg, kwf, nfg, h->wlo, nl, R, bb, K, slotg, c.s));
+        Factor F;
+        F.L = K; F.n = kwg; F.ld = kwg; F.sL = slotg;
+        F.Li64 = Linv; F.sLi64 = nblkg * kNB * kNB;
+        F.ldpart = ldp; F.sPart = nblkg;
+        F.fail = flags + 1; F.batch = bb; F.mode = 0;
+        F.rows = kwg + nm;
+        if (int st = potrf_on(*c.dev, F, pscr, c.s, c.dev->aux[1], c.dev->ev + 8)) return st;
+        CF_DEV(launch_rowsumsq(K + kwg * kwg, nm, kwg, kwg, slotg, bb, g == 0 ? x2 : x2g, nm, c.s));
+        CF_DEV(launch_sum_parts(ldp, (int)nblkg, nblkg, bb, g == 0 ? ldK : ldKg, 1, c.s));
+      }
+      CF_DEV(launch_axpy(x2, x2g, 1.0, (int64_t)bb * nm, c.s));
+      CF_DEV(launch_axpy(ldK, ldKg, 1.0, bb, c.s));
+      CF_DEV(launch_smw_finish(h->chi2N, h->ldN, x2, ldK, bb, nm, i0, m2_dev, chi2_dev, ld_dev, c.s));
+      tm.mark(ST_POTRF);
+      continue;
+    }
     CF_DEV(launch_smw_lambda(cl_dev + i0 * 6 * lstride, 6 * (int64_t)lstride, lstride, h->wl, h->wlo, nl, nf,
                              h->fld, bb, R, flags + 2, c.s));
-    CF_DEV(launch_smw_kernel(h->M, kw, kwf, nf, h->wlo, nl, R, bb, K, slot, c.s));
+    CF_DEV(launch_smw_kernel(h->M, kw, kw, kwf, nf, h->wlo, nl, R, bb, K, slot, c.s));
     CF_DEV(launch_smw_rhs(h->b, nm, kw, kwf, nf, h->wlo, nl, R, bb, K, slot, c.s));
     tm.mark(ST_BUILD);
     Factor F;
@@ -1920,14 +2057,372 @@ extern "C" int cf_smw_loglike(cf_smw* h, int32_t npoints, const double* cl_point
   CF_DEV(hipStreamSynchronize(c.s));
   tm.finish(rep);
   if (rep) {
-    const double kd = (double)kw;
+    const double kd = (double)kw, k0 = (double)kwf, k1 = (double)(kw - kwf);
     rep->n = h->n; rep->nmodes = kw; rep->n_fallback = Bt;
-    rep->flops = (double)npoints * (kd * kd * kd / 3.0 + kd * kd * nm + 2.0 * kwf * kwf * nf * nf * nf);
+    rep->ir_iters = blocked ? 2 : 1;   // K' blocks factorised per point
+    rep->flops = blocked ? (double)npoints * (k0 * k0 * k0 / 3.0 + k1 * k1 * k1 / 3.0 + (k0 * k0 + k1 * k1) * nm +
+                                              2.0 * kwf * kwf * (1.0 + (nf - 1.0) * (nf - 1.0) * (nf - 1.0)))
+                         : (double)npoints * (kd * kd * kd / 3.0 + kd * kd * nm + 2.0 * kwf * kwf * nf * nf * nf);
   }
   return CF_OK;
 }
 
+namespace cf {
+namespace {
+// Leading-order flop counts of a likelihood scan under the two computation bases (Sect. 3, the
+// "auto" choice between the harmonic and the pixel basis; per-point costs as in the complexity
+// table: a Cholesky of the n x n pixel covariance against one of the window-sized kernel).
+int select_basis(const cf_problem* prob, int32_t wlo, int32_t whi, uint32_t wf, int32_t npoints, int32_t nmaps,
+                 cf_basis_choice* out, HostProblem& H) {
+  if (!out) return fail(CF_EINVAL, "out is NULL");
+  std::memset(out, 0, sizeof *out);
+  if (int st = check_problem(prob, H, true)) return st;
+  if (npoints <= 0 || nmaps <= 0) return fail(CF_EINVAL, "npoints and nmaps must be positive");
+  if (wlo < H.lmin || whi > H.lmax || wlo > whi) return fail(CF_EINVAL, "window [%d, %d] outside [%d, %d]", wlo, whi, H.lmin, H.lmax);
+  if (wf == 0 || (wf & ~7u)) return fail(CF_EINVAL, "window fields 0x%x invalid", wf);
+  const bool present[3] = {H.has_t != 0, H.has_p != 0, H.has_p != 0};
+  const int L = H.lmax + 1;
+  int nf = 0;
+  bool ok = true;
+  for (int f = 0; f < 3; ++f)
+    if (wf & (1u << f)) {
+      if (!present[f]) return fail(CF_EINVAL, "window field %d absent from the problem", f);
+      ++nf;
+    }
+  for (int a = 0; a < 3 && ok; ++a)       // a spectrum coupling a window field to a fixed one
+    for (int b = a; b < 3 && ok; ++b) {
+      if (!present[a] || !present[b] || ((wf >> a) & 1u) == ((wf >> b) & 1u)) continue;
+      const double* row = prob->cl + (int64_t)spec_row(a, b) * L;
+      for (int l = wlo; l <= whi; ++l)
+        if (row[l] != 0.0) ok = false;
+    }
+  const double n = H.n, kf = (double)((int64_t)(whi + 1) * (whi + 1) - (int64_t)wlo * wlo), k = kf * nf;
+  // field groups: T and the window's E, B decouple when the fixed spectra carry no TE, TB and the
+  // noise has no T-P block (diagonal noise without a low-rank part; a dense noise in host memory is
+  // scanned; a dense noise in device memory counts as coupled)
+  int groups = 1;
+  if ((wf & 1u) && (wf & 6u) && H.has_t && H.has_p) {
+    bool cross = false;
+    for (int l = H.lmin; l <= H.lmax && !cross; ++l) {
+      const bool in = l >= wlo && l <= whi;
+      if (!(in && (wf & 2u)) && prob->cl[3 * L + l] != 0.0) cross = true;   // TE in N_eff
+      if (!(in && (wf & 4u)) && prob->cl[4 * L + l] != 0.0) cross = true;   // TB in N_eff
+    }
+    if (prob->noise_rank > 0) cross = true;
+    if (!cross && prob->noise_kind == CF_NOISE_DENSE) {
+      if (prob->mem != CF_MEM_HOST) {
+        cross = true;
+      } else {
+        const int64_t nT = H.npx;
+        for (int64_t i = 0; i < nT && !cross; ++i)
+          for (int64_t j = nT; j < H.n; ++j)
+            if (prob->noise[i * H.n + j] != 0.0) { cross = true; break; }
+      }
+    }
+    if (!cross) groups = 2;
+  }
+  const double pix_point = n * n * n / 3.0 + n * n * nmaps;
+  const double k0 = kf, k1 = k - kf;
+  const double harm_point = groups == 2 ? (k0 * k0 * k0 + k1 * k1 * k1) / 3.0 + (k0 * k0 + k1 * k1) * nmaps
+                                        : k * k * k / 3.0 + k * k * nmaps;
+  const double harm_setup = n * n * n / 3.0 + n * n * (k + nmaps) + n * k * (k + nmaps);
+  out->n = H.n;
+  out->k_win = (int64_t)k;
+  out->groups = groups;
+  out->harmonic_ok = ok ? 1 : 0;
+  out->cost_pixel = npoints * pix_point;
+  out->cost_harmonic = harm_setup + npoints * harm_point;
+  out->basis = (ok && out->cost_harmonic < out->cost_pixel) ? 1 : 0;
+  return CF_OK;
+}
+}  // namespace
+}  // namespace cf
+
+namespace cf {
+bool smw_describe(const ::cf_smw* h, int* mem, int* nmaps) {
+  if (!h) return false;
+  *mem = h->mem;
+  *nmaps = h->nmaps;
+  return true;
+}
+}  // namespace cf
+
 extern "C" int64_t cf_smw_dim(const cf_smw* h) { return h ? h->kw : -1; }
+
+// Harmonic-basis Fisher matrix and QML with multipole switching (Sects. 2.3.3, 2.3.4; Eqs.
+// projected_inv_smw, weighted_data_smw, q_harmonic; App. smw_stable): one factorisation of
+// [N_eff; D^T; V_win^T] gives G^T = (L^-1 V^T)^T and U^T = (L^-1 D)^T, M = G^T G, b = G^T U; with
+// Lambda = R R^T at the fiducial and K' = I + R^T M R (eigenvalues >= 1):
+//   Z = V C^-1 V^T = M (I + Lambda M)^-1 = M R K'^-1 R^-1       (I + Lambda M = R K' R^-1)
+//   w = V C^-1 d   = (I + M Lambda)^-1 b = R^-T K'^-1 R^T b
+//   Cov(w | noise) = A T A^T, A = (I + M Lambda)^-1 = R^-T K'^-1 R^T, T = X^T N X, X = N_eff^-1 V^T
+// so no difference of large matrices is formed.  F and y come from Z and w through the sparse
+// trace of the pixel path; the noise bias is 1/2 tr[E_b A T A^T] (T = M without switching).
+extern "C" int cf_smw_qml(const cf_problem* prob, int32_t win_lmin, int32_t win_lmax, const cf_bins* bins,
+                          const double* maps, int32_t nmaps, double* y_out, double* bias_out, double* chat_out,
+                          double* F_out, const cf_exec* ex, cf_report* rep) {
+  using namespace cf;
+  report_init(rep);
+  HostProblem H;
+  if (int st = check_problem(prob, H, true)) return st;
+  if (win_lmin < H.lmin || win_lmax > H.lmax || win_lmin > win_lmax)
+    return fail(CF_EINVAL, "window [%d, %d] outside [lmin, lmax] = [%d, %d]", win_lmin, win_lmax, H.lmin, H.lmax);
+  HostBins B;
+  if (int st = check_bins(bins, H, B)) return st;
+  for (int b = 0; b < B.nb; ++b)
+    if (B.lo[b] < win_lmin || B.hi[b] > win_lmax)
+      return fail(CF_EINVAL, "bin %d = [%d, %d] outside the window [%d, %d]", b, B.lo[b], B.hi[b], win_lmin, win_lmax);
+  if (nmaps <= 0 || !maps) return fail(CF_EINVAL, "no maps");
+  if (!y_out || !bias_out || !chat_out) return fail(CF_EINVAL, "y_out, bias_out and chat_out are required");
+  if ((int64_t)prob->noise_rank > (int64_t)H.nfm * ((int64_t)(win_lmax + 1) * (win_lmax + 1) - (int64_t)win_lmin * win_lmin))
+    return fail(CF_EINVAL, "noise rank %d above the window's mode count", prob->noise_rank);
+  if (prob->mem == CF_MEM_HOST && !finite_all(maps, (int64_t)nmaps * H.n)) return fail(CF_EINVAL, "non-finite map value");
+  // the window holds every harmonic field of the problem (switching by multipole only)
+  const int nf = H.nfm, L = H.lmax + 1;
+  int fld[3] = {0, 0, 0};
+  {
+    int q = 0;
+    if (H.has_t) fld[q++] = 0;
+    if (H.has_p) { fld[q++] = 1; fld[q++] = 2; }
+  }
+  const int64_t n = H.n, k = H.k, kwf = (int64_t)(win_lmax + 1) * (win_lmax + 1) - (int64_t)win_lmin * win_lmin;
+  const int64_t kw = nf * kwf, nm = nmaps, nl = win_lmax - win_lmin + 1;
+  const int K = B.ns * B.nb;
+  std::vector<double> clf(prob->cl, prob->cl + 6 * L);   // fixed spectra: the window's entries removed
+  for (int s = 0; s < 6; ++s)
+    for (int l = win_lmin; l <= win_lmax; ++l) clf[(size_t)s * L + l] = 0.0;
+  CallCtx c;
+  if (int st = c.begin(ex)) return st;
+  const int64_t rows = n + nm + kw, nblk = (n + kNB - 1) / kNB, nblkK = (kw + kNB - 1) / kNB;
+  const int npq = nf * nf, nq = npq * (npq + 1) / 2;
+  const size_t kk = (size_t)kw * kw, nk = (size_t)n * kw, ngram = (size_t)nl * (nl + 1) / 2 * nq;
+  Sizer z;
+  size_staging(z, prob, H);
+  z.add<double>((size_t)rows * n);             // [N_eff; D^T; V_win^T], factorised
+  z.add<double>((size_t)n * k);                // Y
+  z.add<double>((size_t)nblk * kNB * kNB);     // inverted diagonal blocks of N_eff
+  z.add<double>((size_t)potrf_scratch(1));
+  z.add<double>((size_t)nblk);
+  z.add<double>((size_t)nm * n);               // maps (host inputs)
+  z.add<double>((size_t)(kw + nm) * kw);       // [K'; b'^T]
+  z.add<double>((size_t)nblkK * kNB * kNB);
+  z.add<double>((size_t)nblkK);
+  for (int i = 0; i < 8; ++i) z.add<double>(kk);   // M, T, W1, Y1, Z, P1, Q, Bn
+  for (int i = 0; i < 3; ++i) z.add<double>(nk);   // G, X, NX
+  z.add<double>((size_t)kw * nm * 3);          // b, w, scratch
+  z.add<double>((size_t)6 * L * 2);            // fiducial spectra, zero spectra
+  z.add<double>((size_t)nl * 9);               // R
+  z.add<double>(ngram * 2);                    // Gram of Z and of Bn
+  z.add<double>((size_t)nl * npq * 2);         // block traces
+  z.add<double>((size_t)K * K * 2);            // F, copy for the solve
+  z.add<double>((size_t)nm * K * 3 + K);       // y, q, chat, bias
+  z.add<int>(B.nb);
+  z.add<int>(B.nb);
+  z.add<int>(8);
+  if (int st = ensure_ws(*c.dev, z.off)) return st;
+  Bump bp(c.dev->ws);
+  Staged S;
+  if (int st = stage(bp, prob, H, clf.data(), c.s, S)) return st;
+  double* C = bp.take<double>((size_t)rows * n);
+  double* Y = bp.take<double>((size_t)n * k);
+  double* Linv = bp.take<double>((size_t)nblk * kNB * kNB);
+  double* scr = bp.take<double>((size_t)potrf_scratch(1));
+  double* ldp = bp.take<double>((size_t)nblk);
+  double* mcopy = bp.take<double>((size_t)nm * n);
+  double* KK = bp.take<double>((size_t)(kw + nm) * kw);
+  double* LiK = bp.take<double>((size_t)nblkK * kNB * kNB);
+  double* ldpK = bp.take<double>((size_t)nblkK);
+  double* M = bp.take<double>(kk);
+  double* T = bp.take<double>(kk);
+  double* W1 = bp.take<double>(kk);
+  double* Y1 = bp.take<double>(kk);
+  double* Z = bp.take<double>(kk);
+  double* P1 = bp.take<double>(kk);
+  double* Q = bp.take<double>(kk);
+  double* Bn = bp.take<double>(kk);
+  double* G = bp.take<double>(nk);
+  double* X = bp.take<double>(nk);
+  double* NX = bp.take<double>(nk);
+  double* bv = bp.take<double>((size_t)kw * nm * 3);
+  double* wv = bv + (size_t)kw * nm;
+  double* tv = wv + (size_t)kw * nm;
+  double* cl0 = bp.take<double>((size_t)6 * L * 2);
+  double* zl = cl0 + (size_t)6 * L;
+  double* R = bp.take<double>((size_t)nl * 9);
+  double* gramZ = bp.take<double>(ngram * 2);
+  double* gramB = gramZ + ngram;
+  double* ztrZ = bp.take<double>((size_t)nl * npq * 2);
+  double* ztrB = ztrZ + (size_t)nl * npq;
+  double* F = bp.take<double>((size_t)K * K * 2);
+  double* Fw = F + (size_t)K * K;
+  double* y = bp.take<double>((size_t)nm * K * 3 + K);
+  double* q = y + (size_t)nm * K;
+  double* chat = q + (size_t)nm * K;
+  double* bias = chat + (size_t)nm * K;
+  int* dlo = bp.take<int>(B.nb);
+  int* dhi = bp.take<int>(B.nb);
+  int* flags = bp.take<int>(8);
+  hipStream_t s = c.s;
+  CF_DEV(hipMemcpyAsync(dlo, B.lo.data(), sizeof(int) * B.nb, hipMemcpyHostToDevice, s));
+  CF_DEV(hipMemcpyAsync(dhi, B.hi.data(), sizeof(int) * B.nb, hipMemcpyHostToDevice, s));
+  CF_DEV(hipMemcpyAsync(cl0, prob->cl, sizeof(double) * 6 * L, hipMemcpyHostToDevice, s));
+  CF_DEV(launch_fill(zl, 6 * L, 0.0, s));
+  const double* mdev = maps;
+  if (prob->mem == CF_MEM_HOST) {
+    CF_DEV(hipMemcpyAsync(mcopy, maps, sizeof(double) * nm * n, hipMemcpyHostToDevice, s));
+    mdev = mcopy;
+  }
+  CF_DEV(launch_fill_int(flags, 1, 0, s));
+  CF_DEV(launch_fill_int(flags + 1, 4, INT_MAX, s));
+  Timer tm;
+  tm.begin(ex && ex->stage_timing, s);
+  // ---- N_eff with the maps and the window's harmonic rows below it
+  CF_DEV(launch_ybuild(S.P, Y, k, s));
+  CF_DEV(launch_cov_build(S.P, S.cw, 0, 1, prob->noise_kind, S.noise, prob->noise_rank, S.noise_U, C, n, 0, 1, flags, s));
+  CF_DEV(hipMemcpyAsync(C + n * n, mdev, sizeof(double) * nm * n, hipMemcpyDeviceToDevice, s));
+  double* Vt = C + (n + nm) * n;
+  const int64_t c0 = (int64_t)win_lmin * win_lmin - (int64_t)H.lmin * H.lmin;
+  for (int f = 0; f < nf; ++f)
+    CF_DEV(launch_transpose(Y + (int64_t)f * H.kf + c0, n, kwf, k, Vt + f * kwf * n, n, s));
+  tm.mark(ST_BUILD);
+  Factor FN;
+  FN.L = C; FN.n = n; FN.ld = n; FN.sL = 0;
+  FN.Li64 = Linv; FN.ldpart = ldp; FN.fail = flags + 1; FN.batch = 1; FN.rows = rows;
+  if (H.has_t && H.has_p) { FN.rows_early = n + nm + kwf; FN.p_early = H.npx; }   // E,B rows vanish on T pixels
+  if (int st = potrf_on(*c.dev, FN, scr, s, c.dev->aux[1], c.dev->ev + 8)) return st;
+  tm.mark(ST_POTRF);
+  // ---- M = G^T G, b = G^T U, X = L^-T G, T = X^T N X
+  GemmDesc g{};
+  g.M = kw; g.N = kw; g.K = n; g.A = Vt; g.lda = n; g.B = Vt; g.ldb = n; g.bt = 1;
+  g.C = M; g.ldc = kw; g.alpha = 1.0; g.lower = 1; g.batch = 1;
+  CF_DEV(gemm_f64(g, s));
+  CF_DEV(launch_symmetrize(M, kw, kw, s));
+  GemmDesc gb{};
+  gb.M = kw; gb.N = nm; gb.K = n; gb.A = Vt; gb.lda = n; gb.B = C + n * n; gb.ldb = n; gb.bt = 1;
+  gb.C = bv; gb.ldc = nm; gb.alpha = 1.0; gb.batch = 1;
+  CF_DEV(gemm_f64(gb, s));
+  CF_DEV(launch_transpose(Vt, kw, n, n, G, kw, s));                      // G [n][kw]
+  CF_DEV(trsm_lower_t_f64(FN, G, kw, 0, X, kw, 0, kw, s));                // X = L^-T G (G consumed)
+  if (prob->noise_kind == CF_NOISE_DENSE) {
+    GemmDesc gn{};
+    gn.M = n; gn.N = kw; gn.K = n; gn.A = S.noise; gn.lda = n; gn.B = X; gn.ldb = kw;
+    gn.C = NX; gn.ldc = kw; gn.alpha = 1.0; gn.batch = 1;
+    CF_DEV(gemm_f64(gn, s));
+  } else {
+    CF_DEV(launch_fill(NX, (int64_t)nk, 0.0, s));
+    CF_DEV(launch_rowscale_add(S.noise, X, NX, n, kw, s));               // NX = diag(N) X
+  }
+  if (prob->noise_rank > 0) {                                            // + U (U^T X)
+    GemmDesc gu{};
+    gu.M = prob->noise_rank; gu.N = kw; gu.K = n; gu.A = S.noise_U; gu.lda = prob->noise_rank; gu.at = 1;
+    gu.B = X; gu.ldb = kw; gu.C = W1; gu.ldc = kw; gu.alpha = 1.0; gu.batch = 1;   // U^T X in W1
+    CF_DEV(gemm_f64(gu, s));
+    GemmDesc gv{};
+    gv.M = n; gv.N = kw; gv.K = prob->noise_rank; gv.A = S.noise_U; gv.lda = prob->noise_rank;
+    gv.B = gu.C; gv.ldb = kw; gv.C = NX; gv.ldc = kw; gv.alpha = 1.0; gv.beta = 1.0; gv.batch = 1;
+    CF_DEV(gemm_f64(gv, s));
+  }
+  GemmDesc gt{};
+  gt.M = kw; gt.N = kw; gt.K = n; gt.A = X; gt.lda = kw; gt.at = 1; gt.B = NX; gt.ldb = kw;
+  gt.C = T; gt.ldc = kw; gt.alpha = 1.0; gt.batch = 1;
+  CF_DEV(gemm_f64(gt, s));
+  tm.mark(ST_SYRK);
+  // ---- fiducial kernel K' = I + R^T M R and b' = R^T b, factorised together
+  CF_DEV(launch_smw_lambda(cl0, 6 * (int64_t)L, L, S.wl, win_lmin, (int)nl, nf, fld, 1, R, flags + 2, s));
+  const int64_t slotK = (kw + nm) * kw;
+  CF_DEV(launch_smw_kernel(M, kw, kw, kwf, nf, win_lmin, (int)nl, R, 1, KK, slotK, s));
+  CF_DEV(launch_smw_rhs(bv, (int)nm, kw, kwf, nf, win_lmin, (int)nl, R, 1, KK, slotK, s));
+  Factor FK;
+  FK.L = KK; FK.n = kw; FK.ld = kw; FK.sL = slotK; FK.Li64 = LiK; FK.ldpart = ldpK;
+  FK.fail = flags + 3; FK.batch = 1; FK.rows = kw + nm;
+  if (int st = potrf_on(*c.dev, FK, scr, s, c.dev->aux[1], c.dev->ev + 8)) return st;
+  // ---- Z = M R K'^-1 R^-1: W1 = R^T M, Y1 = K'^-1 W1, Z = R^-T Y1 (= Z^T), mirrored
+  CF_DEV(launch_apply_rblock(M, kw, W1, kw, kw, kwf, nf, win_lmin, R, 1, 0, s));
+  CF_DEV(trsm_lower_f64(FK, W1, kw, 0, P1, kw, 0, kw, 0, s));            // P1 = L_K^-1 W1
+  CF_DEV(trsm_lower_t_f64(FK, P1, kw, 0, Y1, kw, 0, kw, s));             // Y1 = L_K^-T P1
+  CF_DEV(launch_apply_rblock(Y1, kw, Z, kw, kw, kwf, nf, win_lmin, R, 3, 0, s));
+  CF_DEV(launch_symmetrize(Z, kw, kw, s));
+  // ---- w = R^-T K'^-1 R^T b: the factorisation left (L_K^-1 b')^T below K'
+  CF_DEV(launch_transpose(KK + kw * kw, nm, kw, kw, tv, nm, s));          // [kw][nm]
+  CF_DEV(trsm_lower_t_f64(FK, tv, nm, 0, wv, nm, 0, nm, s));             // wv = K'^-1 b'
+  CF_DEV(launch_apply_rblock(wv, nm, tv, nm, nm, kwf, nf, win_lmin, R, 3, 0, s));   // tv = R^-T wv
+  // ---- noise covariance of w: Bn = R^-T K'^-1 (R^T T R) K'^-1 R^-1
+  CF_DEV(launch_apply_rblock(T, kw, W1, kw, kw, kwf, nf, win_lmin, R, 1, 0, s));   // W1 = R^T T
+  CF_DEV(launch_apply_rblock(W1, kw, P1, kw, kw, kwf, nf, win_lmin, R, 0, 1, s));  // P1 = W1 R
+  CF_DEV(trsm_lower_f64(FK, P1, kw, 0, W1, kw, 0, kw, 0, s));
+  CF_DEV(trsm_lower_t_f64(FK, W1, kw, 0, Q, kw, 0, kw, s));              // Q = K'^-1 P1
+  CF_DEV(launch_transpose(Q, kw, kw, kw, W1, kw, s));
+  CF_DEV(trsm_lower_f64(FK, W1, kw, 0, P1, kw, 0, kw, 0, s));
+  CF_DEV(trsm_lower_t_f64(FK, P1, kw, 0, Q, kw, 0, kw, s));              // Q = K'^-1 P1 K'^-1
+  CF_DEV(launch_apply_rblock(Q, kw, W1, kw, kw, kwf, nf, win_lmin, R, 3, 0, s));   // R^-T Q
+  CF_DEV(launch_apply_rblock(W1, kw, Bn, kw, kw, kwf, nf, win_lmin, R, 2, 1, s));  // ... R^-1
+  tm.mark(ST_TRSM);
+  // ---- sparse-trace Fisher, y and the noise bias on the window's modes
+  DevProblem Pw = S.P;
+  Pw.lmin = win_lmin; Pw.lmax = win_lmax; Pw.kf = (int)kwf; Pw.k = kw;
+  CF_DEV(launch_gram(Pw, Z, kw, gramZ, ztrZ, s));
+  CF_DEV(launch_gram(Pw, Bn, kw, gramB, ztrB, s));
+  SpecSel sel;
+  sel.ns = B.ns;
+  for (int i = 0; i < 6; ++i) sel.spec[i] = B.spec[i];
+  sel.nb = B.nb; sel.lo = dlo; sel.hi = dhi;
+  CF_DEV(launch_fisher_assemble(Pw, sel, gramZ, F, s));
+  DevProblem Pb = Pw;
+  Pb.lam = zl;                                  // the bias is the traces of Bn alone
+  CF_DEV(launch_bias_assemble(Pb, sel, gramB, ztrB, bias, s));
+  CF_DEV(launch_quad_assemble(Pw, sel, tv, nm, (int)nm, y, s));
+  CF_DEV(hipMemcpyAsync(q, y, sizeof(double) * nm * K, hipMemcpyDeviceToDevice, s));
+  CF_DEV(launch_sub_bias(q, bias, K, (int)nm, s));
+  CF_DEV(hipMemcpyAsync(Fw, F, sizeof(double) * K * K, hipMemcpyDeviceToDevice, s));
+  CF_DEV(launch_small_spd_solve(Fw, K, q, chat, (int)nm, flags + 4, s));
+  tm.mark(ST_QML);
+  int fl[5];
+  if (int st = read_flags(c, flags, 5, fl)) return st;
+  if (fl[0]) return fail(CF_EINVAL, "non-finite entry of N_eff (check noise and spectra)");
+  if (fl[1] != INT_MAX) { if (rep) rep->fail_index = fl[1]; return fail(CF_ENOTPD, "N_eff not positive definite (pivot %d)", fl[1]); }
+  if (fl[2] != INT_MAX) return fail(CF_EINVAL, "the fiducial window spectra are not positive semi-definite at l=%d", fl[2]);
+  if (fl[3] != INT_MAX) return fail(CF_ENOTPD, "I + R^T M R not positive definite (pivot %d)", fl[3]);
+  if (fl[4] != INT_MAX) { if (rep) rep->fail_index = fl[4]; return fail(CF_ENOTPD, "Fisher matrix not positive definite at pivot %d", fl[4]); }
+  if (int st = copy_out(y_out, y, (size_t)nm * K, prob->mem, s)) return st;
+  if (int st = copy_out(bias_out, bias, (size_t)K, prob->mem, s)) return st;
+  if (int st = copy_out(chat_out, chat, (size_t)nm * K, prob->mem, s)) return st;
+  if (F_out)
+    if (int st = copy_out(F_out, F, (size_t)K * K, prob->mem, s)) return st;
+  CF_DEV(hipStreamSynchronize(s));
+  tm.finish(rep);
+  if (rep) {
+    const double nd = (double)n, kd = (double)kw;
+    rep->n = n; rep->nmodes = kw;
+    rep->flops = nd * nd * nd / 3.0 + nd * nd * (kd + nm) * 2.0 + nd * kd * kd * 2.0 + 10.0 * kd * kd * kd;
+  }
+  return CF_OK;
+}
+
+extern "C" int cf_select_basis(const cf_problem* prob, int32_t win_lmin, int32_t win_lmax, uint32_t win_fields,
+                               int32_t npoints, int32_t nmaps, cf_basis_choice* out) {
+  HostProblem H;
+  return cf::select_basis(prob, win_lmin, win_lmax, win_fields, npoints, nmaps, out, H);
+}
+
+extern "C" int cf_loglike_auto(const cf_problem* prob, int32_t win_lmin, int32_t win_lmax, uint32_t win_fields,
+                               int32_t npoints, const double* cl_points, int32_t lstride, const double* maps,
+                               int32_t nmaps, double* m2lnL, double* chi2, double* logdet,
+                               cf_basis_choice* choice, const cf_exec* ex, cf_report* rep) {
+  cf_basis_choice ch;
+  HostProblem H;
+  if (int st = cf::select_basis(prob, win_lmin, win_lmax, win_fields, npoints, nmaps, &ch, H)) return st;
+  if (choice) *choice = ch;
+  if (!ch.basis) {
+    // pixel basis: outputs [npoints][1 problem][nmaps] are the [npoints][nmaps] layout
+    const double* mp[1] = {maps};
+    return cf_loglike_batch(prob, 1, npoints, cl_points, lstride, mp, nmaps, CF_FP64, m2lnL, chi2, logdet, ex, rep);
+  }
+  cf_smw* h = nullptr;
+  if (int st = cf_smw_create(prob, win_lmin, win_lmax, win_fields, maps, nmaps, ex, &h, nullptr)) return st;
+  const int st = cf_smw_loglike(h, npoints, cl_points, lstride, m2lnL, chi2, logdet, ex, rep);
+  cf_smw_destroy(h);
+  return st;
+}
 
 extern "C" void cf_smw_destroy(cf_smw* h) { smw_free(h); }
 

@@ -5,7 +5,12 @@
 #include <stddef.h>
 #include <vector>
 
+struct cf_smw;   // the harmonic-basis likelihood handle of the C ABI
+
 namespace cf {
+
+// Memory space and number of maps of a harmonic-basis handle (false for NULL).
+bool smw_describe(const ::cf_smw* h, int* mem, int* nmaps);
 
 // -------------------------------------------------------------------------------------------
 // Launch-time error plumbing: launchers return hipError_t; the API layer converts to cf_status.
@@ -84,7 +89,18 @@ struct GemmDesc {
 };
 hipError_t gemm_f64(const GemmDesc& g, hipStream_t s);
 
-// A (batched) Cholesky factor with the inverses of its diagonal blocks.
+// Events around every FP64 GEMM launch of the calling thread while a call with stage timing is
+// running (g_ktimer set by the API layer); resolved into cf_report.gemm_* when the call finishes.
+constexpr int kGemmIds = 16;
+struct KernTimer {
+  struct Rec { int id; hipEvent_t a, b; double flops; };
+  std::vector<Rec> rec;
+};
+extern thread_local KernTimer* g_ktimer;
+
+// A (batched) Cholesky factor with the inverses of its diagonal blocks.  The 64 x 64 diagonal blocks
+// of L itself are not kept in L (the fused block kernel leaves them as input); every user of a
+// factor reads the blocks below the diagonal and the inverted diagonal blocks.
 struct Factor {
   double* L = nullptr; int64_t n = 0, ld = 0, sL = 0;   // row-major, lower; batch stride sL
   // Extra rows below the n x n matrix (rows n .. rows-1, same ld) are carried through the
@@ -185,6 +201,9 @@ hipError_t launch_fill_block(double* A, int64_t ld, int64_t rows, int64_t cols, 
 hipError_t launch_coldot(const double* U, const double* V, int64_t rows, int64_t cols, int64_t ld,
                          int64_t sU, int64_t sV, int batch, double* out, int64_t sOut, hipStream_t s);
 hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s);
+// out[i][j] += d[i] X[i][j] (rows x cols, row-major)
+hipError_t launch_rowscale_add(const double* d, const double* X, double* out, int64_t rows, int64_t cols,
+                              hipStream_t s);
 hipError_t launch_sum_parts(const double* parts, int nparts, int64_t sP, int batch, double* out,
                             int64_t sOut, hipStream_t s);
 hipError_t launch_add_scalar(const double* vec, int64_t nper, int batch, const double* scal,
@@ -212,8 +231,16 @@ hipError_t launch_apply_rows(const double* R, const double* q, int K, int nvec, 
 // R: [batch][nl][3][3] lower factors of Lambda_l; K: per point a slot of [kw + nmaps][kw].
 hipError_t launch_smw_lambda(const double* cl, int64_t cl_stride, int64_t cl_ld, const double* wl, int wlo,
                              int nl, int nf, const int* fld, int batch, double* R, int* bad, hipStream_t s);
-hipError_t launch_smw_kernel(const double* M, int64_t kw, int64_t kwf, int nf, int wlo, int nl,
+hipError_t launch_smw_kernel(const double* M, int64_t ldm, int64_t kw, int64_t kwf, int nf, int wlo, int nl,
                              const double* R, int batch, double* K, int64_t slot, hipStream_t s);
+// out = B A (right = 0; A is k x other) or A B (right = 1; A is other x k) with B the per-mode block
+// operator of one point's R (kind 0 R, 1 R^T, 2 R^-1, 3 R^-T) over nf window fields of kwf modes;
+// out must not alias A.
+hipError_t launch_apply_rblock(const double* A, int64_t lda, double* out, int64_t ldo, int64_t other, int64_t kwf,
+                              int nf, int wlo, const double* R, int kind, int right, hipStream_t s);
+// flag |= 1 if any entry of nb blocks rows x cols (leading dimension ld, stride sb) is non-zero.
+hipError_t launch_any_nonzero(const double* A, int64_t ld, int64_t rows, int64_t cols, int64_t sb, int nb,
+                              int* flag, hipStream_t s);
 hipError_t launch_smw_rhs(const double* b, int nmaps, int64_t kw, int64_t kwf, int nf, int wlo, int nl,
                           const double* R, int batch, double* K, int64_t slot, hipStream_t s);
 hipError_t launch_smw_finish(const double* chi2N, const double* ldN, const double* x2b, const double* ldK,

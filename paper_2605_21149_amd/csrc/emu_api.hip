@@ -481,10 +481,15 @@ int cf_emu_train(cf_emu* m, const double* x, const double* y, int64_t N, int32_t
   return CF_OK;
 }
 
-int cf_emu_predict(cf_emu* m, const double* x, int64_t N, int32_t mem, double spread_max,
-                   const cf_problem* exact_prob, const cf_linear_spectra* model,
-                   const double* exact_map, double* y_out, double* spread_out,
-                   uint8_t* used_fallback, const cf_exec* ex, cf_report* rep) {
+}  // extern "C"
+
+namespace {
+// Prediction with the exact fallback through either the pixel likelihood (exact_prob, exact_map)
+// or a harmonic-basis handle (smw, one map); both NULL: routing flags only.
+int emu_predict(cf_emu* m, const double* x, int64_t N, int32_t mem, double spread_max,
+                const cf_problem* exact_prob, const cf_smw* smw, const cf_linear_spectra* model,
+                const double* exact_map, double* y_out, double* spread_out,
+                uint8_t* used_fallback, const cf_exec* ex, cf_report* rep) {
   const auto w0 = std::chrono::steady_clock::now();
   if (rep) { std::memset(rep, 0, sizeof *rep); rep->fail_index = -1; }
   if (!m) return set_error(CF_EINVAL, "emulator is NULL");
@@ -492,10 +497,15 @@ int cf_emu_predict(cf_emu* m, const double* x, int64_t N, int32_t mem, double sp
   if (N < 1 || N > (int64_t)1 << 30) return set_error(CF_EINVAL, "N = %lld outside 1..2^30", (long long)N);
   if (mem != CF_MEM_HOST && mem != CF_MEM_DEVICE) return set_error(CF_EINVAL, "unknown mem %d", mem);
   if (!(spread_max >= 0.0)) return set_error(CF_EINVAL, "spread_max must be >= 0");
-  if (exact_prob) {
-    if (!model || !exact_map) return set_error(CF_EINVAL, "exact fallback needs the spectra model and the map");
+  if (exact_prob || smw) {
+    if (!model || (exact_prob && !exact_map)) return set_error(CF_EINVAL, "exact fallback needs the spectra model and the map");
     if (model->nparam != m->net.in) return set_error(CF_EINVAL, "model has %d parameters, emulator %d", model->nparam, m->net.in);
     if (!model->base || !model->basis || model->lstride < 1) return set_error(CF_EINVAL, "incomplete spectra model");
+  }
+  int smw_mem = CF_MEM_DEVICE, smw_maps = 0;
+  if (smw) {
+    if (!cf::smw_describe(smw, &smw_mem, &smw_maps)) return set_error(CF_EINVAL, "invalid harmonic-basis handle");
+    if (smw_maps != 1) return set_error(CF_EINVAL, "the harmonic-basis handle holds %d maps; the fallback needs one", smw_maps);
   }
   std::lock_guard<std::mutex> lk(m->mu);
   if (!m->scaled) return set_error(CF_EINVAL, "emulator has not been trained");
@@ -540,7 +550,7 @@ int cf_emu_predict(cf_emu* m, const double* x, int64_t N, int32_t mem, double sp
   for (int64_t i = 0; i < N; ++i)
     if (hf[i]) fb.push_back((int)i);
   double ms_exact = 0.0;
-  if (exact_prob && !fb.empty()) {
+  if ((exact_prob || smw) && !fb.empty()) {
     const auto x0 = std::chrono::steady_clock::now();
     const int64_t nf = (int64_t)fb.size();
     const int L = model->lstride;
@@ -572,7 +582,23 @@ int cf_emu_predict(cf_emu* m, const double* x, int64_t N, int32_t mem, double sp
     ex2.stream = s;
     ex2.refine_max = -1;
     const double* maps[1] = {exact_map};
-    if (exact_prob->mem == CF_MEM_DEVICE) {
+    if (smw) {
+      // the handle's memory space holds its spectra and outputs
+      if (smw_mem == CF_MEM_DEVICE) {
+        double* cld;
+        if (int st = S.alloc(&cld, cl.size())) return st;
+        EMU_DEV(hipMemcpyAsync(cld, cl.data(), cl.size() * 8, hipMemcpyHostToDevice, s));
+        if (int st = cf_smw_loglike(const_cast<cf_smw*>(smw), (int32_t)nf, cld, L, vals, nullptr, nullptr, &ex2, nullptr))
+          return st;
+      } else {
+        std::vector<double> hv((size_t)nf);
+        if (int st = cf_smw_loglike(const_cast<cf_smw*>(smw), (int32_t)nf, cl.data(), L, hv.data(), nullptr, nullptr,
+                                    &ex2, nullptr))
+          return st;
+        EMU_DEV(hipMemcpyAsync(vals, hv.data(), (size_t)nf * 8, hipMemcpyHostToDevice, s));
+        EMU_DEV(hipStreamSynchronize(s));
+      }
+    } else if (exact_prob->mem == CF_MEM_DEVICE) {
       double* cld;
       if (int st = S.alloc(&cld, cl.size())) return st;
       EMU_DEV(hipMemcpyAsync(cld, cl.data(), cl.size() * 8, hipMemcpyHostToDevice, s));
@@ -604,6 +630,25 @@ int cf_emu_predict(cf_emu* m, const double* x, int64_t N, int32_t mem, double sp
     rep->n = N;
   }
   return CF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int cf_emu_predict(cf_emu* m, const double* x, int64_t N, int32_t mem, double spread_max,
+                   const cf_problem* exact_prob, const cf_linear_spectra* model,
+                   const double* exact_map, double* y_out, double* spread_out,
+                   uint8_t* used_fallback, const cf_exec* ex, cf_report* rep) {
+  return emu_predict(m, x, N, mem, spread_max, exact_prob, nullptr, model, exact_map, y_out, spread_out,
+                     used_fallback, ex, rep);
+}
+
+int cf_emu_predict_smw(cf_emu* m, const double* x, int64_t N, int32_t mem, double spread_max,
+                       const cf_smw* exact_smw, const cf_linear_spectra* model, double* y_out,
+                       double* spread_out, uint8_t* used_fallback, const cf_exec* ex, cf_report* rep) {
+  if (!exact_smw) return set_error(CF_EINVAL, "harmonic-basis handle is NULL");
+  return emu_predict(m, x, N, mem, spread_max, nullptr, exact_smw, model, nullptr, y_out, spread_out,
+                     used_fallback, ex, rep);
 }
 
 int cf_emu_get_params(const cf_emu* m, int32_t member, float* out) {

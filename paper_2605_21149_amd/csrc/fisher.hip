@@ -405,6 +405,13 @@ __global__ __launch_bounds__(256) void k_coldot(const double* U, const double* V
   if (threadIdx.x == 0) out[blockIdx.z * sOut + j] = red[0];
 }
 
+// out[i][j] += d[i] X[i][j] for a rows x cols row-major X (a diagonal matrix applied from the left)
+__global__ void k_rowscale_add(const double* d, const double* X, double* out, int64_t rows, int64_t cols) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * cols) return;
+  out[t] += d[t / cols] * X[t];
+}
+
 __global__ void k_axpy(double* y, const double* x, double a, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = fma(a, x[i], y[i]);
@@ -625,6 +632,14 @@ hipError_t launch_rowsumsq(const double* X, int64_t rows, int64_t cols, int64_t 
 hipError_t launch_coldot(const double* U, const double* V, int64_t rows, int64_t cols, int64_t ld,
                          int64_t sU, int64_t sV, int batch, double* out, int64_t sOut, hipStream_t s) {
   hipLaunchKernelGGL(k_coldot, dim3((unsigned)cols, 1, batch), dim3(256), 0, s, U, V, rows, ld, sU, sV, out, sOut);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowscale_add(const double* d, const double* X, double* out, int64_t rows, int64_t cols,
+                              hipStream_t s) {
+  const int64_t nt = rows * cols;
+  if (nt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rowscale_add, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, d, X, out, rows, cols);
   return hipGetLastError();
 }
 

@@ -519,6 +519,24 @@ hipError_t launch_tile(const GemmDesc& d, hipStream_t s) {
     g.remap = 1;
   }
   dim3 grid((unsigned)nx, 1, d.batch > 0 ? d.batch : 1), block(256);
+  KernTimer* kt = d.mode == 0 ? g_ktimer : nullptr;
+  KernTimer::Rec rec{};
+  if (kt) {
+    const bool tagged = d.tag == 1 && !d.at && d.bt;
+    rec.id = (BM == 128 ? 1 : 0) + (d.at ? 2 : 0) + (d.bt ? 4 : 0) + (tagged ? 8 : 0);
+    // algorithmic flops: 2 M N K, a lower-triangular output (col <= row + diag_off) on its triangle
+    double outs = (double)d.M * (double)d.N;
+    if (d.lower) {
+      outs = 0.0;
+      for (int64_t r = 0; r < d.M; ++r) {
+        const int64_t c = r + d.diag_off + 1;
+        outs += (double)(c <= 0 ? 0 : (c < d.N ? c : d.N));
+      }
+    }
+    rec.flops = 2.0 * outs * (double)d.K * (double)(d.batch > 0 ? d.batch : 1);
+    if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess) return hipErrorOutOfMemory;
+    CF_HIP_TRY(hipEventRecord(rec.a, s));
+  }
 #define CF_GEMM_MODE(KER)                                                              \
   if (d.at && d.bt) hipLaunchKernelGGL((KER<BM, BN, true, true>), grid, block, 0, s, g);   \
   else if (d.at) hipLaunchKernelGGL((KER<BM, BN, true, false>), grid, block, 0, s, g);     \
@@ -534,7 +552,12 @@ hipError_t launch_tile(const GemmDesc& d, hipStream_t s) {
     CF_GEMM_MODE(k_gemm)
   }
 #undef CF_GEMM_MODE
-  return hipGetLastError();
+  CF_HIP_TRY(hipGetLastError());
+  if (kt) {
+    CF_HIP_TRY(hipEventRecord(rec.b, s));
+    kt->rec.push_back(rec);
+  }
+  return hipSuccess;
 }
 
 template <int BM, int BN, bool AT, bool BT>
@@ -543,6 +566,8 @@ template <int BM, int BN, bool AT, bool BT>
 __global__ __launch_bounds__(256, 2) void k_gemm_lp2(GemmArgs g) { k_gemm_lp_body<BM, BN, AT, BT, 2>(g); }
 
 }  // namespace
+
+thread_local KernTimer* g_ktimer = nullptr;
 
 hipError_t gemm_f64(const GemmDesc& d, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0) return hipSuccess;

@@ -12,6 +12,8 @@
 // Lambda, and a field without power at some l simply contributes a zero column of R.
 #include "cf_internal.h"
 
+#include <algorithm>
+
 namespace cf {
 namespace {
 
@@ -82,10 +84,12 @@ __global__ void k_smw_lambda(const double* __restrict__ cl, int64_t cl_stride, i
 
 // K' = I + R^T M R for every point: one thread per (r_i, r_j) reads the nf x nf field block of M
 // at those positions once and writes the lower-triangle entries of K' for all field pairs.
-// M: [kw][kw] (ld kw), K': slot of [kw + nmaps][kw] per point (the first kw rows).
-__global__ __launch_bounds__(256) void k_smw_kernel(const double* __restrict__ M, int64_t kw, int64_t kwf,
-                                                    int nf, int wlo, int nl, const double* __restrict__ R,
-                                                    double* __restrict__ K, int64_t slot) {
+// M: [kw][kw] (leading dimension ldm: a diagonal block of a larger M for one field group),
+// K': slot of [kw + nmaps][kw] per point (the first kw rows).
+__global__ __launch_bounds__(256) void k_smw_kernel(const double* __restrict__ M, int64_t ldm, int64_t kw,
+                                                    int64_t kwf, int nf, int wlo, int nl,
+                                                    const double* __restrict__ R, double* __restrict__ K,
+                                                    int64_t slot) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int pt = blockIdx.y;
   if (t >= kwf * kwf) return;
@@ -94,7 +98,7 @@ __global__ __launch_bounds__(256) void k_smw_kernel(const double* __restrict__ M
   const double* Rj = R + ((int64_t)pt * nl + (ell_of(rj, wlo) - wlo)) * 9;
   double Mv[3][3];
   for (int c = 0; c < 3; ++c)
-    for (int d = 0; d < 3; ++d) Mv[c][d] = (c < nf && d < nf) ? M[(c * kwf + ri) * kw + d * kwf + rj] : 0.0;
+    for (int d = 0; d < 3; ++d) Mv[c][d] = (c < nf && d < nf) ? M[(c * kwf + ri) * ldm + d * kwf + rj] : 0.0;
   double* Kp = K + (int64_t)pt * slot;
   for (int fi = 0; fi < nf; ++fi)
     for (int fj = 0; fj < nf; ++fj) {
@@ -126,6 +130,68 @@ __global__ void k_smw_rhs(const double* __restrict__ b, int nmaps, int64_t kw, i
   K[(int64_t)pt * slot + (kw + j) * kw + i] = v;
 }
 
+// flag[0] = 1 if any entry of a rows x cols block (leading dimension ld, batch stride sb over nb
+// items) is non-zero or not finite: the coupling block of M between field groups, or the coupling
+// spectra of the points inside the window.
+__global__ void k_any_nonzero(const double* __restrict__ A, int64_t ld, int64_t rows, int64_t cols, int64_t sb,
+                              int nb, int* flag) {
+  const int64_t total = rows * cols * nb;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t z = t / (rows * cols), r = (t / cols) % rows, c = t % cols;
+    if (A[z * sb + r * ld + c] != 0.0) {   // also true for NaN
+      atomicOr(flag, 1);
+      return;
+    }
+  }
+}
+
+// The per-mode block operator B built from R (one point): B[(f,r),(g,r')] = delta_rr' X_l(r)[f][g]
+// with X = R (kind 0), R^T (1), R^-1 (2) or R^-T (3) over the nf window fields; applied on the
+// left (out = B A) or on the right (out = A B) of a k x ncol (left) or nrow x k (right) matrix.
+__device__ __forceinline__ void rblock(const double* Rl, int kind, double X[3][3]) {
+  double Li[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  if (kind >= 2) {                       // inverse of the lower factor, column by column
+    for (int j = 0; j < 3; ++j) {
+      const double d = Rl[j * 3 + j];
+      Li[j][j] = d != 0.0 ? 1.0 / d : 0.0;
+      for (int i = j + 1; i < 3; ++i) {
+        double t = 0.0;
+        for (int q = j; q < i; ++q) t += Rl[i * 3 + q] * Li[q][j];
+        Li[i][j] = Rl[i * 3 + i] != 0.0 ? -t / Rl[i * 3 + i] : 0.0;
+      }
+    }
+  }
+  for (int f = 0; f < 3; ++f)
+    for (int g = 0; g < 3; ++g) {
+      const double r = kind == 0 ? Rl[f * 3 + g] : kind == 1 ? Rl[g * 3 + f] : kind == 2 ? Li[f][g] : Li[g][f];
+      X[f][g] = r;
+    }
+}
+
+__global__ void k_apply_rblock(const double* __restrict__ A, int64_t lda, double* __restrict__ out, int64_t ldo,
+                               int64_t other, int64_t kwf, int nf, int wlo, const double* __restrict__ R, int kind,
+                               int right) {
+  const int64_t kw = kwf * nf;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= kw * other) return;
+  // the mode index of the output entry and its index along the other dimension (the fastest
+  // running one is the contiguous one of the output)
+  const int64_t mode = right ? t % kw : t / other;
+  const int64_t oth = right ? t / kw : t % other;
+  const int f = (int)(mode / kwf);
+  const int64_t r = mode % kwf;
+  double X[3][3];
+  rblock(R + (int64_t)(ell_of(r, wlo) - wlo) * 9, kind, X);
+  double v = 0.0;
+  if (right) {                          // out[oth][(f, r)] = sum_c A[oth][(c, r)] X[c][f]
+    for (int c = 0; c < nf; ++c) v = fma(A[oth * lda + c * kwf + r], X[c][f], v);
+    out[oth * ldo + mode] = v;
+  } else {                              // out[(f, r)][oth] = sum_c X[f][c] A[(c, r)][oth]
+    for (int c = 0; c < nf; ++c) v = fma(X[f][c], A[(c * kwf + r) * lda + oth], v);
+    out[mode * ldo + oth] = v;
+  }
+}
+
 // -2 ln L = d^T N_eff^-1 d - |L^-1 b'|^2 + ln|N_eff| + ln|K'| for the points of one batch.
 __global__ void k_smw_finish(const double* chi2N, const double* ldN, const double* x2b, const double* ldK,
                              int B, int nmaps, int64_t i0, double* m2, double* chi2, double* logdet) {
@@ -148,11 +214,29 @@ hipError_t launch_smw_lambda(const double* cl, int64_t cl_stride, int64_t cl_ld,
   return hipGetLastError();
 }
 
-hipError_t launch_smw_kernel(const double* M, int64_t kw, int64_t kwf, int nf, int wlo, int nl,
+hipError_t launch_smw_kernel(const double* M, int64_t ldm, int64_t kw, int64_t kwf, int nf, int wlo, int nl,
                              const double* R, int batch, double* K, int64_t slot, hipStream_t s) {
   const int64_t nt = kwf * kwf;
-  hipLaunchKernelGGL(k_smw_kernel, dim3((unsigned)((nt + 255) / 256), batch), dim3(256), 0, s, M, kw, kwf, nf,
-                     wlo, nl, R, K, slot);
+  hipLaunchKernelGGL(k_smw_kernel, dim3((unsigned)((nt + 255) / 256), batch), dim3(256), 0, s, M, ldm, kw, kwf,
+                     nf, wlo, nl, R, K, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_rblock(const double* A, int64_t lda, double* out, int64_t ldo, int64_t other, int64_t kwf,
+                              int nf, int wlo, const double* R, int kind, int right, hipStream_t s) {
+  const int64_t total = kwf * nf * other;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_apply_rblock, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, A, lda, out, ldo, other,
+                     kwf, nf, wlo, R, kind, right);
+  return hipGetLastError();
+}
+
+hipError_t launch_any_nonzero(const double* A, int64_t ld, int64_t rows, int64_t cols, int64_t sb, int nb,
+                              int* flag, hipStream_t s) {
+  if (rows <= 0 || cols <= 0 || nb <= 0) return hipSuccess;
+  const int64_t total = rows * cols * nb;
+  const unsigned blocks = (unsigned)std::min<int64_t>(2048, (total + 255) / 256);
+  hipLaunchKernelGGL(k_any_nonzero, dim3(blocks), dim3(256), 0, s, A, ld, rows, cols, sb, nb, flag);
   return hipGetLastError();
 }
 

@@ -255,6 +255,28 @@ def test_loglike_graph_replay_matches_eager():
     np.testing.assert_allclose(eager[:, 0], ref, rtol=TOL)
 
 
+def test_loglike_two_problems_autotuned_in_call(tmp_path, monkeypatch):
+    """Autotuning inside a two-problem call (both below the graph-capture size): one table entry
+    per problem, each problem's scan in its own tuned shape, every point against the oracle."""
+    monkeypatch.setenv("CF_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    pa = tiny_healpix("QU", nside=2, lmax=6, cut=0.2, lowrank=1)
+    pb = tiny_healpix("QU", nside=4, lmax=9, cut=0.3, lowrank=2)
+    maps = [_maps(pa, cv.total_covariance(pa), 2, 81), _maps(pb, cv.total_covariance(pb), 2, 82)]
+    pts = I.scan_points(21, seed=83)
+    clp = np.zeros((21, 2, 6, pb.lmax + 1))
+    clp[:, 0, :, :pa.lmax + 1] = I.scan_spectra(pts, pa.cl)
+    clp[:, 1] = I.scan_spectra(pts, pb.cl)
+    say("two problems, autotune in the call", pa.n, pb.n)
+    got = cf.loglike_batch([pa, pb], clp, maps, device=True, autotune=True)
+    lines = (tmp_path / "tune.txt").read_text().splitlines()
+    say("  tuned:", lines)
+    assert len(lines) == 2 and f"n={pa.n} " in lines[0] and f"n={pb.n} " in lines[1]
+    m2 = to_np(got["m2lnL"])
+    for k, p in enumerate((pa, pb)):
+        ref, _ = likelihood.scan(p, maps[k], clp[:, k, :, :p.lmax + 1])
+        np.testing.assert_allclose(m2[:, k], ref, rtol=TOL)
+
+
 def test_loglike_graph_key_tracks_problem_values():
     """Calls on the same buffers, shapes and batch that differ only in values a captured batch bakes
     into its kernel arguments (lmin 2 -> 3, then the noise's low-rank width 2 -> 1 behind the same
@@ -297,7 +319,10 @@ def test_loglike_autotune_records_a_batch_size(tmp_path, monkeypatch):
     np.testing.assert_allclose(to_np(got["m2lnL"])[:, 0], ref, rtol=TOL)
     lines = (tmp_path / "tune.txt").read_text().splitlines()
     say("  tuned:", lines)
-    assert len(lines) == 1 and f"n={p.n} nmaps=2 mode=0 batch=" in lines[0] and "tile=" in lines[0]
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    assert len(lines) == 1 and lines[0].startswith(f"scan {arch} n={p.n} nmaps=2 mode=0 batch=")
+    assert "tile=" in lines[0] and "graph=" in lines[0]
     # the recorded shape is reused: no second tuning, same results
     again = cf.loglike_batch([p], clp, [maps], device=True, autotune=True)
     assert len((tmp_path / "tune.txt").read_text().splitlines()) == 1

@@ -73,6 +73,46 @@ def test_smw_qu_e_window_matches_oracle_host_arrays():
     _against_oracle(p, maps, pts, 2, 5, "E", device=False)
 
 
+def _no_tp_spectra(lmax, seed):
+    cl = random_spectra(lmax, seed)
+    cl[3] = 0.0                                     # TE
+    cl[4] = 0.0                                     # TB
+    return cl
+
+
+def test_smw_field_blocks_match_oracle_and_fall_back_when_coupled():
+    """App. field_blocks: a TQU problem with no TE, TB and diagonal noise has no T x (E,B) block in
+    M, so the handle records two field groups and factorises K' as a T block and an E,B block; the
+    results equal the oracle's dense SMW likelihood and its direct Cholesky likelihood at 1e-9.  A
+    call with TE inside the window at one point factorises the dense K' (still exact); a problem
+    whose low-rank noise spans T and Q, U keeps one group."""
+    cf = _cf()
+    p = tiny_healpix("TQU", nside=2, lmax=6, cut=0.3)
+    p.cl = _no_tp_spectra(6, 91)
+    maps = np.random.default_rng(92).standard_normal((3, p.n))
+    pts = np.stack([_no_tp_spectra(6, s) for s in range(93, 100)])
+    say("smw field blocks: tiny TQU, window [2, 4] TEB, TE = TB = 0, diagonal noise")
+    with cf.SMW(p, maps, (2, 4), "TEB") as h:
+        assert h.setup_report["ir_iters"] == 2
+        got, rep = h.loglike(pts, report=True)
+        assert rep["ir_iters"] == 2
+        coupled = pts.copy()
+        coupled[2, 3, 3] = 0.2 * np.sqrt(coupled[2, 0, 3] * coupled[2, 1, 3])
+        got2, rep2 = h.loglike(coupled, report=True)
+        assert rep2["ir_iters"] == 1
+    for res, pp in ((got, pts), (got2, coupled)):
+        for i, cl in enumerate(pp):
+            m2, chi2, ld = smw.smw_minus2lnL(p, maps, cl, 2, 4, "TEB")
+            np.testing.assert_allclose(to_np(res["m2lnL"])[i], m2, rtol=1e-9)
+            np.testing.assert_allclose(to_np(res["logdet"])[i], ld, rtol=1e-9, atol=1e-9)
+            d2, _, _ = likelihood.minus2lnL(p, maps, cl=smw.window_spectra(p, cl, 2, 4, "TEB"))
+            np.testing.assert_allclose(to_np(res["m2lnL"])[i], d2, rtol=1e-9)
+    q = tiny_healpix("TQU", nside=2, lmax=6, cut=0.3, lowrank=2)
+    q.cl = p.cl
+    with cf.SMW(q, maps, (2, 4), "TEB") as h:
+        assert h.setup_report["ir_iters"] == 1
+
+
 def test_smw_full_window_equals_direct_gpu_likelihood():
     say("smw: tiny QU, full window [lmin, lmax] EB (N_eff = N) vs cf_loglike_batch")
     cf = _cf()
@@ -151,3 +191,86 @@ def test_smw_tqu_nside16_all_fields_full_size():
     say(f"  max rel |d(-2lnL)| vs direct GPU scan: {d:.3e}")
     assert d <= RTOL
     assert np.abs(got["logdet"] - ref["logdet"][:, 0]).max() <= RTOL * np.abs(ref["logdet"]).min()
+
+
+def test_loglike_auto_follows_the_selector_and_matches_the_direct_likelihood():
+    """cf_loglike_auto: a scan of 12 points whose EE varies in l 2..4 of a QU problem takes the
+    harmonic basis (a 21-mode kernel per point against a Cholesky of the pixel covariance); one point
+    over the whole band takes the pixel basis.  Both equal cf_loglike_batch at 1e-9 relative."""
+    cf = _cf()
+    p = tiny_healpix("QU", nside=4, lmax=9, cut=0.25)
+    p.cl = p.cl.copy()
+    p.cl[5] = 0.0                                           # EB would couple E to the fixed B
+    maps = np.random.default_rng(95).standard_normal((2, p.n))
+    pts = np.repeat(p.cl[None], 12, axis=0)
+    pts[:, 1, 2:5] *= np.random.default_rng(96).uniform(0.5, 1.5, (12, 3))
+    say("loglike auto: harmonic choice", p.n)
+    got = cf.loglike_auto(p, (2, 4), "E", pts, maps)
+    assert got["choice"]["basis"] == "harmonic" and got["choice"]["k_win"] == 21
+    ref = to_np(cf.loglike_batch([p], pts[:, None], [maps])["m2lnL"])[:, 0, :]
+    np.testing.assert_allclose(to_np(got["m2lnL"]), ref, rtol=1e-9)
+    say("loglike auto: pixel choice")
+    one = _points(p, (97,))
+    got1 = cf.loglike_auto(p, (p.lmin, p.lmax), "EB", one, maps)
+    assert got1["choice"]["basis"] == "pixel"
+    ref1 = to_np(cf.loglike_batch([p], one[:, None], [maps])["m2lnL"])[:, 0, :]
+    np.testing.assert_allclose(to_np(got1["m2lnL"]), ref1, rtol=1e-9)
+
+
+# ------------------------------------------------------------------ Fisher / QML in the SMW basis
+def _smw_qml_case(p, spectra, lo, hi, window, nmaps=2, seed=5):
+    """cf_smw_qml against the oracle's harmonic QML (all multipoles of [lmin, lmax] estimated
+    through Z, the same bins) and against the pixel-space cf_qml on the same maps."""
+    from oracle import covariance as cv
+    from oracle import qml
+    from gpu_common import metric_chat, metric_F, metric_vec_fisher
+    cf = _cf()
+    C = cv.total_covariance(p)
+    Lc = np.linalg.cholesky(C)
+    maps = (Lc @ np.random.default_rng(seed).standard_normal((p.n, nmaps))).T.copy()
+    ref = qml.qml_harmonic(p, spectra, lo, hi, maps, C)
+    bins = I.Bins(np.asarray(lo, np.int32), np.asarray(hi, np.int32), tuple(spectra))
+    got = {k: to_np(v) for k, v in cf.smw_qml(p, window, bins, maps, device=True).items()}
+    pix = {k: to_np(v) for k, v in cf.qml(p, bins, maps, device=True).items()}
+    F = ref["F"]
+    res = {"F": metric_F(got["F"], F), "y": metric_vec_fisher(got["y"], ref["y"], F),
+           "bias": metric_vec_fisher(got["bias"], ref["bias"], F),
+           "chat": metric_chat(got["chat"], ref["chat"], F)}
+    vs_pix = {"F": metric_F(got["F"], pix["F"]), "y": metric_vec_fisher(got["y"], pix["y"], F),
+              "bias": metric_vec_fisher(got["bias"], pix["bias"], F),
+              "chat": metric_chat(got["chat"], pix["chat"], F)}
+    return res, vs_pix, got
+
+
+def test_smw_qml_masked_qu_windowed_noise():
+    """Masked QU with low-rank noise; the window [2, 5] leaves l in [6, 9] at the fiducial inside
+    N_eff: F, y, bias and C_hat at 1e-10 of the oracle and of the pixel-space estimator."""
+    p = tiny_healpix("QU", nside=4, lmax=9, cut=0.25, lowrank=2)
+    spectra = ("EE", "BB", "EB")
+    say("smw qml: QU nside 4, window [2, 5], bins [2,3] [4,5]", p.n)
+    res, vs_pix, got = _smw_qml_case(p, spectra, [2, 4], [3, 5], (2, 5))
+    say("  vs oracle", res, "vs pixel", vs_pix)
+    assert max(res.values()) < 1e-10
+    assert max(vs_pix.values()) < 1e-10
+    np.testing.assert_allclose(got["F"], got["F"].T, rtol=0, atol=1e-14 * np.max(np.abs(got["F"])))
+
+
+@pytest.mark.parametrize("fields,window", [("T", (2, 7)), ("TQU", (2, 6))])
+def test_smw_qml_other_fields(fields, window):
+    p = tiny_healpix(fields, nside=4, lmax=9, cut=0.25, lowrank=2)
+    spectra = I.spectra_for_fields(fields)
+    lo = [2, 4, 5]; hi = [3, 4, window[1]]
+    say("smw qml:", fields, "window", window, p.n)
+    res, vs_pix, _ = _smw_qml_case(p, spectra, lo, hi, window, nmaps=3, seed=9)
+    say("  vs oracle", res, "vs pixel", vs_pix)
+    assert max(res.values()) < 1e-10
+    assert max(vs_pix.values()) < 1e-10
+
+
+def test_smw_qml_rejects_bins_outside_window():
+    cf = _cf()
+    p = tiny_healpix("T", nside=2, lmax=6, cut=0.3)
+    bins = I.Bins(np.array([2, 5], np.int32), np.array([4, 6], np.int32), ("TT",))
+    maps = np.zeros((1, p.n))
+    with pytest.raises(cf.CFError):
+        cf.smw_qml(p, (2, 4), bins, maps, device=True)
