@@ -50,6 +50,10 @@ def parse():
     return ap.parse_args()
 
 
+GEMM_ROLE = {"0": "(triangular solves and panel updates)", "1": "(Z = G^T G, E,B block)",
+             "2": "(Cholesky updates C -= L L^T)"}
+
+
 def _traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None when that
     summary was taken on a different source of the GEMM kernel than the one built here."""
@@ -508,28 +512,35 @@ def main():
     reps = []
     t0 = time.perf_counter()
     for k in range(args.steps):
+        # The last timed step carries per-stage device timers and an event pair around every GEMM
+        # launch (the kernel timings of the roofline); the events cost about 6 ms of host time per
+        # step, so the other steps run without them.
+        timed = k == args.steps - 1
         ev[3 * k].record()
-        # Fisher + QML with per-stage device timers and per-launch GEMM events
-        rq = cf.qml(problem, bins, d_maps_qml, device=True, stage_timing=True, report=True,
+        rq = cf.qml(problem, bins, d_maps_qml, device=True, stage_timing=timed, report=True,
                     packed=packed)[1]
         ev[3 * k + 1].record()
-        # the likelihood batch, in the launch shape the autotuner chose during warmup, with the same
-        # timers (the tuned shape launches eagerly at this size)
-        rs = cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True, report=True, stage_timing=True,
+        # the likelihood batch, in the launch shape the autotuner chose during warmup (eager
+        # launches at this size)
+        rs = cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True, report=True, stage_timing=timed,
                               packed=[packed], autotune=True)[1]
         ev[3 * k + 2].record()
-        reps.append((rq, rs))
+        if timed:
+            reps.append((rq, rs))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    qml_ms = [ev[3 * k].elapsed_time(ev[3 * k + 1]) for k in range(args.steps)]
-    scan_ms = [ev[3 * k + 1].elapsed_time(ev[3 * k + 2]) for k in range(args.steps)]
+    # medians over the uninstrumented steps (all of them when only one step is timed)
+    plain = range(args.steps - 1) if args.steps > 1 else range(args.steps)
+    qml_ms = [ev[3 * k].elapsed_time(ev[3 * k + 1]) for k in plain]
+    scan_ms = [ev[3 * k + 1].elapsed_time(ev[3 * k + 2]) for k in plain]
     ms_step = 1000.0 * wall / args.steps
     stage = np.mean([r[0]["ms_stage"] for r in reps], axis=0)
     scan_stage = np.mean([r[1]["ms_stage"] for r in reps], axis=0)
-    # GEMM instances over the timed steps (both calls): summed event time, algorithmic flops, launches
+    # GEMM instances over the instrumented step (both calls): event time, algorithmic flops, launches
     g_ms = np.sum([np.add(r[0]["gemm_ms"], r[1]["gemm_ms"]) for r in reps], axis=0)
     g_fl = np.sum([np.add(r[0]["gemm_flops"], r[1]["gemm_flops"]) for r in reps], axis=0)
     g_n = np.sum([np.add(r[0]["gemm_launches"], r[1]["gemm_launches"]) for r in reps], axis=0)
+    nrep = len(reps)
     mixed = None if args.no_mixed else mixed_precision(cf, I, problem, bins, packed, d_maps_qml, d_cl,
                                                           d_maps_scan)
     extras = None if args.no_extras else qml_extras(cf, I, problem, bins, packed, d_maps_qml)
@@ -543,15 +554,15 @@ def main():
                                      autotune=True)["m2lnL"][:, 0, :].cpu().numpy()
         smw = smw_section(cf, I, problem, packed, d_maps_scan, direct_m2,
                           SCAN_POINTS / (np.median(scan_ms) * 1e-3))
-    # Roofline kernel: the GEMM instance with the most device time over the timed steps (the
-    # factorisations' A B^T updates dominate the step), achieved = its algorithmic flops over the
-    # timed steps / its summed HIP-event durations on the streams it ran on.  Every instance is also
-    # listed (gemm_instances), with the whole factorisations' rates (factorisation).
+    # Roofline kernel: the GEMM instance with the most device time in the instrumented step (the
+    # Cholesky updates C -= L L^T of the two factorisation stages), achieved = its algorithmic flops
+    # in that step / its summed HIP-event durations on the streams it ran on.  Every instance is
+    # also listed (gemm_instances), with the whole factorisations' rates (factorisation).
     inst = []
     for i in range(len(g_ms)):
         if g_n[i] > 0:
-            inst.append({"kernel": cf.gemm_instance_name(i), "launches_per_step": float(g_n[i]) / args.steps,
-                         "ms_per_step": float(g_ms[i]) / args.steps,
+            inst.append({"kernel": cf.gemm_instance_name(i), "launches_per_step": float(g_n[i]) / nrep,
+                         "ms_per_step": float(g_ms[i]) / nrep, "avg_launch_us": float(g_ms[i] / g_n[i]) * 1e3,
                          "tflops": float(g_fl[i] / (g_ms[i] * 1e-3) / 1e12) if g_ms[i] > 0 else None,
                          "flops_per_launch": float(g_fl[i] / g_n[i])})
     inst.sort(key=lambda r: -r["ms_per_step"])
@@ -598,7 +609,8 @@ def main():
         "qu_scan": scan_qu,
         "other_fishers": fishers,
         "factorisation": factorisation,
-        "roofline": {"bound": "mfma", "kernel": top["kernel"] + " FP64 (factorisation and solve updates)",
+        "roofline": {"bound": "mfma", "kernel": top["kernel"] + " FP64 " + GEMM_ROLE.get(top["kernel"][-2], ""),
+                     "avg_launch_us": top["avg_launch_us"],
                      "achieved": top["tflops"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": top["tflops"] / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "launches_per_step": top["launches_per_step"],

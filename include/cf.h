@@ -102,8 +102,9 @@ typedef struct {
   double est_err[4];      /* mixed precision error estimates                           */
   int64_t n_fallback;     /* fallbacks taken                                           */
   /* With cf_exec.stage_timing: every launch of the FP64 matrix-core GEMM is bracketed by events
-   * on its stream and summed per kernel instance, id = (128 x 128 tile) + 2 (A stored transposed)
-   * + 4 (B stored transposed) + 8 (the separately named Z = G^T G instance):                  */
+   * on its stream and summed per kernel instance.  id 0-7: (128 x 128 tile) + 2 (A stored
+   * transposed) + 4 (B stored transposed); 8 + (128 tile): the separately named Z = G^T G
+   * instance; 10 + (128 tile): the Cholesky updates C -= L L^T, also named apart:               */
   double gemm_ms[16];        /* summed device time of the instance's launches                  */
   double gemm_flops[16];     /* their algorithmic flops, 2 M N K, outputs of a lower-triangular
                                 product counted on the triangle only                          */

@@ -62,10 +62,13 @@ class cf_report(C.Structure):
 
 
 def gemm_instance_name(i):
-    """Kernel name of FP64 GEMM instance id i of cf_report.gemm_* (tile, operand storage, tag)."""
+    """Kernel name of FP64 GEMM instance id i of cf_report.gemm_* (tile, operand storage, tag):
+    ids 0-7 untagged (bit 0: 128 tile, bit 1: A transposed, bit 2: B transposed); 8-9 the
+    Z = G^T G product, 10-11 the Cholesky updates (bit 0: 128 tile; A plain, B transposed)."""
     t = 128 if i & 1 else 64
-    return (f"k_gemm<{t}, {t}, {'true' if i & 2 else 'false'}, {'true' if i & 4 else 'false'}, "
-            f"{1 if i & 8 else 0}>")
+    if i >= 8:
+        return f"k_gemm<{t}, {t}, false, true, {1 + (i - 8) // 2}>"
+    return f"k_gemm<{t}, {t}, {'true' if i & 2 else 'false'}, {'true' if i & 4 else 'false'}, 0>"
 
 
 STAGES = ("build", "potrf", "ybuild", "trsm", "syrk", "reduce", "qml", "other")

@@ -86,6 +86,8 @@ struct GemmDesc {
   int mode;                               // 0 FP64 MFMA, 1 FP32 MFMA, 2 split-BF16 x3 MFMA
   int tag;                                // 1: Z = G^T G (a separately named kernel instance)
   int tile;                               // 0: by size; 64 or 128: that workgroup tile
+  int prio;                               // wave priority (0-3) of the launch's waves (s_setprio):
+                                          // critical-path work wins SIMD issue over bulk updates
 };
 hipError_t gemm_f64(const GemmDesc& g, hipStream_t s);
 

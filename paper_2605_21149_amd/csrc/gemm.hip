@@ -31,7 +31,14 @@ struct GemmArgs {
   int64_t sA, sB, sC;
   int tiles_m, tiles_n;
   int remap;          // 0: row-major tiles; 1: XCD chunks, grouped rows; 2: as 1, lower triangle of a square grid
+  int prio;           // wave priority: 0 default, 1 raised, 2 high
 };
+
+// Raises the issue priority of the calling wave (uniform argument, immediate operand).
+__device__ __forceinline__ void set_prio(int prio) {
+  if (prio == 1) __builtin_amdgcn_s_setprio(1);
+  else if (prio >= 2) __builtin_amdgcn_s_setprio(2);
+}
 
 // Tile schedule.  Workgroups go to the 8 XCDs round-robin in launch order and every XCD has its
 // own L2.  With remap, XCD x takes the contiguous range [x*per, (x+1)*per) of the (batch item,
@@ -92,7 +99,8 @@ __device__ __forceinline__ bool tile_of(const GemmArgs& g, int64_t& z, int& tm, 
   return tile_map(g.remap, g.tiles_m, g.tiles_n, gridDim.x, gridDim.z, blockIdx.x, blockIdx.z, z, tm, tn);
 }
 
-// TAG only names a separate instance (profiles can then tell the Z = G^T G launches apart).
+// TAG only names a separate instance, so that profiles tell launches apart: 1 the Z = G^T G
+// product of the Fisher path, 2 the Cholesky updates C -= L L^T (trailing and lookahead).
 template <int BM, int BN, bool AT, bool BT, int TAG = 0>
 __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   constexpr int BK = 16;
@@ -115,6 +123,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   if (!tile_of(g, z, tile_m, tile_n)) return;
   const int64_t i0 = (int64_t)tile_m * BM, j0 = (int64_t)tile_n * BN;
   if (g.lower && j0 >= i0 + g.diag_off + BM) return;   // tile strictly above the diagonal
+  set_prio(g.prio);
   const double* A = g.A + z * g.sA;
   const double* B = g.B + z * g.sB;
   double* C = g.C + z * g.sC;
@@ -309,6 +318,7 @@ __device__ __forceinline__ void k_gemm_lp_body(GemmArgs g) {
   if (!tile_of(g, z, tile_m, tile_n)) return;
   const int64_t i0 = (int64_t)tile_m * BM, j0 = (int64_t)tile_n * BN;
   if (g.lower && j0 >= i0 + g.diag_off + BM) return;
+  set_prio(g.prio);
   const double* A = g.A + z * g.sA;
   const double* B = g.B + z * g.sB;
   double* C = g.C + z * g.sC;
@@ -512,6 +522,7 @@ hipError_t launch_tile(const GemmDesc& d, hipStream_t s) {
   g.tiles_n = (int)tn;
   int64_t nx = tm * tn;
   g.remap = 0;
+  g.prio = d.prio;
   if (d.lower && d.diag_off == 0 && tm == tn && BM == BN && d.M == d.N) {
     g.remap = 2;
     nx = tm * (tm + 1) / 2;
@@ -522,8 +533,10 @@ hipError_t launch_tile(const GemmDesc& d, hipStream_t s) {
   KernTimer* kt = d.mode == 0 ? g_ktimer : nullptr;
   KernTimer::Rec rec{};
   if (kt) {
-    const bool tagged = d.tag == 1 && !d.at && d.bt;
-    rec.id = (BM == 128 ? 1 : 0) + (d.at ? 2 : 0) + (d.bt ? 4 : 0) + (tagged ? 8 : 0);
+    // ids: untagged (BM == 128) + 2 AT + 4 BT; tag t (AT = 0, BT = 1 only): 8 + 2 (t - 1) + (BM == 128)
+    const bool tagged = (d.tag == 1 || d.tag == 2) && !d.at && d.bt;
+    rec.id = tagged ? 8 + 2 * (d.tag - 1) + (BM == 128 ? 1 : 0)
+                    : (BM == 128 ? 1 : 0) + (d.at ? 2 : 0) + (d.bt ? 4 : 0);
     // algorithmic flops: 2 M N K, a lower-triangular output (col <= row + diag_off) on its triangle
     double outs = (double)d.M * (double)d.N;
     if (d.lower) {
@@ -544,6 +557,8 @@ hipError_t launch_tile(const GemmDesc& d, hipStream_t s) {
   else hipLaunchKernelGGL((KER<BM, BN, false, false>), grid, block, 0, s, g);
   if (d.tag == 1 && d.mode == 0 && !d.at && d.bt) {
     hipLaunchKernelGGL((k_gemm<BM, BN, false, true, 1>), grid, block, 0, s, g);
+  } else if (d.tag == 2 && d.mode == 0 && !d.at && d.bt) {
+    hipLaunchKernelGGL((k_gemm<BM, BN, false, true, 2>), grid, block, 0, s, g);
   } else if (d.mode == 1) {
     CF_GEMM_MODE(k_gemm_lp1)
   } else if (d.mode == 2) {

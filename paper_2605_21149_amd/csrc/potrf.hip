@@ -44,6 +44,9 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A_base, int64_t lda,
   __shared__ double rowblk[2][4][NB];     // X_J, all columns
   __shared__ double prodp[16];
   __shared__ int badp[16];
+  // the diagonal blocks are the head of the critical chain: their waves win SIMD issue over the
+  // bulk update waves that share the CU
+  __builtin_amdgcn_s_setprio(2);
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   double* A = A_base + blockIdx.z * sA + c * lda + c;
   double a[4][4], x[4][4];
@@ -451,7 +454,8 @@ hipError_t tri256(const Factor& F, int p, double* scratch, hipStream_t s) {
   return hipSuccess;
 }
 
-GemmDesc upd(const Factor& F, int64_t r0, int64_t c0, int64_t M, int64_t N, int64_t k0, int64_t K) {
+GemmDesc upd(const Factor& F, int64_t r0, int64_t c0, int64_t M, int64_t N, int64_t k0, int64_t K,
+             int prio = 0) {
   // C[r0.., c0..] -= L[r0.., k0..k0+K] L[c0.., k0..k0+K]^T  (lower tiles relative to the diagonal)
   GemmDesc g{};
   g.M = M; g.N = N; g.K = K;
@@ -462,6 +466,8 @@ GemmDesc upd(const Factor& F, int64_t r0, int64_t c0, int64_t M, int64_t N, int6
   g.batch = F.batch; g.sA = F.sL; g.sB = F.sL; g.sC = F.sL;
   g.mode = F.mode;
   g.tile = F.tile;
+  g.tag = 2;                     // its own kernel instance in FP64 (ignored by the mixed modes)
+  g.prio = prio;
   return g;
 }
 
@@ -523,6 +529,7 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     g.C = F.L + (q + b) * lda + q; g.ldc = lda;
     g.alpha = 1.0; g.beta = 0.0; g.lower = 0;
     g.batch = nb; g.sA = F.sL; g.sB = F.sLi64; g.sC = F.sL;
+    g.prio = 2;
     return gemm_f64(g, s);
   };
   // Right-looking panel: after each block, a rank-64 update of the panel's remaining columns.
@@ -532,7 +539,7 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     for (int64_t q = c0; q < c1; q += NB) {
       CF_HIP_TRY(block(q));
       const int64_t qe = q + NB;
-      if (qe < c1) CF_HIP_TRY(gemm_f64(upd(F, qe, qe, n - qe, c1 - qe, q, NB), s));
+      if (qe < c1) CF_HIP_TRY(gemm_f64(upd(F, qe, qe, n - qe, c1 - qe, q, NB, 2), s));
     }
     return hipSuccess;
   };
@@ -545,7 +552,7 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     const int64_t nbk = (c1 - c0 + NB - 1) / NB;
     const int64_t mid = c0 + ((nbk + 1) / 2) * NB;
     CF_HIP_TRY(panel_rec(c0, mid));
-    CF_HIP_TRY(gemm_f64(upd(F, mid, mid, n - mid, c1 - mid, c0, mid - c0), s));
+    CF_HIP_TRY(gemm_f64(upd(F, mid, mid, n - mid, c1 - mid, c0, mid - c0, 2), s));
     return panel_rec(mid, c1);
   };
   const bool rec = nb > 1;   // measured on batches of 8 at n = 5952: 20.0 -> 18.5 ms
@@ -571,7 +578,7 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     const int64_t nbk = (c1 - c0 + NB - 1) / NB;
     const int64_t mid = c0 + ((nbk + 1) / 2) * NB;
     CF_HIP_TRY(panel_ll(c0, mid));
-    CF_HIP_TRY(gemm_f64(upd(F, mid, mid, n - mid, c1 - mid, c0, mid - c0), s));
+    CF_HIP_TRY(gemm_f64(upd(F, mid, mid, n - mid, c1 - mid, c0, mid - c0, 2), s));
     return panel_ll(mid, c1);
   };
   for (int64_t c = 0; c < n; c += W) {
@@ -629,12 +636,12 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     if (st.eA) {
       // on the bulk CUs, after the previous trailing update (stream order) and this panel's chain
       CF_HIP_TRY(ewait(st.s1, st.eL));
-      CF_HIP_TRY(gemm_f64(upd(F, pe, pe, n - pe, pn - pe, c, pe - c), st.s1));
+      CF_HIP_TRY(gemm_f64(upd(F, pe, pe, n - pe, pn - pe, c, pe - c, 1), st.s1));
       CF_HIP_TRY(erec(st.eA, st.s1));
       CF_HIP_TRY(ewait(s, st.eA));
     } else {
       if (pending_b) CF_HIP_TRY(ewait(s, st.eB));
-      CF_HIP_TRY(gemm_f64(upd(F, pe, pe, n - pe, pn - pe, c, pe - c), s));
+      CF_HIP_TRY(gemm_f64(upd(F, pe, pe, n - pe, pn - pe, c, pe - c, 1), s));
     }
     // ---- bulk trailing update beyond the next panel (side stream, overlaps the next panel)
     if (pn < n) {
