@@ -116,6 +116,46 @@ def cross_dense(problem1, problem2, spectra, lo, hi, maps1, maps2):
     return q, W, chat
 
 
+def joint_dense(problem1, problem2, spectra, lo, hi, maps1, maps2, N12=None, s12=1.0):
+    """QML of the joint data vector d = (d1, d2) of two data sets of one sky (Eq. C_joint):
+      C_j = [[S + N1, s12 S + N12], [s12 S + N12^T, S + N2]],   N_j = [[N1, N12], [N12^T, N2]],
+      P_A^j = dC_j/dC_A = [[P_A, s12 P_A], [s12 P_A, P_A]],
+    then the standard estimator on the 2n-dimensional system (Eqs. fisher, q_ell, noise_bias,
+    qml_estimate): F_AB = 1/2 tr[C_j^-1 P_A^j C_j^-1 P_B^j], y_A = 1/2 d^T C_j^-1 P_A^j C_j^-1 d,
+    b_A = 1/2 tr[C_j^-1 P_A^j C_j^-1 N_j], C_hat = F^-1 (y - b).  Both data sets see the same
+    signal (s12 = 1, the equation as written); s12 = 0 decouples the two skies (a test case).
+    Geometry, spectra, beam and window come from problem1; problem2 contributes its noise N2;
+    N12[i][j] = Cov(n1_i, n2_j) (None: independent noise).  Returns dict(F, y, bias, chat)."""
+    th, ph = _directions(problem1)
+    S = cv.signal_pairs(th, ph, problem1.fields, problem1.cl, problem1.bl, problem1.pl,
+                        problem1.lmin, problem1.lmax)
+    n = S.shape[0]
+    X = np.zeros((n, n)) if N12 is None else np.asarray(N12, dtype=np.float64)
+    Nj = np.block([[problem1.noise_matrix(), X], [X.T, problem2.noise_matrix()]])
+    Cj = np.block([[S, s12 * S], [s12 * S, S]]) + Nj
+    fac = sla.cho_factor(Cj, lower=True)
+    pars = parameters(spectra, lo, hi)
+    Pj = []
+    for p in pars:
+        P = derivative_dense(problem1, *p)
+        Pj.append(np.block([[P, s12 * P], [s12 * P, P]]))
+    CiP = [sla.cho_solve(fac, P) for P in Pj]
+    k = len(pars)
+    F = np.zeros((k, k))
+    for a in range(k):
+        for b in range(k):
+            F[a, b] = 0.5 * np.sum(CiP[a] * CiP[b].T)
+    d = np.hstack([np.atleast_2d(maps1), np.atleast_2d(maps2)])     # [nmaps][2n]
+    x = sla.cho_solve(fac, d.T)
+    y = np.zeros((d.shape[0], k))
+    CiN = sla.cho_solve(fac, Nj)
+    bias = np.zeros(k)
+    for a in range(k):
+        y[:, a] = 0.5 * np.sum(x * (Pj[a] @ x), axis=0)
+        bias[a] = 0.5 * np.sum(CiP[a] * CiN.T)
+    return {"F": F, "y": y, "bias": bias, "chat": deconvolve(F, y - bias[None, :])}
+
+
 # ---------------------------------------------------------------------------
 # harmonic (Z) route
 # ---------------------------------------------------------------------------
