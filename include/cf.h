@@ -272,6 +272,19 @@ int cf_smw_qml(const cf_problem* prob, int32_t win_lmin, int32_t win_lmax, const
                const double* maps, int32_t nmaps, double* y_out, double* bias_out, double* chat_out,
                double* F_out, const cf_exec* ex, cf_report* rep);
 
+/* Joint QML of two data sets of one sky (Sect. 2.2, cross-correlation; Eq. C_joint): the data
+ * vector (d1, d2) has covariance [[S + N1, S + N12], [S + N12^T, S + N2]] and derivatives
+ * [[P_b, P_b], [P_b, P_b]]; F, y, the noise bias (of the joint noise, N12 included) and C_hat are
+ * those of the standard estimator (Eqs. fisher, q_ell, noise_bias, qml_estimate) on that
+ * 2n-dimensional system.  Geometry, spectra, beam and pixel window are taken from p1; p2 supplies
+ * the noise N2 and must match p1 in n, fields, l-range and memory space.  N12: dense n x n,
+ * row-major, N12[i][j] = Cov(noise1_i, noise2_j), or NULL for independent noise.  maps1, maps2:
+ * [nmaps][n] (map j of data set 1 pairs with map j of data set 2).  Outputs as cf_qml, all in
+ * p1->mem space.  FP64.  CF_ENOTPD if the joint covariance is not positive definite. */
+int cf_qml_joint(const cf_problem* p1, const cf_problem* p2, const double* N12, const cf_bins* bins,
+                 const double* maps1, const double* maps2, int32_t nmaps, double* y_out, double* bias_out,
+                 double* chat_out, double* F_out, const cf_exec* ex, cf_report* rep);
+
 /* ---------------------------------------------------------------------------------------------
  * Cost-based choice of the computation basis for a likelihood scan (Sect. 3, the "auto" selector
  * of the ComputationBasis interface; per-point costs as in the complexity table of App. C).

@@ -78,7 +78,7 @@ EXPORTS = ("cf_problem_dim", "cf_problem_nmodes", "cf_cov_build", "cf_fisher", "
            "cf_loglike_batch", "cf_loglike_batch_noalloc", "cf_emu_create", "cf_emu_destroy", "cf_emu_param_count", "cf_emu_shape",
            "cf_emu_train", "cf_emu_predict", "cf_emu_predict_smw", "cf_emu_get_params", "cf_emu_set_params",
            "cf_emu_forward", "cf_emu_gradient", "cf_emu_adam", "cf_emu_save", "cf_emu_load",
-           "cf_smw_create", "cf_smw_loglike", "cf_smw_dim", "cf_smw_destroy", "cf_select_basis", "cf_loglike_auto", "cf_smw_qml", "cf_decorrelate", "cf_qml_iterate", "cf_qml_cross",
+           "cf_smw_create", "cf_smw_loglike", "cf_smw_dim", "cf_smw_destroy", "cf_select_basis", "cf_loglike_auto", "cf_smw_qml", "cf_qml_joint", "cf_decorrelate", "cf_qml_iterate", "cf_qml_cross",
            "cf_last_error", "cf_version")
 
 
@@ -187,6 +187,9 @@ def lib():
         L.cf_smw_qml.argtypes = [C.POINTER(cf_problem), C.c_int32, C.c_int32, C.POINTER(cf_bins), _dp, C.c_int32,
                                  _dp, _dp, _dp, _dp, C.POINTER(cf_exec), C.POINTER(cf_report)]
         L.cf_smw_qml.restype = C.c_int
+        L.cf_qml_joint.argtypes = [C.POINTER(cf_problem), C.POINTER(cf_problem), _dp, C.POINTER(cf_bins), _dp, _dp,
+                                   C.c_int32, _dp, _dp, _dp, _dp, C.POINTER(cf_exec), C.POINTER(cf_report)]
+        L.cf_qml_joint.restype = C.c_int
         L.cf_smw_dim.argtypes = [C.c_void_p]
         L.cf_smw_dim.restype = C.c_int64
         L.cf_smw_destroy.argtypes = [C.c_void_p]
@@ -445,6 +448,37 @@ def loglike_batch(problems: Sequence, cl_points, maps: Sequence, precision=CF_FP
             _ptr(m2), _ptr(x2), _ptr(ld), C.byref(ex), C.byref(rep))
     _check(st, rep)
     out = {"m2lnL": m2, "chi2": x2, "logdet": ld}
+    return (out, rep.as_dict()) if report else out
+
+
+def qml_joint(p1, p2, bins, maps1, maps2, N12=None, device=False, report=False, packed=None):
+    """Joint QML of two data sets of one sky (cf_qml_joint): p1 gives geometry, spectra and noise
+    N1, p2 the noise N2; N12 [n][n] the shared noise (None: independent).  dict(y, bias, chat, F)."""
+    pk1, pk2 = packed or (pack_problem(p1, device), pack_problem(p2, device))
+    bs, keep = pack_bins(bins)
+    K = len(bins.spectra) * bs.nbins
+
+    def _dev(a):
+        if device:
+            import torch
+            t = a if _is_torch(a) else torch.as_tensor(np.ascontiguousarray(a, np.float64))
+            return t.to("cuda", torch.float64).contiguous()
+        return np.ascontiguousarray(_host(a))
+    m1 = _dev(maps1)
+    m2 = _dev(maps2)
+    if m1.ndim == 1:
+        m1, m2 = m1[None], m2[None]
+    x12 = None if N12 is None else _dev(N12)
+    nm = int(m1.shape[0])
+    y, bias, chat, F = (_alloc((nm, K), device), _alloc((K,), device), _alloc((nm, K), device),
+                        _alloc((K, K), device))
+    rep = cf_report()
+    ex = _exec(_torch_stream() if device else None)
+    st = lib().cf_qml_joint(C.byref(pk1.struct), C.byref(pk2.struct), _ptr(x12) if x12 is not None else None,
+                            C.byref(bs), _ptr(m1), _ptr(m2), nm, _ptr(y), _ptr(bias), _ptr(chat), _ptr(F),
+                            C.byref(ex), C.byref(rep))
+    _check(st, rep)
+    out = {"y": y, "bias": bias, "chat": chat, "F": F}
     return (out, rep.as_dict()) if report else out
 
 

@@ -2398,6 +2398,185 @@ extern "C" int cf_smw_qml(const cf_problem* prob, int32_t win_lmin, int32_t win_
   return CF_OK;
 }
 
+// Joint two-map QML (Eq. C_joint): the data vector (d1, d2) of one sky seen by two data sets, with
+// covariance [[S + N1, S + N12], [S + N12^T, S + N2]], is the data vector of a 2n-dimensional
+// problem whose harmonic operator is the stacked [Y; Y].  One factorisation of
+// [C_j; (d1 d2) rows; (Y^T Y^T) rows] gives u^T = (L^-1 d)^T and G^T = (L^-1 [Y; Y])^T; then
+// Z = G^T G, w = G^T u, F, y, the noise bias 1/2 tr[E_b (Z - Z Lambda Z)] (C_j minus the joint
+// signal [Y; Y] Lambda [Y; Y]^T is the joint noise) and C_hat as in cf_qml.
+extern "C" int cf_qml_joint(const cf_problem* p1, const cf_problem* p2, const double* N12, const cf_bins* bins,
+                            const double* maps1, const double* maps2, int32_t nmaps, double* y_out,
+                            double* bias_out, double* chat_out, double* F_out, const cf_exec* ex,
+                            cf_report* rep) {
+  using namespace cf;
+  report_init(rep);
+  HostProblem H, H2;
+  if (int st = check_problem(p1, H, true)) return st;
+  if (int st = check_problem(p2, H2, false)) return st;
+  if (H2.n != H.n || H2.lmin != H.lmin || H2.lmax != H.lmax || p2->fields != p1->fields || p2->mem != p1->mem)
+    return fail(CF_EINVAL, "the two data sets disagree on n, fields, l-range or memory space");
+  HostBins B;
+  if (int st = check_bins(bins, H, B)) return st;
+  if (nmaps <= 0 || !maps1 || !maps2) return fail(CF_EINVAL, "no maps");
+  if (!y_out || !bias_out || !chat_out) return fail(CF_EINVAL, "y_out, bias_out and chat_out are required");
+  const int64_t n = H.n, n2 = 2 * (int64_t)H.n, k = H.k, nm = nmaps;
+  const bool host = p1->mem == CF_MEM_HOST;
+  if (host) {
+    if (!finite_all(maps1, nm * n) || !finite_all(maps2, nm * n)) return fail(CF_EINVAL, "non-finite map value");
+    if (N12 && !finite_all(N12, n * n)) return fail(CF_EINVAL, "non-finite entry of N12");
+  }
+  CallCtx c;
+  if (int st = c.begin(ex)) return st;
+  const int K = B.ns * B.nb;
+  const int nl = H.lmax - H.lmin + 1;
+  const int np = H.nfm * H.nfm, nq = np * (np + 1) / 2;
+  const int64_t rows = n2 + nm + k, nblk = (n2 + kNB - 1) / kNB;
+  Sizer z;
+  size_staging(z, p1, H);
+  size_staging(z, p2, H2);
+  z.add<double>((size_t)rows * n2);            // [C_j; d rows; Y_j^T rows], factorised
+  z.add<double>((size_t)n * k);                // Y
+  z.add<double>((size_t)n * n);                // N12^T (or a zero diagonal)
+  z.add<double>(host && N12 ? (size_t)n * n : 1);   // N12 (host input)
+  z.add<double>((size_t)nm * n * 2);           // maps (host inputs)
+  z.add<double>((size_t)k * k);                // Z
+  z.add<double>((size_t)nblk * kNB * kNB);     // inverted diagonal blocks
+  z.add<double>((size_t)potrf_scratch(1));
+  z.add<double>((size_t)nblk);
+  z.add<double>((size_t)k * nm);               // w
+  z.add<double>((size_t)nl * (nl + 1) / 2 * nq);
+  z.add<double>((size_t)nl * np);
+  z.add<double>((size_t)K * K * 2);            // F and its copy for the solve
+  z.add<double>((size_t)nm * K * 3 + K);       // y, y - b, chat, bias
+  z.add<int>(B.nb);
+  z.add<int>(B.nb);
+  z.add<int>(8);
+  if (int st = ensure_ws(*c.dev, z.off)) return st;
+  Bump bp(c.dev->ws);
+  Staged S1, S2;
+  if (int st = stage(bp, p1, H, nullptr, c.s, S1)) return st;
+  if (int st = stage(bp, p2, H2, nullptr, c.s, S2)) return st;
+  double* C = bp.take<double>((size_t)rows * n2);
+  double* Y = bp.take<double>((size_t)n * k);
+  double* X12 = bp.take<double>((size_t)n * n);
+  double* N12c = bp.take<double>(host && N12 ? (size_t)n * n : 1);
+  double* mcopy = bp.take<double>((size_t)nm * n * 2);
+  double* Z = bp.take<double>((size_t)k * k);
+  double* Linv = bp.take<double>((size_t)nblk * kNB * kNB);
+  double* scr = bp.take<double>((size_t)potrf_scratch(1));
+  double* ldp = bp.take<double>((size_t)nblk);
+  double* W = bp.take<double>((size_t)k * nm);
+  double* gram = bp.take<double>((size_t)nl * (nl + 1) / 2 * nq);
+  double* ztr = bp.take<double>((size_t)nl * np);
+  double* F = bp.take<double>((size_t)K * K * 2);
+  double* Fw = F + (size_t)K * K;
+  double* y = bp.take<double>((size_t)nm * K * 3 + K);
+  double* q = y + (size_t)nm * K;
+  double* chat = q + (size_t)nm * K;
+  double* bias = chat + (size_t)nm * K;
+  int* dlo = bp.take<int>(B.nb);
+  int* dhi = bp.take<int>(B.nb);
+  int* flags = bp.take<int>(8);
+  hipStream_t s = c.s;
+  CF_DEV(hipMemcpyAsync(dlo, B.lo.data(), sizeof(int) * B.nb, hipMemcpyHostToDevice, s));
+  CF_DEV(hipMemcpyAsync(dhi, B.hi.data(), sizeof(int) * B.nb, hipMemcpyHostToDevice, s));
+  const double *m1 = maps1, *m2 = maps2, *x12 = N12;
+  if (host) {
+    CF_DEV(hipMemcpyAsync(mcopy, maps1, sizeof(double) * nm * n, hipMemcpyHostToDevice, s));
+    CF_DEV(hipMemcpyAsync(mcopy + nm * n, maps2, sizeof(double) * nm * n, hipMemcpyHostToDevice, s));
+    m1 = mcopy;
+    m2 = mcopy + nm * n;
+    if (N12) {
+      CF_DEV(hipMemcpyAsync(N12c, N12, sizeof(double) * n * n, hipMemcpyHostToDevice, s));
+      x12 = N12c;
+    }
+  }
+  CF_DEV(launch_fill_int(flags, 1, 0, s));
+  CF_DEV(launch_fill_int(flags + 1, 3, INT_MAX, s));
+  Timer tm;
+  tm.begin(ex && ex->stage_timing, s);
+  // ---- C_j (lower): the two diagonal blocks with their noises and the full off-diagonal block
+  //      S + N12^T, whose "noise" is N12^T as a dense matrix (or a zero diagonal)
+  CF_DEV(launch_cov_build(S1.P, S1.cw, 0, 1, p1->noise_kind, S1.noise, p1->noise_rank, S1.noise_U, C, n2, 0, 1,
+                          flags, s));
+  CF_DEV(launch_cov_build(S1.P, S1.cw, 0, 1, p2->noise_kind, S2.noise, p2->noise_rank, S2.noise_U,
+                          C + n * n2 + n, n2, 0, 1, flags, s));
+  if (x12) CF_DEV(launch_transpose(x12, n, n, n, X12, n, s));
+  else CF_DEV(launch_fill(X12, n, 0.0, s));
+  CF_DEV(launch_cov_build(S1.P, S1.cw, 0, 1, x12 ? CF_NOISE_DENSE : CF_NOISE_DIAG, X12, 0, nullptr, C + n * n2,
+                          n2, 0, 0, flags, s));
+  // ---- extra rows: the maps (d1 | d2) and the stacked harmonic operator (Y^T | Y^T)
+  double* Dt = C + n2 * n2;
+  double* Gt = Dt + nm * n2;
+  CF_DEV(hipMemcpy2DAsync(Dt, sizeof(double) * n2, m1, sizeof(double) * n, sizeof(double) * n, nm,
+                          hipMemcpyDeviceToDevice, s));
+  CF_DEV(hipMemcpy2DAsync(Dt + n, sizeof(double) * n2, m2, sizeof(double) * n, sizeof(double) * n, nm,
+                          hipMemcpyDeviceToDevice, s));
+  CF_DEV(launch_ybuild(S1.P, Y, k, s));
+  CF_DEV(launch_transpose(Y, n, k, k, Gt, n2, s));
+  CF_DEV(launch_transpose(Y, n, k, k, Gt + n, n2, s));
+  tm.mark(ST_BUILD);
+  Factor FN;
+  FN.L = C; FN.n = n2; FN.ld = n2; FN.sL = 0;
+  FN.Li64 = Linv; FN.ldpart = ldp; FN.fail = flags + 1; FN.batch = 1; FN.rows = rows;
+  if (int st = potrf_on(*c.dev, FN, scr, s, c.dev->aux[1], c.dev->ev + 8)) return st;
+  tm.mark(ST_POTRF);
+  // ---- Z = G^T G (lower), w = G^T u
+  GemmDesc g{};
+  g.M = k; g.N = k; g.K = n2;
+  g.A = Gt; g.lda = n2; g.B = Gt; g.ldb = n2; g.bt = 1;
+  g.C = Z; g.ldc = k; g.alpha = 1.0; g.lower = 1; g.batch = 1;
+  CF_DEV(gemm_f64(g, s));
+  if (nm <= 8) {
+    CF_DEV(launch_rowdot(Gt, n2, k, n2, Dt, n2, (int)nm, W, nm, k, 0, s));
+  } else {
+    GemmDesc w{};
+    w.M = k; w.N = nm; w.K = n2;
+    w.A = Gt; w.lda = n2; w.B = Dt; w.ldb = n2; w.bt = 1;
+    w.C = W; w.ldc = nm; w.alpha = 1.0; w.batch = 1;
+    CF_DEV(gemm_f64(w, s));
+  }
+  tm.mark(ST_SYRK);
+  CF_DEV(launch_symmetrize(Z, k, k, s));
+  CF_DEV(launch_gram(S1.P, Z, k, gram, ztr, s));
+  SpecSel sel;
+  sel.ns = B.ns;
+  for (int i = 0; i < 6; ++i) sel.spec[i] = B.spec[i];
+  sel.nb = B.nb; sel.lo = dlo; sel.hi = dhi;
+  CF_DEV(launch_fisher_assemble(S1.P, sel, gram, F, s));
+  CF_DEV(launch_bias_assemble(S1.P, sel, gram, ztr, bias, s));
+  CF_DEV(launch_quad_assemble(S1.P, sel, W, (int)nm, (int)nm, y, s));
+  CF_DEV(hipMemcpyAsync(q, y, sizeof(double) * nm * K, hipMemcpyDeviceToDevice, s));
+  CF_DEV(launch_sub_bias(q, bias, K, (int)nm, s));
+  CF_DEV(hipMemcpyAsync(Fw, F, sizeof(double) * K * K, hipMemcpyDeviceToDevice, s));
+  CF_DEV(launch_small_spd_solve(Fw, K, q, chat, (int)nm, flags + 3, s));
+  tm.mark(ST_QML);
+  int fl[4];
+  if (int st = read_flags(c, flags, 4, fl)) return st;
+  if (fl[0]) return fail(CF_EINVAL, "non-finite entry of the joint covariance (check noises and spectra)");
+  if (fl[1] != INT_MAX) {
+    if (rep) rep->fail_index = fl[1];
+    return fail(CF_ENOTPD, "joint covariance not positive definite at pivot %d", fl[1]);
+  }
+  if (fl[3] != INT_MAX) {
+    if (rep) rep->fail_index = fl[3];
+    return fail(CF_ENOTPD, "Fisher matrix not positive definite at pivot %d", fl[3]);
+  }
+  if (int st = copy_out(y_out, y, (size_t)nm * K, p1->mem, s)) return st;
+  if (int st = copy_out(bias_out, bias, (size_t)K, p1->mem, s)) return st;
+  if (int st = copy_out(chat_out, chat, (size_t)nm * K, p1->mem, s)) return st;
+  if (F_out)
+    if (int st = copy_out(F_out, F, (size_t)K * K, p1->mem, s)) return st;
+  CF_DEV(hipStreamSynchronize(s));
+  tm.finish(rep);
+  if (rep) {
+    const double nd = (double)n2, kd = (double)k;
+    rep->n = n2; rep->nmodes = k;
+    rep->flops = nd * nd * nd / 3.0 + nd * nd * (kd + nm) + kd * kd * nd;
+  }
+  return CF_OK;
+}
+
 extern "C" int cf_select_basis(const cf_problem* prob, int32_t win_lmin, int32_t win_lmax, uint32_t win_fields,
                                int32_t npoints, int32_t nmaps, cf_basis_choice* out) {
   HostProblem H;
