@@ -100,9 +100,8 @@ struct KernTimer {
 };
 extern thread_local KernTimer* g_ktimer;
 
-// A (batched) Cholesky factor with the inverses of its diagonal blocks.  The 64 x 64 diagonal blocks
-// of L itself are not kept in L (the fused block kernel leaves them as input); every user of a
-// factor reads the blocks below the diagonal and the inverted diagonal blocks.
+// A (batched) Cholesky factor with the inverses of its diagonal blocks.  Users of a factor read
+// the blocks below the diagonal and the inverted 64 x 64 diagonal blocks.
 struct Factor {
   double* L = nullptr; int64_t n = 0, ld = 0, sL = 0;   // row-major, lower; batch stride sL
   // Extra rows below the n x n matrix (rows n .. rows-1, same ld) are carried through the

@@ -210,202 +210,6 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A_base, int64_t lda,
   }
 }
 
-// ---------------------------------------------------------------------------------------------
-// Fused left-looking step for one diagonal block: block column [q, q + b) of a sub-panel that
-// starts at column c (q - c a multiple of 64; the columns [c, q) of the sub-panel are factored, the
-// updates from columns before c were applied by earlier trailing updates).
-//   1. D = A_qq - L_q,[c,q) L_q,[c,q)^T and, for the 64 rows r of workgroup g >= 1 below the block,
-//      T = A_r,q - L_r,[c,q) L_q,[c,q)^T (FP64 MFMA; slabs of 16 columns staged through LDS);
-//   2. D = L_qq L_qq^T and X = L_qq^-1 in one sweep over its 64 columns: wave w owns columns
-//      16w..16w+15 of every row (lane = row); per column the owning wave takes the pivot, publishes
-//      the scaled column through LDS, and every wave updates its columns of the factor (right of
-//      the pivot) and of the inverse (left of it, from the finished row of X read across lanes);
-//   3. workgroup 0 writes X as the inverted diagonal block, the block's sum of ln L_jj and the
-//      first non-positive pivot; workgroup g >= 1 writes L_rq = T X^T (MFMA).
-// Every workgroup factors the diagonal block itself (bit-identical copies), so no workgroup waits
-// for another; A_qq itself is left as it was (other workgroups of the launch read it), so the
-// factor keeps only the inverses of its diagonal blocks, which is all that its users read.  Rows
-// and columns beyond b are padded with the identity.
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
-struct BlockArgs {
-  double* A; int64_t lda, sA;      // matrix (row-major; lower triangle authoritative), batch stride
-  int64_t n;                       // order
-  int64_t q, c;                    // block column and the first column of its sub-panel
-  int b;                           // block width (64, or n - q for the last block)
-  double* Li; int64_t sLi; int blk;
-  double* ldpart; int64_t sPart;
-  int* fail;
-};
-
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-  const long long u = __double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffLL), lane);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)u >> 32), lane);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-__global__ __launch_bounds__(256) void k_potrf_block(BlockArgs p) {
-  constexpr int LS = NB + 1;             // LDS row stride of the 64 x 64 tiles
-  constexpr int LK = 17;                 // LDS row stride of the 128 x 16 update slabs
-  __shared__ double S0[NB * LS];         // update slabs, then D, then X
-  __shared__ double S1[NB * LS];         // T
-  __shared__ double colb[2][NB];         // the current column of L (double-buffered by column parity)
-  __shared__ double rsv[2];              // its pivot's reciprocal square root
-  __shared__ double dpiv[NB];            // pivots
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  double* A = p.A + (int64_t)blockIdx.z * p.sA;
-  const int64_t lda = p.lda, q = p.q, c = p.c;
-  const int b = p.b, g = blockIdx.x;
-  const int64_t r0 = q + b + (int64_t)(g - 1) * NB;
-  const int nr = g == 0 ? 0 : (int)(p.n - r0 < NB ? p.n - r0 : NB);
-  const int K = (int)(q - c);
-
-  // ---- 1. left-looking update; output row space: 0..63 the block's rows, 64..127 this workgroup's
-  dbl4 acc[2][4];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[a][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  const bool busy = w < 2 || nr > 0;     // waves 2 and 3 hold the T rows
-  for (int k0 = 0; k0 < K; k0 += 16) {
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int rr = (tid >> 4) + 16 * t, kk = tid & 15;
-      double v = 0.0;
-      if (rr < NB) {
-        if (rr < b) v = A[(q + rr) * lda + c + k0 + kk];
-      } else if (rr - NB < nr) {
-        v = A[(r0 + rr - NB) * lda + c + k0 + kk];
-      }
-      S0[rr * LK + kk] = v;
-    }
-    __syncthreads();
-    if (busy) {
-#pragma unroll
-      for (int kq = 0; kq < 4; ++kq) {
-        const int kr = 4 * kq + (lane >> 4);
-        double av[2], bv[4];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) av[a] = S0[(32 * w + 16 * a + (lane & 15)) * LK + kr];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = S0[(16 * j + (lane & 15)) * LK + kr];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[a][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[j], acc[a][j], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-  }
-  // D into S0 (lower part; identity beyond b), T into S1 (zeros beyond this workgroup's rows and b)
-  if (busy) {
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 32 * w + 16 * a + (lane >> 4) + 4 * r, col = 16 * j + (lane & 15);
-          if (i < NB) {
-            double v;
-            if (i < b && col < b) v = col <= i ? A[(q + i) * lda + q + col] - acc[a][j][r] : 0.0;
-            else v = i == col ? 1.0 : 0.0;
-            S0[i * LS + col] = v;
-          } else {
-            const int ii = i - NB;
-            S1[ii * LS + col] = (ii < nr && col < b) ? A[(r0 + ii) * lda + q + col] - acc[a][j][r] : 0.0;
-          }
-        }
-  }
-  __syncthreads();
-
-  // ---- 2. factor and invert the diagonal block
-  double fa[16], fx[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    fa[u] = S0[lane * LS + 16 * w + u];
-    fx[u] = lane == 16 * w + u ? 1.0 : 0.0;
-  }
-  for (int o = 0; o < 4; ++o) {
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int j = 16 * o + t, buf = j & 1;
-      if (w == o) {
-        const double d = readlane_f64(fa[t], j);
-        const double y = rsq_nr(d);
-        const double l = lane > j ? fa[t] * y : (lane == j ? d * y : 0.0);
-        fa[t] = l;
-        colb[buf][lane] = l;
-        if (lane == 0) {
-          rsv[buf] = y;
-          dpiv[j] = d;
-        }
-      }
-      __syncthreads();
-      const double y = rsv[buf];
-      const double lr = lane > j ? colb[buf][lane] : 0.0;   // L_rj for the rows below the pivot
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int k = 16 * w + u;
-        if (k <= j) {            // inverse: row j of X is final once scaled; rows below subtract it
-          const double xj = readlane_f64(fx[u], j) * y;
-          fx[u] = lane == j ? xj : fma(-lr, xj, fx[u]);
-        } else {                 // factor: columns right of the pivot
-          fa[u] = fma(-lr, colb[buf][k], fa[u]);
-        }
-      }
-    }
-  }
-  __syncthreads();
-
-  // ---- 3. outputs
-  if (g == 0) {
-    double* Li = p.Li + (int64_t)blockIdx.z * p.sLi + (int64_t)p.blk * NB * NB;
-#pragma unroll
-    for (int u = 0; u < 16; ++u) Li[lane * NB + 16 * w + u] = fx[u];
-    if (tid == 0) {
-      double acc_ld = 0.0;
-      int bad = INT_MAX;
-      for (int j = 0; j < b; ++j) {
-        const double d = dpiv[j];
-        if (bad == INT_MAX && (!(d > 0.0) || !isfinite(d))) bad = (int)q + j;
-        acc_ld += 0.5 * log(d);
-      }
-      p.ldpart[(int64_t)blockIdx.z * p.sPart + p.blk] = acc_ld;
-      if (bad != INT_MAX) atomicMin(p.fail, bad);
-    }
-    return;
-  }
-  // X into S0 as [row of X][column]: the B operand of T X^T reads X[j][k] at S0[j * LS + k]
-#pragma unroll
-  for (int u = 0; u < 16; ++u) S0[lane * LS + 16 * w + u] = fx[u];
-  __syncthreads();
-  dbl4 o4[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) o4[j] = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int kq = 0; kq < 16; ++kq) {
-    const int kr = 4 * kq + (lane >> 4);
-    const double av = S1[(16 * w + (lane & 15)) * LS + kr];
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      o4[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, S0[(16 * j + (lane & 15)) * LS + kr], o4[j], 0, 0, 0);
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = 16 * w + (lane >> 4) + 4 * r, col = 16 * j + (lane & 15);
-      if (i < nr && col < b) A[(r0 + i) * lda + q + col] = o4[j][r];
-    }
-}
-
-}  // namespace
-
-namespace {
-
-// Li256 block p: the four inverted 64-blocks on the diagonal, zeros elsewhere.
 __global__ void k_tri256_init(const double* Li64_base, int64_t sLi64, double* Li256_base, int64_t sLi256,
                               int p) {
   const double* Li64 = Li64_base + blockIdx.z * sLi64 + (int64_t)(4 * p) * NB * NB;
@@ -486,7 +290,6 @@ GemmDesc xupd(const Factor& F, double* X, int64_t rx, int64_t k0, int64_t k1, in
 }
 
 constexpr int64_t kDefer = 512;    // measured: rank-512 extra-row updates beat 256 and 1024 (paced loop)
-constexpr int64_t kLeaf = 256;     // widest sub-panel factored by fused left-looking blocks
 
 }  // namespace
 
@@ -556,35 +359,10 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     return panel_rec(mid, c1);
   };
   const bool rec = nb > 1;   // measured on batches of 8 at n = 5952: 20.0 -> 18.5 ms
-  // Fused left-looking blocks (CF_POTRF_FUSED=1): one launch per 64 columns does the in-panel
-  // update, the diagonal factor and inverse and the panel solve (k_potrf_block), for sub-panels of
-  // at most kLeaf columns; wider panels split recursively with one GEMM update between the halves.
-  // Correct (the whole GPU suite passes on it) but measured slower than the three-launch blocks
-  // (likelihood batch 26.0 vs 18.6 ms, Fisher 20.9 vs 15.5 ms), so it is not the default.
-  const char* fz = getenv("CF_POTRF_FUSED");
-  const bool fused = fz && fz[0] == '1';
-  auto ll_panel = [&](int64_t c0, int64_t c1) -> hipError_t {
-    for (int64_t q = c0; q < c1; q += NB) {
-      const int b = (int)((n - q) < NB ? (n - q) : NB);
-      const int64_t below = n - (q + b);
-      BlockArgs a{F.L, lda, F.sL, n, q, c0, b, F.Li64, F.sLi64, (int)(q / NB), F.ldpart, F.sPart, F.fail};
-      hipLaunchKernelGGL(k_potrf_block, dim3((unsigned)(1 + (below + NB - 1) / NB), 1, nb), dim3(256), 0, s, a);
-      CF_HIP_TRY(hipGetLastError());
-    }
-    return hipSuccess;
-  };
-  std::function<hipError_t(int64_t, int64_t)> panel_ll = [&](int64_t c0, int64_t c1) -> hipError_t {
-    if (c1 - c0 <= kLeaf) return ll_panel(c0, c1);
-    const int64_t nbk = (c1 - c0 + NB - 1) / NB;
-    const int64_t mid = c0 + ((nbk + 1) / 2) * NB;
-    CF_HIP_TRY(panel_ll(c0, mid));
-    CF_HIP_TRY(gemm_f64(upd(F, mid, mid, n - mid, c1 - mid, c0, mid - c0, 2), s));
-    return panel_ll(mid, c1);
-  };
   for (int64_t c = 0; c < n; c += W) {
     const int64_t pe = (c + W < n) ? c + W : n;
     // ---- critical path: the diagonal blocks and panels of this outer panel (rows of C only)
-    CF_HIP_TRY(fused ? panel_ll(c, pe) : (rec ? panel_rec(c, pe) : panel_right(c, pe)));
+    CF_HIP_TRY(rec ? panel_rec(c, pe) : panel_right(c, pe));
     CF_HIP_TRY(erec(st.eL, s));
     // ---- keep the host at most two panels ahead of the device.  Measured: with every panel of
     //      every stream queued up front, the device dispatches the critical chain markedly later
