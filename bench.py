@@ -65,7 +65,7 @@ def _traffic(kernel):
         src = open(os.path.join(here, "paper_2605_21149_amd", "csrc", "gemm.hip"), "rb").read()
     except (OSError, ValueError):
         return None
-    k = rec.get("kernels", {}).get(kernel)
+    k = rec.get("kernels", {}).get(kernel.replace(" ", ""))
     if not k or rec.get("gemm_source_sha256") != hashlib.sha256(src).hexdigest():
         return None
     return k["fetch_bytes"] + k["write_bytes"]
@@ -221,7 +221,11 @@ def cpu_baseline(problem, bins, cl_points, maps_qml, maps_scan, full=False):
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     if full:
         _oracle_sample(problem, bins, cl_points, maps_qml, maps_scan)
-        runs = [_oracle_sample(problem, bins, cl_points, maps_qml, maps_scan) for _ in range(3)]
+        _log("cpu baseline: warmup run done")
+        runs = []
+        for r in range(3):
+            runs.append(_oracle_sample(problem, bins, cl_points, maps_qml, maps_scan))
+            _log(f"cpu baseline: run {r + 1} of 3: Fisher+QML {runs[-1][0]:.1f} s, one point {runs[-1][1]:.1f} s")
         t_f = float(np.median([r[0] for r in runs]))
         t_p = float(np.median([r[1] for r in runs]))
     else:
@@ -238,6 +242,7 @@ def cpu_baseline(problem, bins, cl_points, maps_qml, maps_scan, full=False):
     if full:
         with threadpool_limits(limits=1):
             t1f, t1p = _oracle_sample(problem, bins, cl_points, maps_qml, maps_scan)
+        _log(f"cpu baseline: single thread: Fisher+QML {t1f:.1f} s, one point {t1p:.1f} s")
         out["single_thread"] = {"fisher_qml_s": t1f, "loglike_point_s": t1p,
                                 "steps_per_s": 1.0 / (t1f + SCAN_POINTS * t1p)}
     return out
@@ -554,6 +559,7 @@ def main():
     g_ms = np.sum([np.add(r[0]["gemm_ms"], r[1]["gemm_ms"]) for r in reps], axis=0)
     g_fl = np.sum([np.add(r[0]["gemm_flops"], r[1]["gemm_flops"]) for r in reps], axis=0)
     g_n = np.sum([np.add(r[0]["gemm_launches"], r[1]["gemm_launches"]) for r in reps], axis=0)
+    g_by = np.sum([np.add(r[0]["gemm_bytes"], r[1]["gemm_bytes"]) for r in reps], axis=0)
     nrep = len(reps)
     mixed = None if args.no_mixed else mixed_precision(cf, I, problem, bins, packed, d_maps_qml, d_cl,
                                                           d_maps_scan)
@@ -578,7 +584,8 @@ def main():
             inst.append({"kernel": cf.gemm_instance_name(i), "launches_per_step": float(g_n[i]) / nrep,
                          "ms_per_step": float(g_ms[i]) / nrep, "avg_launch_us": float(g_ms[i] / g_n[i]) * 1e3,
                          "tflops": float(g_fl[i] / (g_ms[i] * 1e-3) / 1e12) if g_ms[i] > 0 else None,
-                         "flops_per_launch": float(g_fl[i] / g_n[i])})
+                         "flops_per_launch": float(g_fl[i] / g_n[i]),
+                         "algorithmic_bytes_per_launch": float(g_by[i] / g_n[i])})
     inst.sort(key=lambda r: -r["ms_per_step"])
     top = inst[0]
     traffic = _traffic(top["kernel"])
@@ -628,7 +635,8 @@ def main():
                      "achieved": top["tflops"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": top["tflops"] / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "launches_per_step": top["launches_per_step"],
-                     "flops_per_launch": top["flops_per_launch"]},
+                     "flops_per_launch": top["flops_per_launch"],
+                     "algorithmic_bytes_per_launch": top["algorithmic_bytes_per_launch"]},
     }
     if not args.no_emulator:
         out["emulator"] = emulator_bench(cf, I, args.emu_train, args.emu_epochs, args.emu_query)

@@ -109,6 +109,8 @@ typedef struct {
   double gemm_flops[16];     /* their algorithmic flops, 2 M N K, outputs of a lower-triangular
                                 product counted on the triangle only                          */
   int64_t gemm_launches[16]; /* their number                                                  */
+  double gemm_bytes[16];     /* their algorithmic HBM bytes: A and B read once, C written once
+                                (read as well when beta != 0), lower outputs on the triangle only */
 } cf_report;
 
 /* Data dimension n = nmaps * npix of a problem, or -1 (see cf_last_error). */

@@ -50,7 +50,7 @@ class cf_report(C.Structure):
                 ("logdet", C.c_double), ("n", C.c_int64), ("nmodes", C.c_int64),
                 ("fail_index", C.c_int32), ("ir_iters", C.c_int32), ("est_err", C.c_double * 4),
                 ("n_fallback", C.c_int64), ("gemm_ms", C.c_double * 16), ("gemm_flops", C.c_double * 16),
-                ("gemm_launches", C.c_int64 * 16)]
+                ("gemm_launches", C.c_int64 * 16), ("gemm_bytes", C.c_double * 16)]
 
     def as_dict(self):
         return {"ms_total": self.ms_total, "ms_stage": list(self.ms_stage), "flops": self.flops,
@@ -58,7 +58,7 @@ class cf_report(C.Structure):
                 "fail_index": self.fail_index, "ir_iters": self.ir_iters,
                 "est_err": list(self.est_err), "n_fallback": self.n_fallback,
                 "gemm_ms": list(self.gemm_ms), "gemm_flops": list(self.gemm_flops),
-                "gemm_launches": list(self.gemm_launches)}
+                "gemm_launches": list(self.gemm_launches), "gemm_bytes": list(self.gemm_bytes)}
 
 
 def gemm_instance_name(i):

@@ -376,6 +376,7 @@ struct Timer {
       if (rep && r.id >= 0 && r.id < kGemmIds) {
         rep->gemm_ms[r.id] += ms;
         rep->gemm_flops[r.id] += r.flops;
+        rep->gemm_bytes[r.id] += r.bytes;
         rep->gemm_launches[r.id] += 1;
       }
       (void)hipEventDestroy(r.a);
@@ -1401,6 +1402,8 @@ int scan_replay(ScanCtx& x, int64_t i0, int b, int64_t nb, int64_t* i0p) {
     CF_DEV(hipGraphDestroy(graph));
     std::lock_guard<std::mutex> g(g_graph_mu);
     if (g_graphs[dev].size() >= 16) {
+      // the evicted graph may still have replays queued (on any stream): let them finish first
+      CF_DEV(hipDeviceSynchronize());
       (void)hipGraphExecDestroy(g_graphs[dev].front().exec);
       g_graphs[dev].erase(g_graphs[dev].begin());
     }

@@ -95,7 +95,7 @@ hipError_t gemm_f64(const GemmDesc& g, hipStream_t s);
 // running (g_ktimer set by the API layer); resolved into cf_report.gemm_* when the call finishes.
 constexpr int kGemmIds = 16;
 struct KernTimer {
-  struct Rec { int id; hipEvent_t a, b; double flops; };
+  struct Rec { int id; hipEvent_t a, b; double flops, bytes; };
   std::vector<Rec> rec;
 };
 extern thread_local KernTimer* g_ktimer;

@@ -546,7 +546,9 @@ hipError_t launch_tile(const GemmDesc& d, hipStream_t s) {
         outs += (double)(c <= 0 ? 0 : (c < d.N ? c : d.N));
       }
     }
-    rec.flops = 2.0 * outs * (double)d.K * (double)(d.batch > 0 ? d.batch : 1);
+    const double nb = (double)(d.batch > 0 ? d.batch : 1);
+    rec.flops = 2.0 * outs * (double)d.K * nb;
+    rec.bytes = 8.0 * ((double)d.M * d.K + (double)d.N * d.K + outs * (d.beta != 0.0 ? 2.0 : 1.0)) * nb;
     if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess) return hipErrorOutOfMemory;
     CF_HIP_TRY(hipEventRecord(rec.a, s));
   }
