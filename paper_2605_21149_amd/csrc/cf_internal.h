@@ -45,7 +45,8 @@ struct DevProblem {
   int64_t k;          // total modes nfm * kf
   const double* pix;  // [npx][kPixRec]
   const double* coef; // [lmax+1][kCoef]
-  const double* cw;   // [6][lmax+1] c^XY_l = (2l+1)/(4pi) C^XY_l W_l (zero below lmin)
+  const double* cw;   // [6][lmax+1] c^XY_l = (2l+1)/(4pi) C^XY_l W_l (zero below lmin) for XY = TT,
+                      // EE + BB, EE - BB, TE, TB, EB
   const double* wl;   // [lmax+1] W_l
   const double* lam;  // [6][lmax+1] C^XY_l W_l (mode covariance)
 };

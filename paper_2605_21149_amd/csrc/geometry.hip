@@ -64,8 +64,8 @@ __global__ void k_geometry(const int* ring_idx, int nside, const double* theta, 
   r[8] = z;       r[9] = phi;
 }
 
-// Per-multipole tables: weights c^XY_l, window W_l, mode covariance C^XY_l W_l, recurrence
-// coefficients.  One thread per (item, l); items are scan points sharing one problem.
+// Per-multipole tables: weights c^XY_l (in the order TT, EE + BB, EE - BB, TE, TB, EB), window
+// W_l, mode covariance C^XY_l W_l, recurrence coefficients.  One thread per (item, l); items are scan points sharing one problem.
 __global__ void k_tables(const double* cl, const double* bl, const double* pl, int lmin, int lmax,
                          int64_t cl_stride, int64_t cl_ld, double* cw, double* wl, double* lam,
                          double* coef, const int64_t* i0p, int nitems, int inter) {
@@ -80,14 +80,17 @@ __global__ void k_tables(const double* cl, const double* bl, const double* pl, i
   double f = (2.0 * l + 1.0) / (4.0 * pi) * W;
   const bool real = item < nitems;                   // false: zero padding of the last chunk
   const double* c = cl + (item + (i0p ? *i0p : 0)) * cl_stride;
+  double v[6];
+  for (int x = 0; x < 6; ++x) v[x] = real ? c[(int64_t)x * cl_ld + l] : 0.0;
   for (int x = 0; x < 6; ++x) {
-    double v = real ? c[(int64_t)x * cl_ld + l] : 0.0;
     if (cw) {
+      // the covariance assembly takes the EE and BB weights as their sum and difference
+      const double u = x == 1 ? v[1] + v[2] : (x == 2 ? v[1] - v[2] : v[x]);
       const int64_t at = inter > 1 ? (((int64_t)(item / inter) * L + l) * 6 + x) * inter + item % inter
                                    : (int64_t)item * 6 * L + x * L + l;
-      cw[at] = (l >= lmin) ? f * v : 0.0;
+      cw[at] = (l >= lmin) ? f * u : 0.0;
     }
-    if (lam && real) lam[(int64_t)item * 6 * L + x * L + l] = (l >= lmin) ? W * v : 0.0;
+    if (lam && real) lam[(int64_t)item * 6 * L + x * L + l] = (l >= lmin) ? W * v[x] : 0.0;
   }
   if (item == 0) {
     if (wl) wl[l] = W;

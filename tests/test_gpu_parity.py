@@ -14,7 +14,7 @@ from paper_2605_21149_amd import cf
 from paper_2605_21149_amd import inputs as I
 
 from gpu_common import metric_C, metric_chat, metric_F, metric_vec_fisher, say, to_np
-from oracle_cases import gl_problem, tiny_healpix
+from oracle_cases import gl_problem, random_spectra, tiny_healpix
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
@@ -53,6 +53,47 @@ def test_cov_build_dense_noise_host_path():
     say("cov_build host path", p.n)
     got = cf.cov_build(p, device=False)
     assert metric_C(got, cv.total_covariance(p)) < TOL
+
+
+@pytest.mark.parametrize("dense", [False, True])
+def test_cov_build_ragged_pixel_tiles(dense):
+    """Several 16-pixel tiles with a ragged last one: every unordered pixel pair is formed once and
+    stored at (i, j) and (j, i); diagonal noise with a low-rank part, or one dense matrix."""
+    mask = I.mask_abs_z_above(4, 0.1)
+    keep = np.flatnonzero(mask)
+    mask[keep[[3, 40, 77, 120, 150]]] = False          # 171 pixels: 10 full tiles and one of 11
+    cl = random_spectra(11, 5)
+    p = I.Problem("ragged_TQU", "TQU", 2, 11, cl, I.gaussian_beam(11, 1200.0), I.disc_pixel_window(11, 4), 4, mask)
+    p.noise_diag = np.full(p.n, 0.5)
+    p.noise_U = 0.3 * I.smooth_modes(4, mask, p.nmaps, 3, 12)
+    if dense:
+        p.noise_dense = p.noise_matrix()
+    assert p.npix % 16 and p.npix > 160
+    say("cov_build ragged tiles", p.npix, "dense" if dense else "diag + U U^T")
+    got = to_np(cf.cov_build(p, device=True))
+    m = metric_C(got, cv.total_covariance(p))
+    say("  M_C", m)
+    assert m < TOL
+    assert np.array_equal(got, got.T)
+
+
+def test_loglike_batch_ragged_pixel_tiles():
+    """The scan's batched build (points in groups of 8 share each pixel pair) on ragged pixel tiles,
+    with a partly filled last group: 11 points."""
+    mask = I.mask_abs_z_above(4, 0.1)
+    keep = np.flatnonzero(mask)
+    mask[keep[[3, 40, 77, 120, 150]]] = False
+    p = I.Problem("ragged_TQU", "TQU", 2, 11, random_spectra(11, 5), I.gaussian_beam(11, 1200.0),
+                  I.disc_pixel_window(11, 4), 4, mask)
+    p.noise_diag = np.full(p.n, 0.5)
+    p.noise_U = 0.3 * I.smooth_modes(4, mask, p.nmaps, 3, 12)
+    maps = _maps(p, cv.total_covariance(p), 3, 31)
+    clp = I.scan_spectra(I.scan_points(11, seed=32), p.cl)[:, None]
+    say("loglike ragged tiles", p.npix, "points", 11)
+    got = cf.loglike_batch([p], clp, [maps], device=True)
+    ref_m2, ref_ld = likelihood.scan(p, maps, clp[:, 0])
+    np.testing.assert_allclose(to_np(got["m2lnL"])[:, 0], ref_m2, rtol=TOL)
+    np.testing.assert_allclose(to_np(got["logdet"])[:, 0], ref_ld, rtol=TOL)
 
 
 def test_cov_build_spin0_nside8():
