@@ -24,7 +24,9 @@ PEAK_FP64_TFLOPS = 78.6
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    # 30 timed steps (under a second): the one instrumented step among them (per-launch GEMM
+    # events, about 2 ms of extra host time with the device idle) then adds under 0.1 ms per step
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-full", action="store_true",
