@@ -210,6 +210,226 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A_base, int64_t lda,
   }
 }
 
+// The same for batches of factorisations, with a shorter dependent chain.  256 threads, four
+// waves; lane r of wave w holds row r of the block's columns 16w..16w+15 in registers.
+//   1. Column sweep.  Wave w first applies the updates of the columns left of its own as the
+//      waves owning them announce them (the column in LDS plus a ready flag, no barrier), then
+//      factors its 16 columns.  From one pivot to the next the chain is the reciprocal square root
+//      and d_(j+1) = p - (q y_j)^2 with p, q (entries of lane j + 1) read beforehand; the next two
+//      columns take column j's update at once, the others during the next chain.
+//   2. Inverse X = L^-1 by blocks of 16: each wave inverts its diagonal block by substitution
+//      (one column of X per lane), then the off-diagonal blocks follow from
+//      [A 0; B C]^-1 = [A^-1 0; -C^-1 B A^-1  C^-1] at 32 and at 64 columns, as FP64 matrix-core
+//      products (one 16 x 16 output tile per wave).
+// Outputs as k_potrf_diag.  Measured on blocks of n = 5952: 23-27 us against 31-34 us, and a
+// batch of 8 likelihood points 16.2 -> 15.7 ms; a single factorisation, whose chain runs on a few
+// reserved CUs, became slower with it (12.2 -> 12.3 ms for Fisher + QML) and keeps k_potrf_diag.
+// The waits on the ready flags are bounded; a wait that runs out (which needs a fault elsewhere)
+// reports the block's first column as a failed pivot instead of hanging.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Waits until another wave of the workgroup sets *f; false after about 2^20 polls.
+__device__ __forceinline__ bool wait_flag(const int* f) {
+  for (int i = 0; i < (1 << 20); ++i) {
+    if (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) return true;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return false;
+}
+
+typedef double dbl4d __attribute__((ext_vector_type(4)));
+
+// Offset of column j in a 64 x 64 lower triangle packed by columns (entry i >= j at PK(j) + i).
+__device__ __forceinline__ int PK(int j) { return j * NB - (j * (j + 1)) / 2; }
+
+__global__ __launch_bounds__(256) void k_potrf_diag_sweep(double* A_base, int64_t lda, int64_t sA, int64_t c,
+                                                    int b, double* Li_base, int64_t sLi,
+                                                    double* ldpart_base, int64_t sL, int blk,
+                                                    int* fail) {
+  constexpr int LS = NB + 1;               // row stride of X in LDS
+  constexpr int TS = 33;                   // row stride of the 32 x 32 product buffer
+  // L by columns, lower triangle packed: L_ij (i >= j) at colP[PK(j) + i]; the space holds the
+  // 32 x 32 product of the last inverse step once L is no longer read.  52 KB in all (76 KB
+  // unpacked, which measured slower in the batched factorisation).
+  // (the 64 entries past the triangle take the stores of the lanes above the diagonal)
+  constexpr int PSZ = NB * (NB + 1) / 2;
+  __shared__ double colP[PSZ + 64];
+  __shared__ double Xs[NB * LS];           // X = L^-1, row-major
+  __shared__ double yv[NB], dv[NB];        // 1 / L_jj and the pivots
+  __shared__ int ready[NB + 64];           // flags; the 64 past NB take the other lanes' stores
+  __shared__ int stall;
+  // the diagonal blocks are the head of the critical chain: their waves win SIMD issue over the
+  // bulk update waves that share the CU
+  __builtin_amdgcn_s_setprio(2);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  if (tid < NB) ready[tid] = 0;
+  if (tid == 0) stall = 0;
+  for (int i = tid; i < NB * LS; i += 256) Xs[i] = 0.0;
+  double* A = A_base + blockIdx.z * sA + c * lda + c;
+  double a[16];
+#pragma unroll
+  for (int cc = 0; cc < 16; ++cc) {
+    const int q = 16 * w + cc;
+    a[cc] = (lane < b && q < b) ? (q <= lane ? A[lane * lda + q] : 0.0) : (lane == q ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  // ---- 1a. updates from the columns left of this wave's, as they are published
+  bool ok = true;
+  for (int j = 0; j < 16 * w; ++j) {
+    ok = wait_flag(&ready[j]) && ok;
+    const double lv = colP[PK(j) + (lane >= j ? lane : j)];
+    const double l = lane >= j ? lv : 0.0;
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) a[cc] = fma(-l, colP[PK(j) + 16 * w + cc], a[cc]);
+  }
+  // ---- 1b. this wave's columns.  The chain from one pivot to the next is the reciprocal square
+  //      root and d_(j+1) = p - (q y_j)^2, with p = A_(j+1,j+1) and q = A_(j+1,j) read beforehand
+  //      (the value lane j + 1 then forms itself, up to rounding).  The next two columns take
+  //      column j's update at once (their entries give the next p, q); the columns beyond take it
+  //      from the column's LDS copy during the next chain.  Column j - 1 is announced after
+  //      column j's chain; the flag and column stores are plain LDS stores, which the wave
+  //      performs in order.
+  double dj = readlane_f64(a[0], 16 * w);
+  double my_y = 0.0, my_d = 0.0;           // lane j keeps 1 / L_jj and the pivot
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj) {
+    const int j = 16 * w + jj;
+    double q1 = 0.0, p1 = 0.0, r2 = 0.0;
+    if (jj + 1 < 16) {
+      q1 = readlane_f64(a[jj], j + 1);
+      p1 = readlane_f64(a[jj + 1], j + 1);
+    }
+    if (jj + 2 < 16) r2 = readlane_f64(a[jj], j + 2);
+    if (jj > 0) {                          // column j - 1 into the columns beyond the two it updated
+      const double lp = a[jj - 1];
+#pragma unroll
+      for (int cc = jj + 2; cc < 16; ++cc) a[cc] = fma(-lp, colP[PK(j - 1) + 16 * w + cc], a[cc]);
+    }
+    // y = 1 / sqrt(d): hardware estimate, two Newton steps (the second's product formed early)
+    const double y0 = __builtin_amdgcn_rsq(dj);
+    const double h = -0.5 * dj;
+    const double e = h * y0;
+    const double f = fma(e, y0, 1.5);
+    const double y1 = y0 * f;
+    const double f2 = fma(e * f, y1, 1.5);
+    const double y = y1 * f2;
+    double lc = 0.0, dn = 0.0;
+    if (jj + 1 < 16) {
+      lc = (q1 * y1) * f2;                 // L_(j+1,j)
+      dn = fma(-lc, lc, p1);               // the next pivot
+    }
+    const double l = lane > j ? a[jj] * y : (lane == j ? dj * y : 0.0);
+    a[jj] = l;
+    if (jj + 1 < 16) a[jj + 1] = fma(-l, lc, a[jj + 1]);
+    if (jj + 2 < 16) a[jj + 2] = fma(-l, r2 * y, a[jj + 2]);
+    my_y = lane == j ? y : my_y;
+    my_d = lane == j ? dj : my_d;
+    if (jj > 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __hip_atomic_store(&ready[lane == 0 ? j - 1 : NB + lane], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    colP[PSZ + lane + ((PK(j) - PSZ) & -(int)(lane >= j))] = l;   // (a select, kept branch-free)
+    dj = dn;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __hip_atomic_store(&ready[lane == 0 ? 16 * w + 15 : NB + lane], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (lane >= 16 * w && lane < 16 * w + 16) {
+    yv[lane] = my_y;
+    dv[lane] = my_d;
+  }
+  if (!ok) stall = 1;
+  // L (lower) in place
+#pragma unroll
+  for (int cc = 0; cc < 16; ++cc) {
+    const int q = 16 * w + cc;
+    if (lane < b && q < b && q <= lane) A[lane * lda + q] = a[cc];
+  }
+  __syncthreads();
+  // ---- 2a. the diagonal 16-block of wave w: lane k < 16 forms column 16w + k of X
+  if (lane < 16) {
+    double s[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s[r] = r == lane ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const double xk = s[k] * yv[16 * w + k];
+      Xs[(16 * w + k) * LS + 16 * w + lane] = xk;
+#pragma unroll
+      for (int r = k + 1; r < 16; ++r) s[r] = fma(-colP[PK(16 * w + k) + 16 * w + r], xk, s[r]);
+    }
+  }
+  __syncthreads();
+  // ---- 2b. the 16 x 16 blocks below the diagonal pairs: X_10 (wave 0) and X_32 (wave 1)
+  //      X_{P+1,P} = -X_{P+1,P+1} (L_{P+1,P} X_{PP}); the first product's accumulator already holds
+  //      the second one's B operand (row 4kq + lane/16, column lane%16 of slab kq)
+  const int ri = lane & 15, rk = lane >> 4;
+  if (w < 2) {
+    const int p0 = 32 * w;
+    dbl4d t = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq) {
+      const int k = p0 + 4 * kq + rk;
+      t = __builtin_amdgcn_mfma_f64_16x16x4f64(colP[PK(k) + p0 + 16 + ri], Xs[k * LS + p0 + ri], t, 0, 0, 0);
+    }
+    dbl4d o = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq)
+      o = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[(p0 + 16 + ri) * LS + p0 + 16 + 4 * kq + rk], t[kq], o, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Xs[(p0 + 16 + rk + 4 * r) * LS + p0 + ri] = -o[r];
+  }
+  __syncthreads();
+  // ---- 2c. the 32 x 32 block X[32:64, 0:32] = -X[32:64, 32:64] (L[32:64, 0:32] X[0:32, 0:32]);
+  //      wave w owns output tile (ta, tb) of both products
+  const int ta = w >> 1, tb = w & 1;
+  {
+    dbl4d t = {0.0, 0.0, 0.0, 0.0};
+    for (int kq = 4 * tb; kq < 8; ++kq) {            // X[k, 16tb..] vanishes for k < 16tb
+      const int k = 4 * kq + rk;
+      t = __builtin_amdgcn_mfma_f64_16x16x4f64(colP[PK(k) + 32 + 16 * ta + ri], Xs[k * LS + 16 * tb + ri], t, 0, 0, 0);
+    }
+    __syncthreads();                                  // L is read for the last time above
+    double* Ts = colP;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Ts[(16 * ta + rk + 4 * r) * TS + 16 * tb + ri] = t[r];
+  }
+  __syncthreads();
+  {
+    dbl4d o = {0.0, 0.0, 0.0, 0.0};
+    const double* Ts = colP;
+    for (int kq = 0; kq < 4 * (ta + 1); ++kq) {       // X[32 + 16ta.., 32 + k] vanishes for k >= 16(ta + 1)
+      const int k = 4 * kq + rk;
+      o = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[(32 + 16 * ta + ri) * LS + 32 + k], Ts[k * TS + 16 * tb + ri], o,
+                                               0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Xs[(32 + 16 * ta + rk + 4 * r) * LS + 16 * tb + ri] = -o[r];
+  }
+  __syncthreads();
+  // ---- outputs: L^-1, the block's sum of ln L_jj = 1/2 ln d_j, the first non-positive pivot
+  double* Li = Li_base + blockIdx.z * sLi + (int64_t)blk * NB * NB;
+  for (int i = tid; i < NB * NB; i += 256) Li[i] = Xs[(i >> 6) * LS + (i & 63)];
+  if (w == 0) {
+    const double d = dv[lane];             // pivots of padded columns are 1
+    const bool bad = lane < b && (!(d > 0.0) || !isfinite(d));
+    const unsigned long long m = __ballot(bad);
+    double v = lane < b ? 0.5 * log(d) : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) {
+      ldpart_base[blockIdx.z * sL + blk] = v;
+      if (m) atomicMin(fail, (int)c + (int)__builtin_ctzll(m));
+      else if (stall) atomicMin(fail, (int)c);
+    }
+  }
+}
+
 __global__ void k_tri256_init(const double* Li64_base, int64_t sLi64, double* Li256_base, int64_t sLi256,
                               int p) {
   const double* Li64 = Li64_base + blockIdx.z * sLi64 + (int64_t)(4 * p) * NB * NB;
@@ -320,7 +540,7 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
   auto block = [&](int64_t q) -> hipError_t {
     const int b = (int)((n - q) < NB ? (n - q) : NB);
     const int blk = (int)(q / NB);
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, nb), dim3(256), 0, s, F.L, lda, F.sL, q, b, F.Li64,
+    hipLaunchKernelGGL(nb > 1 ? k_potrf_diag_sweep : k_potrf_diag, dim3(1, 1, nb), dim3(256), 0, s, F.L, lda, F.sL, q, b, F.Li64,
                        F.sLi64, F.ldpart, F.sPart, blk, F.fail);
     CF_HIP_TRY(hipGetLastError());
     const int64_t below = n - (q + b);
@@ -364,14 +584,16 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     // ---- critical path: the diagonal blocks and panels of this outer panel (rows of C only)
     CF_HIP_TRY(rec ? panel_rec(c, pe) : panel_right(c, pe));
     CF_HIP_TRY(erec(st.eL, s));
-    // ---- keep the host at most two panels ahead of the device.  Measured: with every panel of
+    // ---- keep the host at most one panel ahead of the device: the rest of this panel's launches
+    //      are issued once the previous panel's chain has run.  Measured: with every panel of
     //      every stream queued up front, the device dispatches the critical chain markedly later
-    //      (a single n = 5952 factorisation with its solves: 12.0 ms unthrottled, 10.0 ms here).
+    //      (a single n = 5952 factorisation with its solves: 12.0 ms unthrottled, 10.0 ms two
+    //      panels ahead, 9.2 ms one panel ahead; batches are indifferent between one and two).
     //      Graph capture records launches without running them, so it is never throttled.
     if (st.ring && !capturing) {
       const int64_t pidx = c / W;
       CF_HIP_TRY(hipEventRecord(st.ring[pidx % 4], s));
-      if (pidx >= 2) CF_HIP_TRY(hipEventSynchronize(st.ring[(pidx - 2) % 4]));
+      if (pidx >= 1) CF_HIP_TRY(hipEventSynchronize(st.ring[(pidx - 1) % 4]));
     }
     // ---- 256-block inverse for the solves (side stream)
     if (F.Li256 && pe - c >= OUTER) {
