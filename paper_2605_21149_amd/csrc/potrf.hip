@@ -509,7 +509,10 @@ GemmDesc xupd(const Factor& F, double* X, int64_t rx, int64_t k0, int64_t k1, in
   return u;
 }
 
-constexpr int64_t kDefer = 512;    // measured: rank-512 extra-row updates beat 256 and 1024 (paced loop)
+// Extra-row updates wait until the pending panels span kDefer columns.  Measured with the host
+// paced one panel ahead (n = 5952 with 6965 extra rows, 256-column panels): 256 (every panel at
+// once) 11.8 ms for Fisher + QML, 512 12.0-12.1, 1024 13.1, 2048 13.7.
+constexpr int64_t kDefer = 256;
 
 }  // namespace
 
