@@ -339,7 +339,7 @@ def qu_scan(cf, I, npoints=8192):
     """The QU likelihood scan of the batched-scan workload (N_side 8, n = 1088, and N_side 16,
     n = 3968, 64 maps each) over npoints points of its parameter box, each problem in its own call
     (calls that mix the two problems stay off the GPU: see the library's notes) in the launch shape
-    the autotuner recorded for it (tuned on 64 points first): points/s (one point = both problems,
+    the autotuner recorded for it (tuned on 128 points first): points/s (one point = both problems,
     the two calls' times added) and map evaluations/s, FP64 and FP32 mixed (with the refined chi^2
     and the log-det correction), and the mixed path's largest |d(-2 ln L)| against FP64."""
     import torch
@@ -355,9 +355,9 @@ def qu_scan(cf, I, npoints=8192):
     out, ref = {"n": [pa.n, pb.n], "points": npoints, "maps": 64}, None
     for prec, name in ((cf.CF_FP64, "fp64"), (cf.CF_MIXED_FP32, "fp32")):
         for k, p in enumerate((pa, pb)):
-            cf.loglike_batch([p], d_cl[:64, k:k + 1, :, :p.lmax + 1].contiguous(), maps[k:k + 1], precision=prec,
+            cf.loglike_batch([p], d_cl[:128, k:k + 1, :, :p.lmax + 1].contiguous(), maps[k:k + 1], precision=prec,
                              device=True, packed=pks[k:k + 1], autotune=True)
-        t, parts = 0.0, []
+        t, parts, tk = 0.0, [], []
         for k, p in enumerate((pa, pb)):
             cl1 = d_cl[:, k:k + 1, :, :p.lmax + 1].contiguous()
             torch.cuda.synchronize()
@@ -365,11 +365,13 @@ def qu_scan(cf, I, npoints=8192):
             res = cf.loglike_batch([p], cl1, maps[k:k + 1], precision=prec, device=True, packed=pks[k:k + 1],
                                    autotune=True)
             torch.cuda.synchronize()
-            t += time.perf_counter() - t0
+            tk.append(time.perf_counter() - t0)
+            t += tk[-1]
             parts.append(res["m2lnL"].cpu().numpy())
         _log(f"qu scan {name}: {npoints} points x 2 problems in {t:.2f} s")
         m2 = np.concatenate(parts, axis=1)
-        out[name] = {"ms": 1e3 * t, "points_per_s": npoints / t, "map_evals_per_s": 2 * 64 * npoints / t}
+        out[name] = {"ms": 1e3 * t, "ms_per_problem": [1e3 * x for x in tk], "points_per_s": npoints / t,
+                     "map_evals_per_s": 2 * 64 * npoints / t}
         if ref is None:
             ref = m2
         else:

@@ -176,7 +176,7 @@ int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t npoints,
  * pinned buffers and runs every launch eagerly, in order, on cf_exec.stream (NULL: the null
  * stream), returning when the results are written.  It does not autotune (cf_exec.autotune,
  * no_graph and stage_timing are ignored): the batch of points factorised together is the largest
- * (at most 16) whose workspace fits the array.  CF_EINVAL when even one point does not fit (for
+ * (at most 128) whose workspace fits the array.  CF_EINVAL when even one point does not fit (for
  * FP64 with 64 maps, up to about n = 2600; host-memory problems also stage their inputs in it).
  * Calls on one GPU share the array, which keeps the last call's contents; the library serialises
  * calls per device and each returns after its work is done, so calls never overlap on it. */
