@@ -381,6 +381,29 @@ def qu_scan(cf, I, npoints=8192):
     return out
 
 
+def tqu_scan(cf, I, problem, packed, d_maps_scan, npoints=64):
+    """The likelihood of the step's workload as a scan: npoints points per call (the step itself
+    holds 8 per call) in the launch shape the autotuner picks for them, 64 maps, FP64: points/s and
+    map evaluations/s, median of three calls after the tuning call."""
+    import torch
+    pts = I.scan_points(npoints, seed=404)
+    cl = torch.as_tensor(np.ascontiguousarray(I.scan_spectra(pts, problem.cl)[:, None])).cuda()
+    cf.loglike_batch([problem], cl, [d_maps_scan], device=True, packed=[packed], autotune=True)
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cf.loglike_batch([problem], cl, [d_maps_scan], device=True, packed=[packed], autotune=True)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts))
+    n = problem.n
+    return {"points_per_call": npoints, "ms": 1e3 * t, "points_per_s": npoints / t,
+            "map_evals_per_s": npoints * NMAPS_SCAN / t,
+            "tflops": npoints * (n ** 3 / 3.0 + NMAPS_SCAN * n ** 2) / t / 1e12,
+            "autotuned": [l for l in (_tuned_lines(os.environ["CF_TUNE_CACHE"]) or []) if f"n={n} " in l]}
+
+
 def other_fishers(cf, I, reps=2):
     """Fisher+QML of one map for the two other QML workloads, median device-synchronised wall time:
     the spin-0 N_side 8 problem (n = 544, 23 unbinned multipoles; latency-bound) in FP64, and the
@@ -552,6 +575,7 @@ def main():
             reps.append((rq, rs))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    step_tuned = _tuned_line(os.environ["CF_TUNE_CACHE"], n)     # the step's launch shape
     # medians over the uninstrumented steps (all of them when only one step is timed)
     plain = range(args.steps - 1) if args.steps > 1 else range(args.steps)
     qml_ms = [ev[3 * k].elapsed_time(ev[3 * k + 1]) for k in plain]
@@ -569,6 +593,7 @@ def main():
                                                           d_maps_scan)
     extras = None if args.no_extras else qml_extras(cf, I, problem, bins, packed, d_maps_qml)
     scan_qu = None if args.no_extras else qu_scan(cf, I, args.scan_points)
+    scan_tqu = None if args.no_extras else tqu_scan(cf, I, problem, packed, d_maps_scan)
     fishers = None if args.no_extras else other_fishers(cf, I)
     host_inputs = None if args.no_extras else host_input_step(cf, problem, bins, maps_qml, maps_scan,
                                                                  cl_points)
@@ -619,7 +644,7 @@ def main():
                                 f"{NMAPS_SCAN} maps"),
                    "precision": "fp64", "n": n, "nmodes": 6900, "scan_points_per_step": SCAN_POINTS,
                    "maps_per_point": NMAPS_SCAN,
-                   "autotuned": _tuned_line(os.environ["CF_TUNE_CACHE"], n)},
+                   "autotuned": step_tuned},
         "fisher_qml_ms": float(np.median(qml_ms)),
         "loglike_ms": float(np.median(scan_ms)),
         "loglike_points_per_s": SCAN_POINTS / (np.median(scan_ms) * 1e-3),
@@ -632,6 +657,7 @@ def main():
         "qml_extras": extras,
         "host_inputs": host_inputs,
         "qu_scan": scan_qu,
+        "tqu_scan": scan_tqu,
         "other_fishers": fishers,
         "factorisation": factorisation,
         "roofline": {"bound": "mfma", "kernel": top["kernel"] + " FP64 " + GEMM_ROLE.get(top["kernel"][-2], ""),

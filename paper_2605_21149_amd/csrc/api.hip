@@ -1199,6 +1199,7 @@ struct TuneEntry {
   int64_t n;
   int nmaps, mode, bt, panel, tile;
   int graph;                          // launch mode of the trials (-1: not recorded)
+  int maxb = 16;                      // the largest batch the trials could try (the call's cap)
 };
 std::vector<TuneEntry> g_tune;
 std::string g_tune_loaded;            // path the table was read from
@@ -1221,11 +1222,12 @@ void tune_load() {
     TuneEntry e{};
     char arch[64] = {0};
     long long n;
-    const int got = sscanf(line, "scan %63s n=%lld nmaps=%d mode=%d batch=%d panel=%d tile=%d graph=%d", arch, &n,
-                           &e.nmaps, &e.mode, &e.bt, &e.panel, &e.tile, &e.graph);
+    const int got = sscanf(line, "scan %63s n=%lld nmaps=%d mode=%d batch=%d panel=%d tile=%d graph=%d max=%d",
+                           arch, &n, &e.nmaps, &e.mode, &e.bt, &e.panel, &e.tile, &e.graph, &e.maxb);
     if (got < 5) continue;
     if (got < 7) e.panel = e.tile = 0;
     if (got < 8) e.graph = -1;
+    if (got < 9) e.maxb = 16;           // entries from before larger batches were tried
     e.arch = arch;
     e.n = n;
     g_tune.push_back(e);
@@ -1234,16 +1236,17 @@ void tune_load() {
 }
 const TuneEntry* tune_get(const char* arch, int64_t n, int nmaps, int mode) {
   tune_load();
-  for (auto& e : g_tune)
-    if (e.arch == arch && e.n == n && e.nmaps == nmaps && e.mode == mode) return &e;
+  // the latest entry of the shape: a call that could try larger batches tunes again and appends
+  for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
+    if (it->arch == arch && it->n == n && it->nmaps == nmaps && it->mode == mode) return &*it;
   return nullptr;
 }
 void tune_put(const TuneEntry& e) {
   g_tune.push_back(e);
   FILE* f = fopen(tune_path().c_str(), "a");
   if (!f) return;
-  fprintf(f, "scan %s n=%lld nmaps=%d mode=%d batch=%d panel=%d tile=%d graph=%d\n", e.arch.c_str(), (long long)e.n,
-          e.nmaps, e.mode, e.bt, e.panel, e.tile, e.graph);
+  fprintf(f, "scan %s n=%lld nmaps=%d mode=%d batch=%d panel=%d tile=%d graph=%d max=%d\n", e.arch.c_str(),
+          (long long)e.n, e.nmaps, e.mode, e.bt, e.panel, e.tile, e.graph, e.maxb);
   fclose(f);
 }
 
@@ -1479,7 +1482,8 @@ int loglike_core(const cf_problem* probs, int32_t nprob, int32_t npoints, const 
     for (int p = 0; p < nprob; ++p)
       if (const TuneEntry* tp = tune_get(c.dev->arch, H[p].n, nmaps, mode)) {
         te[p] = *tp;                     // copied: tune_put may grow the table
-        tuned[p] = 1;
+        // tuned by a call with fewer points than this one can batch: tune again if asked to
+        tuned[p] = !(ex && ex->autotune && cap[p] > te[p].maxb);
       }
   const int L = lmax_all + 1;
   // workspace bytes for batches of up to bw[p] points of problem p
@@ -1629,7 +1633,7 @@ int loglike_core(const cf_problem* probs, int32_t nprob, int32_t npoints, const 
     // chosen shape, so every output comes from one configuration.
     if (ex && ex->autotune && !tuned[p] && npoints >= 2 && !noalloc) {
       double best_rate = 0.0;
-      TuneEntry best{c.dev->arch, h.n, nmaps, mode, b, 0, 0, graph ? 1 : 0};
+      TuneEntry best{c.dev->arch, h.n, nmaps, mode, b, 0, 0, graph ? 1 : 0, cap[p]};
       const bool verbose = getenv("CF_TUNE_VERBOSE") != nullptr;
       auto trial = [&](int cand, int panel, int tile, bool g) -> int {
         if (cand > cap[p]) return CF_OK;

@@ -191,6 +191,26 @@ def test_loglike_batch_small():
     np.testing.assert_allclose(ld, ref_ld, rtol=TOL)
 
 
+def test_autotune_again_for_larger_calls(tmp_path, monkeypatch):
+    """A shape tuned by a call of 4 points is tuned again by a call that can batch 16 (a second
+    entry, which later calls read), not by one of 8 points after that; every result against the oracle."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("CF_TUNE_CACHE", str(cache))
+    p = tiny_healpix("QU", nside=4, lmax=9, cut=0.25, lowrank=2)
+    maps = _maps(p, cv.total_covariance(p), 2, 41)
+    clp = I.scan_spectra(I.scan_points(16, seed=42), p.cl)[:, None]
+    ref, _ = likelihood.scan(p, maps, clp[:, 0])
+    nlines = []
+    for k in (4, 16, 8):
+        got = to_np(cf.loglike_batch([p], clp[:k].copy(), [maps], device=True, autotune=True)["m2lnL"])[:, 0]
+        np.testing.assert_allclose(got, ref[:k], rtol=TOL)
+        nlines.append(len(cache.read_text().splitlines()))
+    lines = cache.read_text().splitlines()
+    say("  tuned:", lines)
+    assert nlines == [1, 2, 2]
+    assert lines[0].endswith(" max=4") and lines[1].endswith(" max=16")
+
+
 def test_loglike_single_point_captured():
     """One point per batch: the captured batch factorises a single matrix (the reserved-CU
     streams of single factorisations stay out of graph capture)."""
