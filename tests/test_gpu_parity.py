@@ -253,6 +253,33 @@ def test_not_positive_definite_reports_pivot():
     assert e.value.report["fail_index"] >= 0
 
 
+def test_loglike_batch_not_positive_definite_reports_pivot():
+    """A batch of 8 points (the batched diagonal-block kernel) whose covariances turn indefinite at
+    a pixel of the second 64-block: CF_ENOTPD with the first non-positive pivot over the batch,
+    the one a plain Cholesky sweep of each point's covariance meets first."""
+    import dataclasses
+    p = tiny_healpix("QU", nside=4, lmax=9, cut=0.25, lowrank=2)
+    p.noise_diag = np.full(p.n, 0.5)
+    p.noise_diag[70:] = -500.0
+    maps = np.ones((2, p.n))
+    clp = I.scan_spectra(I.scan_points(8, seed=52), p.cl)[:, None]
+    say("ENOTPD case, batch of 8")
+    with pytest.raises(cf.CFError) as e:
+        cf.loglike_batch([p], clp, [maps], device=True)
+    assert e.value.status == cf.CF_ENOTPD
+    first = []
+    for i in range(8):
+        A = cv.total_covariance(dataclasses.replace(p, cl=clp[i, 0])).copy()
+        for j in range(A.shape[0]):
+            if A[j, j] <= 0:
+                first.append(j)
+                break
+            A[j + 1:, j] /= np.sqrt(A[j, j])
+            A[j + 1:, j + 1:] -= np.outer(A[j + 1:, j], A[j + 1:, j])
+    say("  fail_index", e.value.report["fail_index"], "first pivots", first)
+    assert len(first) == 8 and e.value.report["fail_index"] == min(first) == 70
+
+
 # ----------------------------------------------------------------------------------- mixed precision
 # Tolerances of the mixed paths (FP32 / split-BF16x3 MFMA with FP64 diagonal blocks, FP64
 # refinement of C^-1 d and of C^-1 Y, log-det correction): Fisher relative Frobenius error, y after
