@@ -437,6 +437,7 @@ int potrf_on(Device& d, Factor& F, double* scratch, hipStream_t s, hipStream_t s
   CF_DEV(hipStreamIsCapturing(s, &cap));
   if (!d.crit || F.batch > 1 || cap != hipStreamCaptureStatusNone) {
     Streams st{s, d.aux[0], side, ev[0], ev[1], ev[2], d.ring};
+    st.eT = ev[6];   // lookahead of depth two
     CF_DEV(potrf_f64(F, scratch, st));
     return CF_OK;
   }

@@ -643,13 +643,23 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
       CF_HIP_TRY(erec(st.eA, st.s1));
       CF_HIP_TRY(ewait(s, st.eA));
     } else {
-      if (pending_b) CF_HIP_TRY(ewait(s, st.eB));
+      // after the previous trailing update, or with eT only after its first part: the columns of
+      // this lookahead's panel (the rest of that update runs on beside the next panels' chains)
+      if (pending_b) CF_HIP_TRY(ewait(s, st.eT ? st.eT : st.eB));
       CF_HIP_TRY(gemm_f64(upd(F, pe, pe, n - pe, pn - pe, c, pe - c, 1), s));
     }
     // ---- bulk trailing update beyond the next panel (side stream, overlaps the next panel)
     if (pn < n) {
       CF_HIP_TRY(ewait(st.s1, st.eL));
-      CF_HIP_TRY(gemm_f64(upd(F, pn, pn, n - pn, n - pn, c, pe - c), st.s1));
+      const int64_t pn2 = (pn + W < n) ? pn + W : n;    // end of the panel after next
+      if (st.eT && !st.eA && pn2 < n) {
+        CF_HIP_TRY(gemm_f64(upd(F, pn, pn, n - pn, pn2 - pn, c, pe - c), st.s1));
+        CF_HIP_TRY(erec(st.eT, st.s1));
+        CF_HIP_TRY(gemm_f64(upd(F, pn2, pn2, n - pn2, n - pn2, c, pe - c), st.s1));
+      } else {
+        CF_HIP_TRY(gemm_f64(upd(F, pn, pn, n - pn, n - pn, c, pe - c), st.s1));
+        if (st.eT && !st.eA) CF_HIP_TRY(erec(st.eT, st.s1));
+      }
       CF_HIP_TRY(erec(st.eB, st.s1));
       pending_b = true;
     }
