@@ -219,7 +219,10 @@ def test_cov_build_qu_nside32_sampled_rows():
 @pytest.mark.timeout(1800)
 def test_fisher_qu_nside32_sampled_entries():
     """n = 12288, 18424 modes, unbinned EE/BB/EB over l = 2..95 (282 parameters): the Fisher
-    entries among l = 2, 30, 95 against the oracle (C by the harmonic route, Z on those modes)."""
+    entries among l = 2, 30, 95 against the oracle (C by the harmonic route, Z on those modes);
+    QML of one map: y and the noise bias of those parameters against the oracle's
+    y = 1/2 w^T E w (w = Y^T C^-1 d) and b = 1/2 tr[E X^T N X] (X = C^-1 Y), a route apart from the
+    library's b = 1/2 tr[E (Z - Z Lambda Z)]."""
     import scipy.linalg as sla
     cf = _cf()
     p = I.qu_problem_nside32()
@@ -229,6 +232,10 @@ def test_fisher_qu_nside32_sampled_entries():
     nb = len(bins.lo)
     assert got.shape == (3 * nb, 3 * nb)
     assert np.array_equal(got, got.T)
+    d = I.white_maps(p.n, 1, 311, rms=2.0)
+    q = cf.qml(p, bins, d, device=True)
+    Fq, yq, bq = to_np(q["F"]), to_np(q["y"])[0], to_np(q["bias"])
+    assert np.array_equal(Fq, got)
     ells = [2, 30, 95]
     idx = [s * nb + (l - 2) for s in range(3) for l in ells]
     say("  oracle ...")
@@ -249,3 +256,12 @@ def test_fisher_qu_nside32_sampled_entries():
     m = metric_F(sub, ref)
     say("  M_F sampled", m)
     assert m < TOL
+    X = sla.cho_solve(fac, Ys)                                   # C^-1 Y on the sampled modes
+    w = X.T @ d[0]
+    y_ref = qml.quadratic_from_w(w, coo)[0]
+    XNX = X.T @ (p.noise_diag[:, None] * X)
+    b_ref = np.array([0.5 * np.sum(v * XNX[c, r]) for r, c, v in coo])
+    my = metric_vec_fisher(yq[idx], y_ref, got[np.ix_(idx, idx)])
+    mb = metric_vec_fisher(bq[idx], b_ref, got[np.ix_(idx, idx)])
+    say("  y, bias sampled (Fisher units)", my, mb)
+    assert my < TOL and mb < TOL
