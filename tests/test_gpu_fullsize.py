@@ -217,51 +217,45 @@ def test_cov_build_qu_nside32_sampled_rows():
 
 
 @pytest.mark.timeout(1800)
-def test_fisher_qu_nside32_sampled_entries():
-    """n = 12288, 18424 modes, unbinned EE/BB/EB over l = 2..95 (282 parameters): the Fisher
-    entries among l = 2, 30, 95 against the oracle (C by the harmonic route, Z on those modes);
-    QML of one map: y and the noise bias of those parameters against the oracle's
-    y = 1/2 w^T E w (w = Y^T C^-1 d) and b = 1/2 tr[E X^T N X] (X = C^-1 Y), a route apart from the
-    library's b = 1/2 tr[E (Z - Z Lambda Z)]."""
+def test_qml_qu_nside32_full():
+    """n = 12288, 18424 modes, unbinned EE/BB/EB over l = 2..95 (282 parameters), one map: every
+    Fisher entry, y, the noise bias and C_hat against the oracle: Z = Y^T C^-1 Y over all modes
+    (C by the harmonic route), y = 1/2 w^T E w (w = Y^T C^-1 d), b = 1/2 tr[E X^T N X] (X = C^-1 Y,
+    a route apart from the library's b = 1/2 tr[E (Z - Z Lambda Z)]) and C_hat = F^-1 (y - b)."""
     import scipy.linalg as sla
     cf = _cf()
     p = I.qu_problem_nside32()
-    bins = I.uniform_bins(2, 95, 1, ("EE", "BB", "EB"))
-    say("fisher qu nside32: GPU ...")
-    got = to_np(cf.fisher(p, bins, device=True))
+    spectra = ("EE", "BB", "EB")
+    bins = I.uniform_bins(2, 95, 1, spectra)
     nb = len(bins.lo)
-    assert got.shape == (3 * nb, 3 * nb)
-    assert np.array_equal(got, got.T)
+    say("qml qu nside32: GPU ...")
+    F_f = to_np(cf.fisher(p, bins, device=True))
+    assert F_f.shape == (3 * nb, 3 * nb)
+    assert np.array_equal(F_f, F_f.T)
     d = I.white_maps(p.n, 1, 311, rms=2.0)
     q = cf.qml(p, bins, d, device=True)
-    Fq, yq, bq = to_np(q["F"]), to_np(q["y"])[0], to_np(q["bias"])
-    assert np.array_equal(Fq, got)
-    ells = [2, 30, 95]
-    idx = [s * nb + (l - 2) for s in range(3) for l in ells]
+    F, y, b, chat = to_np(q["F"]), to_np(q["y"])[0], to_np(q["bias"]), to_np(q["chat"])[0]
+    assert np.array_equal(F, F_f)
     say("  oracle ...")
     th, ph = healpix.active_directions(p.nside, p.mask)
     Y, modes = cv.harmonic_basis(th, ph, "QU", p.lmin, p.lmax)
     C = cv.total_covariance(p, route="harmonic")
     fac = sla.cho_factor(C, lower=True)
     del C
-    sel = [j for j, (_, l, _, _) in enumerate(modes) if l in ells]
-    pos = {j: q for q, j in enumerate(sel)}
-    Ys = Y[:, sel]
+    X = sla.cho_solve(fac, Y)                                    # C^-1 Y, all modes
+    del fac
+    Z = Y.T @ X
     del Y
-    Zs = Ys.T @ sla.cho_solve(fac, Ys)
-    coo = qml.coo_derivatives(p, modes, ("EE", "BB", "EB"), ells, ells)
-    coo = [(np.array([pos[r] for r in ra]), np.array([pos[c] for c in ca]), va) for ra, ca, va in coo]
-    ref = qml.fisher_from_z(Zs, coo)
-    sub = got[np.ix_(idx, idx)]
-    m = metric_F(sub, ref)
-    say("  M_F sampled", m)
-    assert m < TOL
-    X = sla.cho_solve(fac, Ys)                                   # C^-1 Y on the sampled modes
+    coo = qml.coo_derivatives(p, modes, bins.spectra, bins.lo, bins.hi)
+    assert len(coo) == 3 * nb
+    F_ref = qml.fisher_from_z(Z, coo)
+    del Z
     w = X.T @ d[0]
     y_ref = qml.quadratic_from_w(w, coo)[0]
-    XNX = X.T @ (p.noise_diag[:, None] * X)
-    b_ref = np.array([0.5 * np.sum(v * XNX[c, r]) for r, c, v in coo])
-    my = metric_vec_fisher(yq[idx], y_ref, got[np.ix_(idx, idx)])
-    mb = metric_vec_fisher(bq[idx], b_ref, got[np.ix_(idx, idx)])
-    say("  y, bias sampled (Fisher units)", my, mb)
-    assert my < TOL and mb < TOL
+    XN = p.noise_diag[:, None] * X
+    b_ref = np.array([0.5 * np.sum(v * np.einsum("pi,pi->i", XN[:, c], X[:, r])) for r, c, v in coo])
+    chat_ref = np.linalg.solve(F_ref, y_ref - b_ref)
+    m = {"F": metric_F(F, F_ref), "y": metric_vec_fisher(y, y_ref, F_ref), "bias": metric_vec_fisher(b, b_ref, F_ref),
+         "chat": metric_chat(chat, chat_ref, F_ref)}
+    say("  metrics", m)
+    assert max(m.values()) < TOL
