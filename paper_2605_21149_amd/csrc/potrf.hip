@@ -538,6 +538,13 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
   const int64_t rows = F.rows > n ? F.rows : n;
   auto rows_for = [&](int64_t pe) { return (F.rows_early > 0 && pe <= F.p_early) ? F.rows_early : rows; };
   double* X = F.L + n * lda;                 // extra rows
+  // A batch folds its extra rows into the rows of the panel solves and the updates (they follow
+  // the matrix rows in memory) instead of solving them apart on the side stream: measured on a
+  // batch of 8 at n = 5952 with 64 maps, factorisation 16.4 -> 15.9 ms; the QU N_side 16 scan
+  // 1777 -> 1805 points/s.  A single factorisation, whose thousands of solve rows fill the bulk
+  // CUs beside a chain on reserved ones, keeps them apart.
+  const bool fold = nb > 1 && rows > n && F.rows_early == 0;
+  const int64_t nr = fold ? rows : n;        // rows of the panel solves and updates
   // One 64-column block: factor and invert the diagonal block, then X <- X L11^-T for the column
   // panel below it (in place; each tile owns its rows).
   auto block = [&](int64_t q) -> hipError_t {
@@ -546,7 +553,7 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     hipLaunchKernelGGL(nb > 1 ? k_potrf_diag_sweep : k_potrf_diag, dim3(1, 1, nb), dim3(256), 0, s, F.L, lda, F.sL, q, b, F.Li64,
                        F.sLi64, F.ldpart, F.sPart, blk, F.fail);
     CF_HIP_TRY(hipGetLastError());
-    const int64_t below = n - (q + b);
+    const int64_t below = nr - (q + b);
     if (below <= 0) return hipSuccess;
     GemmDesc g{};
     g.M = below; g.N = b; g.K = b;
@@ -565,7 +572,7 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     for (int64_t q = c0; q < c1; q += NB) {
       CF_HIP_TRY(block(q));
       const int64_t qe = q + NB;
-      if (qe < c1) CF_HIP_TRY(gemm_f64(upd(F, qe, qe, n - qe, c1 - qe, q, NB, 2), s));
+      if (qe < c1) CF_HIP_TRY(gemm_f64(upd(F, qe, qe, nr - qe, c1 - qe, q, NB, 2), s));
     }
     return hipSuccess;
   };
@@ -578,7 +585,7 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     const int64_t nbk = (c1 - c0 + NB - 1) / NB;
     const int64_t mid = c0 + ((nbk + 1) / 2) * NB;
     CF_HIP_TRY(panel_rec(c0, mid));
-    CF_HIP_TRY(gemm_f64(upd(F, mid, mid, n - mid, c1 - mid, c0, mid - c0, 2), s));
+    CF_HIP_TRY(gemm_f64(upd(F, mid, mid, nr - mid, c1 - mid, c0, mid - c0, 2), s));
     return panel_rec(mid, c1);
   };
   const bool rec = nb > 1;   // measured on batches of 8 at n = 5952: 20.0 -> 18.5 ms
@@ -608,7 +615,7 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     //      pending panels [px, pe) on to the next panel's columns, and to all later columns once
     //      they span kDefer columns.  Extra rows never feed back into C, so they trail the
     //      factorisation.
-    const int64_t rx = rows_for(pe) - n;
+    const int64_t rx = fold ? 0 : rows_for(pe) - n;
     const int64_t pn = (pe + W < n) ? pe + W : n;    // end of the next panel
     if (rx > 0) {
       CF_HIP_TRY(ewait(st.s2, st.eL));
@@ -639,25 +646,25 @@ hipError_t potrf_f64(Factor& F, double* scratch, const Streams& st) {
     if (st.eA) {
       // on the bulk CUs, after the previous trailing update (stream order) and this panel's chain
       CF_HIP_TRY(ewait(st.s1, st.eL));
-      CF_HIP_TRY(gemm_f64(upd(F, pe, pe, n - pe, pn - pe, c, pe - c, 1), st.s1));
+      CF_HIP_TRY(gemm_f64(upd(F, pe, pe, nr - pe, pn - pe, c, pe - c, 1), st.s1));
       CF_HIP_TRY(erec(st.eA, st.s1));
       CF_HIP_TRY(ewait(s, st.eA));
     } else {
       // after the previous trailing update, or with eT only after its first part: the columns of
       // this lookahead's panel (the rest of that update runs on beside the next panels' chains)
       if (pending_b) CF_HIP_TRY(ewait(s, st.eT ? st.eT : st.eB));
-      CF_HIP_TRY(gemm_f64(upd(F, pe, pe, n - pe, pn - pe, c, pe - c, 1), s));
+      CF_HIP_TRY(gemm_f64(upd(F, pe, pe, nr - pe, pn - pe, c, pe - c, 1), s));
     }
     // ---- bulk trailing update beyond the next panel (side stream, overlaps the next panel)
     if (pn < n) {
       CF_HIP_TRY(ewait(st.s1, st.eL));
       const int64_t pn2 = (pn + W < n) ? pn + W : n;    // end of the panel after next
       if (st.eT && !st.eA && pn2 < n) {
-        CF_HIP_TRY(gemm_f64(upd(F, pn, pn, n - pn, pn2 - pn, c, pe - c), st.s1));
+        CF_HIP_TRY(gemm_f64(upd(F, pn, pn, nr - pn, pn2 - pn, c, pe - c), st.s1));
         CF_HIP_TRY(erec(st.eT, st.s1));
-        CF_HIP_TRY(gemm_f64(upd(F, pn2, pn2, n - pn2, n - pn2, c, pe - c), st.s1));
+        CF_HIP_TRY(gemm_f64(upd(F, pn2, pn2, nr - pn2, n - pn2, c, pe - c), st.s1));
       } else {
-        CF_HIP_TRY(gemm_f64(upd(F, pn, pn, n - pn, n - pn, c, pe - c), st.s1));
+        CF_HIP_TRY(gemm_f64(upd(F, pn, pn, nr - pn, n - pn, c, pe - c), st.s1));
         if (st.eT && !st.eA) CF_HIP_TRY(erec(st.eT, st.s1));
       }
       CF_HIP_TRY(erec(st.eB, st.s1));
