@@ -13,6 +13,7 @@
 // FP64 MFMA lane layout (measured on gfx950): lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // output register r of lane l is D[l/16 + 4r][l%16].
 #include "cf_internal.h"
+#include "tile_map.h"
 #include <type_traits>
 
 namespace cf {
@@ -30,7 +31,7 @@ struct GemmArgs {
   int64_t diag_off;
   int64_t sA, sB, sC;
   int tiles_m, tiles_n;
-  int remap;          // 0: row-major tiles; 1: XCD chunks, grouped rows; 2: as 1, lower triangle of a square grid
+  int remap;          // 0: row-major tiles; 1: XCD chunks, grouped rows; 2: as 1, lower trapezoid
   int prio;           // wave priority: 0 default, 1 raised, 2 high
 };
 
@@ -38,61 +39,6 @@ struct GemmArgs {
 __device__ __forceinline__ void set_prio(int prio) {
   if (prio == 1) __builtin_amdgcn_s_setprio(1);
   else if (prio >= 2) __builtin_amdgcn_s_setprio(2);
-}
-
-// Tile schedule.  Workgroups go to the 8 XCDs round-robin in launch order and every XCD has its
-// own L2.  With remap, XCD x takes the contiguous range [x*per, (x+1)*per) of the (batch item,
-// tile) sequence, and the tiles of one batch item are ordered in bands of 8 tile rows swept column
-// by column, so that the tiles resident on one XCD at a time form compact blocks that share their
-// A and B panels.  remap 2 enumerates only the lower triangle (diagonal included) of a square tile
-// grid, so no workgroup is launched for a skipped tile.
-__host__ __device__ inline bool tile_map(int remap, int tiles_m, int tiles_n, int64_t nx, int64_t nz,
-                                         int64_t bx, int64_t bz, int64_t& z, int& tm, int& tn) {
-  if (!remap) {
-    tm = (int)(bx / tiles_n);
-    tn = (int)(bx % tiles_n);
-    z = bz;
-    return true;
-  }
-  const int64_t gid = bz * nx + bx;
-  const int64_t total = nx * nz;
-  const int64_t base = total / 8, rem = total % 8, x = gid % 8;   // XCD x owns base (+1 if x < rem) items
-  const int64_t tg = x * base + (x < rem ? x : rem) + gid / 8;
-  if (tg >= total) return false;
-  z = tg / nx;
-  const int64_t t = tg % nx;
-  constexpr int G = 8;
-  if (remap == 2) {
-    auto S = [](int64_t q) { const int64_t r = q * G; return r * (r + 1) / 2; };   // tiles in rows < qG
-    int64_t q = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5) / G;
-    while (q > 0 && S(q) > t) --q;
-    while (S(q + 1) <= t) ++q;
-    const int64_t r0 = q * G;
-    const int rows = (int)(tiles_m - r0 < G ? tiles_m - r0 : G);
-    int64_t u = t - S(q);
-    if (u < rows * r0) {
-      tn = (int)(u / rows);
-      tm = (int)(r0 + u % rows);
-    } else {
-      u -= rows * r0;
-      int c = 0;
-      while (u >= rows - c) {
-        u -= rows - c;
-        ++c;
-      }
-      tn = (int)(r0 + c);
-      tm = (int)(r0 + c + u);
-    }
-  } else {
-    const int64_t span = (int64_t)G * tiles_n;
-    const int64_t q = t / span;
-    const int64_t r0 = q * G;
-    const int rows = (int)(tiles_m - r0 < G ? tiles_m - r0 : G);
-    const int64_t u = t - q * span;
-    tn = (int)(u / rows);
-    tm = (int)(r0 + u % rows);
-  }
-  return true;
 }
 
 __device__ __forceinline__ bool tile_of(const GemmArgs& g, int64_t& z, int& tm, int& tn) {
@@ -523,9 +469,9 @@ hipError_t launch_tile(const GemmDesc& d, hipStream_t s) {
   int64_t nx = tm * tn;
   g.remap = 0;
   g.prio = d.prio;
-  if (d.lower && d.diag_off == 0 && tm == tn && BM == BN && d.M == d.N) {
+  if (d.lower && d.diag_off == 0 && tm >= tn && BM == BN) {
     g.remap = 2;
-    nx = tm * (tm + 1) / 2;
+    nx = tn * (tn + 1) / 2 + (tm - tn) * tn;
   } else if (!d.lower) {
     g.remap = 1;
   }
