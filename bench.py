@@ -6,12 +6,17 @@ One step = one pass of the whole path on one batch of synthetic input:
   Z = Y^T C^-1 Y, Fisher block reduction, y, noise bias, C_hat)
   + the likelihood -2 ln L of SCAN_POINTS parameter points x 64 maps (per point: covariance
     rebuild, Cholesky, log det, 64 triangular solves, chi^2).
+The two parts run one after the other; with --overlap each timed step runs them at once, the
+likelihood on a second host thread (the library gives concurrent calls separate streams and
+workspaces), and the step ends when both have (measured slower on this workload: 29.0 against
+27.7 ms per step).
 Inputs are resident in device memory before the timed region.  Prints one JSON line.
 """
 import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -28,6 +33,8 @@ def parse():
     # events, about 2 ms of extra host time with the device idle) then adds under 0.1 ms per step
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--overlap", action="store_true",
+                    help="run the step's two parts at once on two host threads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-full", action="store_true",
                     help="time the oracle sample as a median of 3 after one warmup, plus a single-thread run")
@@ -543,52 +550,101 @@ def main():
                                              direct["m2lnL"][:, 0, :].cpu().numpy(), None)}), flush=True)
         return
 
-    def step(timing):
-        q, rq = cf.qml(problem, bins, d_maps_qml, device=True, stage_timing=timing, report=True,
-                       packed=packed)
-        s, rs = cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True, report=True,
-                                 packed=[packed], autotune=True)
-        return rq, rs
+    sA, sB = torch.cuda.Stream(), torch.cuda.Stream()   # default priority, one per part
 
-    for _ in range(args.warmup):
-        step(True)
-        step(False)
+    def parts(timed, overlap):
+        """One step: Fisher + QML of one map on this thread, the likelihood batch on this thread
+        after it (overlap False) or on a second thread at the same time (overlap True).  Returns
+        the two reports and each part's wall time (host call until its stream is idle)."""
+        out, err = {}, []
+
+        def lik():
+            try:
+                with torch.cuda.stream(sB):
+                    t = time.perf_counter()
+                    # in the launch shape the autotuner chose before warmup (eager launches here)
+                    rep = cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True, report=True,
+                                           stage_timing=timed, packed=[packed], autotune=True)[1]
+                    sB.synchronize()
+                    out["l"] = (rep, time.perf_counter() - t)
+            except BaseException as e:      # re-raised on the calling thread
+                err.append(e)
+        th = threading.Thread(target=lik) if overlap else None
+        if th:
+            th.start()
+        try:
+            with torch.cuda.stream(sA):
+                t = time.perf_counter()
+                rep = cf.qml(problem, bins, d_maps_qml, device=True, stage_timing=timed, report=True,
+                             packed=packed)[1]
+                sA.synchronize()
+                out["q"] = (rep, time.perf_counter() - t)
+        finally:
+            if th:
+                th.join()
+        if not th:
+            lik()
+        if err:
+            raise err[0]
+        return out["q"], out["l"]
+
+    overlap = args.overlap
+    # the likelihood batch's launch shape is tuned first, alone on the device
+    cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True, packed=[packed], autotune=True)
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * args.steps)]
-    reps = []
+    for _ in range(args.warmup):
+        parts(True, overlap)
+        parts(False, overlap)
+    torch.cuda.synchronize()
+    reps, part_ms = [], []
     t0 = time.perf_counter()
     for k in range(args.steps):
         # The last timed step carries per-stage device timers and an event pair around every GEMM
         # launch (the kernel timings of the roofline); the events cost about 6 ms of host time per
         # step, so the other steps run without them.
         timed = k == args.steps - 1
-        ev[3 * k].record()
-        rq = cf.qml(problem, bins, d_maps_qml, device=True, stage_timing=timed, report=True,
-                    packed=packed)[1]
-        ev[3 * k + 1].record()
-        # the likelihood batch, in the launch shape the autotuner chose during warmup (eager
-        # launches at this size)
-        rs = cf.loglike_batch([problem], d_cl, [d_maps_scan], device=True, report=True, stage_timing=timed,
-                              packed=[packed], autotune=True)[1]
-        ev[3 * k + 2].record()
+        (rq, tq), (rs, ts) = parts(timed, overlap)
+        part_ms.append((1e3 * tq, 1e3 * ts))
         if timed:
             reps.append((rq, rs))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     step_tuned = _tuned_line(os.environ["CF_TUNE_CACHE"], n)     # the step's launch shape
-    # medians over the uninstrumented steps (all of them when only one step is timed)
-    plain = range(args.steps - 1) if args.steps > 1 else range(args.steps)
-    qml_ms = [ev[3 * k].elapsed_time(ev[3 * k + 1]) for k in plain]
-    scan_ms = [ev[3 * k + 1].elapsed_time(ev[3 * k + 2]) for k in plain]
+    # each part alone: medians over steps run in sequence after the timed region (for the
+    # overlapped step these are the parts' own times, which overlap inside the timed steps), and
+    # one instrumented sequential step for the stage times and the whole factorisations' rates
+    if overlap:
+        seq_ms = [parts(False, False) for _ in range(max(3, min(args.steps, 10)))]
+        qml_ms = [1e3 * q[1] for q, _ in seq_ms]
+        scan_ms = [1e3 * l[1] for _, l in seq_ms]
+        (sq, _), (sl, _) = parts(True, False)
+        seq_rep = (sq, sl)
+    else:
+        plain = range(args.steps - 1) if args.steps > 1 else range(args.steps)
+        qml_ms = [part_ms[k][0] for k in plain]
+        scan_ms = [part_ms[k][1] for k in plain]
+        seq_rep = reps[-1]
     ms_step = 1000.0 * wall / args.steps
-    stage = np.mean([r[0]["ms_stage"] for r in reps], axis=0)
-    scan_stage = np.mean([r[1]["ms_stage"] for r in reps], axis=0)
-    # GEMM instances over the instrumented step (both calls): event time, algorithmic flops, launches
-    g_ms = np.sum([np.add(r[0]["gemm_ms"], r[1]["gemm_ms"]) for r in reps], axis=0)
-    g_fl = np.sum([np.add(r[0]["gemm_flops"], r[1]["gemm_flops"]) for r in reps], axis=0)
-    g_n = np.sum([np.add(r[0]["gemm_launches"], r[1]["gemm_launches"]) for r in reps], axis=0)
-    g_by = np.sum([np.add(r[0]["gemm_bytes"], r[1]["gemm_bytes"]) for r in reps], axis=0)
-    nrep = len(reps)
+    stage = np.asarray(seq_rep[0]["ms_stage"])
+    scan_stage = np.asarray(seq_rep[1]["ms_stage"])
+
+    def instances(rr):
+        """GEMM instances over instrumented steps (both calls): event time, algorithmic flops,
+        launches, sorted by device time."""
+        g_ms = np.sum([np.add(r[0]["gemm_ms"], r[1]["gemm_ms"]) for r in rr], axis=0)
+        g_fl = np.sum([np.add(r[0]["gemm_flops"], r[1]["gemm_flops"]) for r in rr], axis=0)
+        g_n = np.sum([np.add(r[0]["gemm_launches"], r[1]["gemm_launches"]) for r in rr], axis=0)
+        g_by = np.sum([np.add(r[0]["gemm_bytes"], r[1]["gemm_bytes"]) for r in rr], axis=0)
+        res = []
+        for i in range(len(g_ms)):
+            if g_n[i] > 0:
+                res.append({"kernel": cf.gemm_instance_name(i), "launches_per_step": float(g_n[i]) / len(rr),
+                            "ms_per_step": float(g_ms[i]) / len(rr), "avg_launch_us": float(g_ms[i] / g_n[i]) * 1e3,
+                            "tflops": float(g_fl[i] / (g_ms[i] * 1e-3) / 1e12) if g_ms[i] > 0 else None,
+                            "flops_per_launch": float(g_fl[i] / g_n[i]),
+                            "algorithmic_bytes_per_launch": float(g_by[i] / g_n[i])})
+        res.sort(key=lambda r: -r["ms_per_step"])
+        return res
     mixed = None if args.no_mixed else mixed_precision(cf, I, problem, bins, packed, d_maps_qml, d_cl,
                                                           d_maps_scan)
     extras = None if args.no_extras else qml_extras(cf, I, problem, bins, packed, d_maps_qml)
@@ -603,20 +659,16 @@ def main():
                                      autotune=True)["m2lnL"][:, 0, :].cpu().numpy()
         smw = smw_section(cf, I, problem, packed, d_maps_scan, direct_m2,
                           SCAN_POINTS / (np.median(scan_ms) * 1e-3))
-    # Roofline kernel: the GEMM instance with the most device time in the instrumented step (the
-    # Cholesky updates C -= L L^T of the two factorisation stages), achieved = its algorithmic flops
+    # Roofline kernel: the GEMM instance with the most device time in the instrumented timed step
+    # (the Cholesky updates C -= L L^T of the two factorisations), achieved = its algorithmic flops
     # in that step / its summed HIP-event durations on the streams it ran on.  Every instance is
-    # also listed (gemm_instances), with the whole factorisations' rates (factorisation).
-    inst = []
-    for i in range(len(g_ms)):
-        if g_n[i] > 0:
-            inst.append({"kernel": cf.gemm_instance_name(i), "launches_per_step": float(g_n[i]) / nrep,
-                         "ms_per_step": float(g_ms[i]) / nrep, "avg_launch_us": float(g_ms[i] / g_n[i]) * 1e3,
-                         "tflops": float(g_fl[i] / (g_ms[i] * 1e-3) / 1e12) if g_ms[i] > 0 else None,
-                         "flops_per_launch": float(g_fl[i] / g_n[i]),
-                         "algorithmic_bytes_per_launch": float(g_by[i] / g_n[i])})
-    inst.sort(key=lambda r: -r["ms_per_step"])
+    # also listed (gemm_instances), with the whole factorisations' rates (factorisation).  With
+    # the parts overlapped, each launch shares the device with the other part's kernels;
+    # roofline_sequential gives the same instance in the instrumented sequential step.
+    inst = instances(reps)
     top = inst[0]
+    inst_seq = instances([seq_rep]) if overlap else inst
+    top_seq = [r for r in inst_seq if r["kernel"] == top["kernel"]][0]
     traffic = _traffic(top["kernel"])
     # whole factorisations against the same peak, algorithmic flops only: n^3/3 for the Cholesky and
     # m^2 per right-hand side solved over m rows (the E,B columns of Y vanish above the first Q
@@ -644,6 +696,7 @@ def main():
                                 f"{NMAPS_SCAN} maps"),
                    "precision": "fp64", "n": n, "nmodes": 6900, "scan_points_per_step": SCAN_POINTS,
                    "maps_per_point": NMAPS_SCAN,
+                   "parts": "overlapped" if overlap else "sequential",
                    "autotuned": step_tuned},
         "fisher_qml_ms": float(np.median(qml_ms)),
         "loglike_ms": float(np.median(scan_ms)),
@@ -660,6 +713,11 @@ def main():
         "tqu_scan": scan_tqu,
         "other_fishers": fishers,
         "factorisation": factorisation,
+        "roofline_sequential": {"kernel": top_seq["kernel"], "avg_launch_us": top_seq["avg_launch_us"],
+                                "achieved": top_seq["tflops"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                "frac": top_seq["tflops"] / PEAK_FP64_TFLOPS,
+                                "launches_per_step": top_seq["launches_per_step"],
+                                "flops_per_launch": top_seq["flops_per_launch"]},
         "roofline": {"bound": "mfma", "kernel": top["kernel"] + " FP64 " + GEMM_ROLE.get(top["kernel"][-2], ""),
                      "avg_launch_us": top["avg_launch_us"],
                      "achieved": top["tflops"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",

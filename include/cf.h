@@ -4,8 +4,13 @@
  * "CosmoForge I" (Galloni & Pagano), Sects. 2.1-2.6 and Apps. A-C.
  *
  * Every entry point runs its whole computation in HIP kernels on the current
- * HIP device and returns only when the results are written.  Calls that use
- * the same device are serialised by the library (one workspace per device).
+ * HIP device and returns only when the results are written.  Two calls on one
+ * device from different host threads run at the same time, each on a call
+ * lane of its own (streams, events, workspace); a third waits for the first
+ * lane.  Once two calls have overlapped on a device, single factorisations
+ * there stop reserving CUs for their chain of diagonal blocks.  The entry
+ * points that allocate nothing share one scratch array per device and are
+ * serialised among themselves.
  *
  * Conventions shared by all entry points
  * --------------------------------------
@@ -81,7 +86,9 @@ typedef struct {
 
 /* Optional execution controls (NULL = defaults). */
 typedef struct {
-  void* stream;           /* hipStream_t to run on; NULL = the library's stream */
+  void* stream;           /* hipStream_t the call is ordered on (NULL: none): the call starts
+                             after the work queued on it and the work queued on it after the call
+                             waits for the call; the kernels run on the library's own streams */
   int32_t stage_timing;   /* 1: record per-stage device time in the report      */
   int32_t refine_max;     /* mixed precision: max refinement steps (-1 default)  */
   int32_t allow_fallback; /* mixed precision: fall back to FP64 instead of ENOCONV */

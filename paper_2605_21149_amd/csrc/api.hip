@@ -3,6 +3,7 @@
 #include "cf_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstdarg>
 #include <cmath>
@@ -60,6 +61,10 @@ constexpr int kGraphMaxN = 512;
 constexpr int64_t kLdProbes = 384;
 // Largest number of scan points factorised together (memory permitting: 6 GB of covariances).
 constexpr int kScanBatchMax = 128;
+// Call lanes per device: each lane is a complete set of streams, events, workspace and pinned
+// flags, held by one call at a time.  A call takes the first free lane, so that two host threads
+// can run two calls on one device at once; with every lane busy it waits for lane 0.
+constexpr int kLanes = 2;
 struct Device {
   std::mutex mu;
   hipStream_t stream = nullptr;
@@ -70,12 +75,21 @@ struct Device {
   hipStream_t crit = nullptr, bulk = nullptr, bulk2 = nullptr;   // bulk2: same CUs as bulk
   hipEvent_t ev[kEvents] = {};               // ordering events between the streams
   hipEvent_t ring[4] = {};                   // pacing events of the factorisation loop
+  hipEvent_t jin = nullptr, jout = nullptr;   // a call joined after and back into the caller's stream
   char* ws = nullptr;
   size_t cap = 0;
   int* hflags = nullptr;   // pinned host mirror of the device flags
   char arch[64] = {0};     // the device's architecture name (gcnArchName up to its first ':')
+  int id = -1;             // the device this lane belongs to
 };
-Device g_dev[64];
+Device g_dev[64 * kLanes];
+// Set for a device once two calls have overlapped on it (a call found lane 0 busy).  From then on
+// single factorisations run on the plain streams too: the CU-masked streams reserve 32 CUs for the
+// chain of diagonal blocks, which pays for a call alone on the device (a Fisher + QML of n = 5952:
+// 11.8 ms masked, 12.7 ms plain) but less beside another call, whose kernels the reservation
+// confines (that Fisher + QML beside an 8-point likelihood batch: 29.0 ms for the pair on plain
+// streams, 29.6-30.0 ms with the masked ones; 27.7 ms for the two in sequence).
+std::atomic<bool> g_overlap[64];
 
 struct Bump {  // carves 256-byte aligned sub-buffers out of the workspace
   char* base;
@@ -435,7 +449,8 @@ int potrf_on(Device& d, Factor& F, double* scratch, hipStream_t s, hipStream_t s
   // scan with CU-masked streams taking part crashed the runtime).
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   CF_DEV(hipStreamIsCapturing(s, &cap));
-  if (!d.crit || F.batch > 1 || cap != hipStreamCaptureStatusNone) {
+  if (!d.crit || F.batch > 1 || cap != hipStreamCaptureStatusNone ||
+      (d.id >= 0 && g_overlap[d.id].load(std::memory_order_relaxed))) {
     Streams st{s, d.aux[0], side, ev[0], ev[1], ev[2], d.ring};
     st.eT = ev[6];   // lookahead of depth two
     CF_DEV(potrf_f64(F, scratch, st));
@@ -465,8 +480,13 @@ char* g_scratch[64] = {};
 struct CallCtx {
   Device* dev = nullptr;
   hipStream_t s = nullptr;
+  hipStream_t caller = nullptr;   // the caller's stream, joined into s at the start and back at the end
   int id = 0;
   std::unique_lock<std::mutex> lock;
+  ~CallCtx() {
+    if (caller && dev && s && dev->jout && hipEventRecord(dev->jout, s) == hipSuccess)
+      (void)hipStreamWaitEvent(caller, dev->jout, 0);
+  }
   // For the entry points that allocate nothing: the caller's stream (or the null stream), no
   // library streams, events or pinned buffers; the scratch array's address is looked up on the
   // first such call on the device.
@@ -474,7 +494,7 @@ struct CallCtx {
     CF_DEV(hipGetDevice(&id));
     if (id < 0 || id >= 64) return fail(CF_EDEVICE, "device id %d unsupported", id);
     std::call_once(g_atexit_once, [] { std::atexit(release_device_state); });
-    dev = &g_dev[id];
+    dev = &g_dev[id * kLanes];          // the scratch array is the device's: one such call at a time
     lock = std::unique_lock<std::mutex>(dev->mu);
     if (!g_scratch[id]) {
       void* p = nullptr;
@@ -493,13 +513,27 @@ struct CallCtx {
     // graphs, streams (CU-masked ones included), events and memory go back while the runtime and
     // any profiler attached to it are still whole.
     std::call_once(g_atexit_once, [] { std::atexit(release_device_state); });
-    dev = &g_dev[id];
-    lock = std::unique_lock<std::mutex>(dev->mu);
+    dev = nullptr;
+    for (int l = 0; l < kLanes && !dev; ++l) {
+      std::unique_lock<std::mutex> t(g_dev[id * kLanes + l].mu, std::try_to_lock);
+      if (t.owns_lock()) {
+        dev = &g_dev[id * kLanes + l];
+        lock = std::move(t);
+      }
+    }
+    if (!dev) {
+      dev = &g_dev[id * kLanes];
+      lock = std::unique_lock<std::mutex>(dev->mu);
+    }
+    if (dev != &g_dev[id * kLanes]) g_overlap[id].store(true, std::memory_order_relaxed);
     if (!dev->stream) {
+      dev->id = id;
       CF_DEV(hipStreamCreateWithFlags(&dev->stream, hipStreamNonBlocking));
       for (auto& a : dev->aux) CF_DEV(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
       for (auto& e : dev->ev) CF_DEV(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       for (auto& e : dev->ring) CF_DEV(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      CF_DEV(hipEventCreateWithFlags(&dev->jin, hipEventDisableTiming));
+      CF_DEV(hipEventCreateWithFlags(&dev->jout, hipEventDisableTiming));
       make_cholesky_streams(*dev, id);
       hipDeviceProp_t prop;
       if (hipGetDeviceProperties(&prop, id) == hipSuccess) {
@@ -513,7 +547,19 @@ struct CallCtx {
       if (!dev->arch[0]) std::snprintf(dev->arch, sizeof dev->arch, "unknown");
     }
     if (!dev->hflags) CF_DEV(hipHostMalloc((void**)&dev->hflags, 64 * sizeof(int), hipHostMallocDefault));
-    s = (ex && ex->stream) ? (hipStream_t)ex->stream : dev->stream;
+    // The kernels run on the lane's own streams, ordered after the caller's stream and joined back
+    // into it when the call returns.  Computing on the caller's stream instead made the call's
+    // speed depend on which hardware queue the runtime had mapped that stream to: sharing one
+    // with the lane's side streams serialises the factorisation's chain with its own trailing
+    // updates (an 8-point likelihood batch at n = 5952: 15.3 ms on the lane's stream, 16.3 ms on
+    // a stream of the caller's; a Fisher + QML without the CU-masked streams 12.7 vs 16.0 ms).
+    s = dev->stream;
+    hipStream_t cs = (ex && ex->stream) ? (hipStream_t)ex->stream : nullptr;
+    if (cs && cs != s) {
+      CF_DEV(hipEventRecord(dev->jin, cs));
+      CF_DEV(hipStreamWaitEvent(s, dev->jin, 0));
+      caller = cs;
+    }
     return CF_OK;
   }
 };
@@ -1161,22 +1207,23 @@ struct ScanGraph {
   hipGraphExec_t exec = nullptr;
 };
 std::mutex g_graph_mu;
-std::vector<ScanGraph> g_graphs[64];
+std::vector<ScanGraph> g_graphs[64 * kLanes];   // per lane: the graphs write the lane's workspace
 
 void release_device_state() {
   int cur = -1;
   (void)hipGetDevice(&cur);
-  for (int id = 0; id < 64; ++id) {
-    Device& d = g_dev[id];
+  for (int li = 0; li < 64 * kLanes; ++li) {
+    const int id = li / kLanes;
+    Device& d = g_dev[li];
     // a call still running on another thread at exit keeps its device's state (no deadlock)
     std::unique_lock<std::mutex> dl(d.mu, std::try_to_lock);
     if (!dl.owns_lock()) continue;
     {
       std::unique_lock<std::mutex> g(g_graph_mu, std::try_to_lock);
       if (!g.owns_lock()) continue;
-      if (!g_graphs[id].empty() || d.stream) (void)hipSetDevice(id);
-      for (auto& e : g_graphs[id]) (void)hipGraphExecDestroy(e.exec);
-      g_graphs[id].clear();
+      if (!g_graphs[li].empty() || d.stream) (void)hipSetDevice(id);
+      for (auto& e : g_graphs[li]) (void)hipGraphExecDestroy(e.exec);
+      g_graphs[li].clear();
     }
     if (!d.stream && !d.ws && !d.hflags) continue;
     (void)hipSetDevice(id);
@@ -1185,6 +1232,7 @@ void release_device_state() {
       if (*st) { (void)hipStreamDestroy(*st); *st = nullptr; }
     for (auto& e : d.ev) if (e) { (void)hipEventDestroy(e); e = nullptr; }
     for (auto& e : d.ring) if (e) { (void)hipEventDestroy(e); e = nullptr; }
+    for (hipEvent_t* e : {&d.jin, &d.jout}) if (*e) { (void)hipEventDestroy(*e); *e = nullptr; }
     if (d.ws) { (void)hipFree(d.ws); d.ws = nullptr; d.cap = 0; }
     if (d.hflags) { (void)hipHostFree(d.hflags); d.hflags = nullptr; }
   }
@@ -1204,6 +1252,7 @@ struct TuneEntry {
 };
 std::vector<TuneEntry> g_tune;
 std::string g_tune_loaded;            // path the table was read from
+std::mutex g_tune_mu;                 // calls on several lanes or devices share the table
 
 std::string tune_path() {
   const char* p = getenv("CF_TUNE_CACHE");
@@ -1235,14 +1284,20 @@ void tune_load() {
   }
   fclose(f);
 }
-const TuneEntry* tune_get(const char* arch, int64_t n, int nmaps, int mode) {
+bool tune_get(const char* arch, int64_t n, int nmaps, int mode, TuneEntry& out) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
   tune_load();
   // the latest entry of the shape: a call that could try larger batches tunes again and appends
   for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
-    if (it->arch == arch && it->n == n && it->nmaps == nmaps && it->mode == mode) return &*it;
-  return nullptr;
+    if (it->arch == arch && it->n == n && it->nmaps == nmaps && it->mode == mode) {
+      out = *it;
+      return true;
+    }
+  return false;
 }
 void tune_put(const TuneEntry& e) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_load();
   g_tune.push_back(e);
   FILE* f = fopen(tune_path().c_str(), "a");
   if (!f) return;
@@ -1388,8 +1443,7 @@ std::string graph_key(const ScanCtx& x, int b, const char* ws) {
 // Runs points [i0, i0 + nb*b) of problem x.p as nb replays of the captured batch.
 int scan_replay(ScanCtx& x, int64_t i0, int b, int64_t nb, int64_t* i0p) {
   CallCtx& c = *x.c;
-  int dev = 0;
-  CF_DEV(hipGetDevice(&dev));
+  const int dev = (int)(c.dev - g_dev);          // the call's lane
   const std::string key = graph_key(x, b, c.dev->ws);
   hipGraphExec_t exec = nullptr;
   {
@@ -1481,8 +1535,7 @@ int loglike_core(const cf_problem* probs, int32_t nprob, int32_t npoints, const 
   std::vector<char> tuned(nprob, 0);
   if (!noalloc)
     for (int p = 0; p < nprob; ++p)
-      if (const TuneEntry* tp = tune_get(c.dev->arch, H[p].n, nmaps, mode)) {
-        te[p] = *tp;                     // copied: tune_put may grow the table
+      if (tune_get(c.dev->arch, H[p].n, nmaps, mode, te[p])) {
         // tuned by a call with fewer points than this one can batch: tune again if asked to
         tuned[p] = !(ex && ex->autotune && cap[p] > te[p].maxb);
       }
