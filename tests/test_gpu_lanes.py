@@ -84,8 +84,8 @@ def test_fisher_qml_beside_a_likelihood_batch():
         m2, _, ld = likelihood.minus2lnL(pl, maps_l, cl=clp[i, 0])
         assert np.max(np.abs(l0["m2lnL"][i, 0] - m2) / np.abs(m2)) < TOL
         assert abs(l0["logdet"][i, 0] - ld) <= TOL * abs(ld)
-    for rnd in range(3):
-        say(f"lanes: overlapped calls, round {rnd}")
+    for rep in range(3):
+        say(f"lanes: overlapped calls, repetition {rep}")
         q, l = at_once()
         for k in q0:
             assert np.array_equal(q[k], q0[k]), k
