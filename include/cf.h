@@ -186,7 +186,8 @@ int cf_loglike_batch(const cf_problem* probs, int32_t nprob, int32_t npoints,
  * (at most 128) whose workspace fits the array.  CF_EINVAL when even one point does not fit (for
  * FP64 with 64 maps, up to about n = 2600; host-memory problems also stage their inputs in it).
  * Calls on one GPU share the array, which keeps the last call's contents; the library serialises
- * calls per device and each returns after its work is done, so calls never overlap on it. */
+ * these calls per device (other entry points run beside them on call lanes of their own, never on
+ * the array) and each returns after its work is done, so calls never overlap on it. */
 int cf_loglike_batch_noalloc(const cf_problem* probs, int32_t nprob, int32_t npoints,
                              const double* cl_points, int32_t lstride, const double* const* maps,
                              int32_t nmaps, int32_t precision, double* m2lnL, double* chi2,

@@ -792,7 +792,7 @@ int fisher_core_fp64(const cf_problem* prob, const HostProblem& H, const Staged&
 }
 
 // Covariance, factor, Y, G = L^-1 Y, Z = G^T G (+ u = L^-1 d, w = G^T u), Gram of Z blocks.
-// Three streams: the caller's stream s carries the covariance, the factorisation and the T part;
+// Three streams: the call's stream s carries the covariance, the factorisation and the T part;
 // aux[0] builds Y (concurrently with the factorisation) and then carries the E,B part; aux[1]
 // solves the maps.  Events order the hand-offs; everything is joined back into s.
 int fisher_core(const cf_problem* prob, const HostProblem& H, const Staged& S, FisherBufs& f,
