@@ -59,8 +59,12 @@ constexpr int kGraphMaxN = 512;
 // N_side 16 scan problem (|X|_F about 2.8e-3), against biases of ln|C| of the FP32 factor of up to
 // 1e-3 there and 2e-3 at n = 5952; 384 probes keep a deviation of 1e-3 beyond five of them.
 constexpr int64_t kLdProbes = 384;
-// Largest number of scan points factorised together (memory permitting: 6 GB of covariances).
+// Largest number of scan points factorised together, memory permitting: their covariances take at
+// most kScanBytes, or an eighth of the device's memory if that is less.  Measured (64 maps,
+// autotuned): 6 GB allowed batches of 22 at n = 5952 and 48 at n = 3968, and 24 GB batches of 64
+// and 128, the scans' rates 613 -> 667 and 1890 -> 2080 points/s.
 constexpr int kScanBatchMax = 128;
+constexpr size_t kScanBytes = size_t(24) << 30;
 // Call lanes per device: each lane is a complete set of streams, events, workspace and pinned
 // flags, held by one call at a time.  A call takes the first free lane, so that two host threads
 // can run two calls on one device at once; with every lane busy it waits for lane 0.
@@ -80,6 +84,7 @@ struct Device {
   size_t cap = 0;
   int* hflags = nullptr;   // pinned host mirror of the device flags
   char arch[64] = {0};     // the device's architecture name (gcnArchName up to its first ':')
+  size_t mem = 0;          // the device's memory in bytes
   int id = -1;             // the device this lane belongs to
 };
 Device g_dev[64 * kLanes];
@@ -537,6 +542,7 @@ struct CallCtx {
       make_cholesky_streams(*dev, id);
       hipDeviceProp_t prop;
       if (hipGetDeviceProperties(&prop, id) == hipSuccess) {
+        dev->mem = prop.totalGlobalMem;
         size_t k = 0;
         while (k + 1 < sizeof dev->arch && prop.gcnArchName[k] && prop.gcnArchName[k] != ':') {
           dev->arch[k] = prop.gcnArchName[k];
@@ -1523,12 +1529,14 @@ int loglike_core(const cf_problem* probs, int32_t nprob, int32_t npoints, const 
   int nmax = 0;
   for (int p = 0; p < nprob; ++p) nmax = H[p].n > nmax ? H[p].n : nmax;
   // Points factorised together, per problem: the autotuned batch of the problem's shape if known,
-  // else the largest of at most 128 whose covariances fit in 6 GB.  The workspace holds, for every
-  // buffer, the largest of the problems' batches of it.
+  // else the largest of at most 128 whose covariances fit the budget (kScanBytes, or an eighth of
+  // the device's memory if less).  The workspace holds, for every buffer, the largest of the
+  // problems' batches of it.
+  const size_t budget = (c.dev->mem > 0 && c.dev->mem / 8 < kScanBytes) ? c.dev->mem / 8 : kScanBytes;
   std::vector<int> cap(nprob);
   for (int p = 0; p < nprob; ++p) {
     const size_t per = (size_t)H[p].n * H[p].n * 8 * (mode ? 2 : 1);
-    cap[p] = (int)std::min<size_t>(kScanBatchMax, std::max<size_t>(1, (size_t(6) << 30) / per));
+    cap[p] = (int)std::min<size_t>(kScanBatchMax, std::max<size_t>(1, budget / per));
     cap[p] = (int)std::min<int64_t>(cap[p], npoints);
   }
   std::vector<TuneEntry> te(nprob);
