@@ -117,9 +117,10 @@ def emulator_bench(cf, I, n_train, epochs, n_query, spread_max=0.1, seed_map=403
     def spectra(x):
         return torch.as_tensor(np.ascontiguousarray(base[None] + np.einsum("nk,kxl->nxl", x, basis))).to(dev)
 
-    # pixel-space scan, short sample (the batch shape tunes on the first call)
+    # pixel-space scan, short sample (the batch shape tunes on a first, untimed call of the same
+    # size: a call that could batch more points than the tuning trials would tune again)
     xd = I.scan_points(512, seed=500)
-    cf.loglike_batch([p], spectra(xd[:64])[:, None], [d_map[None]], device=True, packed=[packed], autotune=True)
+    cf.loglike_batch([p], spectra(xd)[:, None], [d_map[None]], device=True, packed=[packed], autotune=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     cf.loglike_batch([p], spectra(xd)[:, None], [d_map[None]], device=True, packed=[packed], autotune=True)
