@@ -1729,6 +1729,9 @@ int loglike_core(const cf_problem* probs, int32_t nprob, int32_t npoints, const 
       // among more points (n = 1088: 14k points/s at 16 per batch)
       for (int cand : {2, 4, 8, 16, 32, 64, 128})
         if (int st = trial(cand, 0, 0, graph)) return st;
+      // and the largest batch the call allows when it is not one of those (memory or points)
+      if (cap[p] > 2 && (cap[p] & (cap[p] - 1)) != 0)
+        if (int st = trial(cap[p], 0, 0, graph)) return st;
       const int bt = best.bt;
       for (int panel : {0, 256, 512}) {       // panel width and tile jointly (they interact)
         if (panel && h.n <= 512) continue;
