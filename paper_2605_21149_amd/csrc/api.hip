@@ -52,7 +52,7 @@ constexpr int kEvents = 16;
 // (n <= 512): processes that captured and replayed batches of larger problems (n = 1088 and
 // n = 3968 with 64 maps, factorised over several panels on three streams) ended with host
 // segmentation faults whose cause is not established, so larger problems launch eagerly,
-// host-paced two panels ahead (measured faster for n = 5952 batches of 8 than the replay).
+// host-paced one outer panel ahead (measured faster for n = 5952 batches of 8 than the replay).
 constexpr int kGraphMaxN = 512;
 // Probes of the mixed path's stochastic log-det correction: the estimate's standard deviation is
 // about sqrt(2 / kLdProbes) |X|_F.  Measured with FP32 updates: 2.5e-4 at 256 probes on the QU
